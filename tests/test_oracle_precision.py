@@ -1,0 +1,99 @@
+"""Pins of the oracle's reduced-precision preconditioner forms (FP32 and
+diagonally scaled FP16 storage with FP32 arithmetic).
+
+The paper fixes only that the preconditioner runs in single precision while
+the Krylov solver stays in double (Section 9).  The forms are defined in
+symmetrically scaled variables (exact-arithmetic invariant); these tests pin
+(1) the binary16 rounding against numpy's IEEE conversion, (2) exactness on
+dyadic data where no rounding can occur, so the reduced forms must equal the
+float64 textbook form bit for bit, and (3) error bounds against float64.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gen import poisson2d, laplace3d, random_sparse, vardiff3d, CSR
+
+F, B, S = oracle.FORWARD, oracle.BACKWARD, oracle.SYMMETRIC
+
+
+def test_round_f16_all_bit_patterns():
+    h = np.arange(65536, dtype=np.uint32).astype(np.uint16).view(np.float16)
+    d = h.astype(np.float64)
+    out = np.array([oracle.round_f16(x) for x in d])
+    fin = np.isfinite(d)
+    assert np.array_equal(out[fin], d[fin])
+    assert np.all(np.isinf(out[np.isinf(d)]) & (np.sign(out[np.isinf(d)]) == np.sign(d[np.isinf(d)])))
+    assert np.all(np.isnan(out[np.isnan(d)]))
+
+
+def test_round_f16_random_and_ties():
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([
+        rng.standard_normal(20000) * 10.0 ** rng.uniform(-9, 5, 20000),
+        rng.uniform(65000, 66000, 2000) * rng.choice([-1, 1], 2000),
+    ])
+    # exact midpoints between consecutive finite halfs (ties -> even)
+    h = np.arange(0, 0x7BFF, dtype=np.uint16).view(np.float16).astype(np.float64)
+    mids = (h[:-1] + h[1:]) / 2
+    xs = np.concatenate([xs, mids, -mids, [65519.99, 65520.0, 65504.0, 2.0 ** -25, 2.0 ** -26, 3 * 2.0 ** -26]])
+    with np.errstate(over="ignore"):
+        ref = xs.astype(np.float16).astype(np.float64)
+    out = np.array([oracle.round_f16(x) for x in xs])
+    assert np.array_equal(out, ref)
+
+
+def dyadic_problem(N):
+    A = poisson2d(N)  # d = 4: scale 1/2, scaled off-diagonals -1/4, all exact
+    v = np.random.default_rng(1).integers(-8, 9, A.n).astype(np.float64)
+    return A, v
+
+
+@pytest.mark.parametrize("prec", [oracle.FP32, oracle.FP16S])
+@pytest.mark.parametrize("variant,sweeps,inner", [(F, 1, 1), (F, 2, 3), (B, 1, 2), (S, 2, 1), (F, 3, 0)])
+def test_reduced_forms_exact_on_dyadic_data(prec, variant, sweeps, inner):
+    """Every scaled value, product and partial sum is a short dyadic rational,
+    exactly representable in binary32, so the reduced form must reproduce the
+    float64 textbook (unscaled) result exactly."""
+    A, v = dyadic_problem(6)
+    z64 = oracle.gs2_apply(A, v, variant, sweeps, inner, 1.0)
+    zlp = oracle.gs2_apply_lp(A, v, prec, variant, sweeps, inner, 1.0)
+    assert np.array_equal(z64, zlp)
+
+
+@pytest.mark.parametrize("mk", [lambda: random_sparse(200, seed=7, avg_offdiag=6, neg_diag_rows=10),
+                                lambda: vardiff3d(6, seed=3), lambda: laplace3d(6)])
+@pytest.mark.parametrize("variant,sweeps,inner", [(F, 2, 1), (S, 1, 2)])
+def test_reduced_forms_error_bounds(mk, variant, sweeps, inner):
+    """Relative 2-norm error against float64: a few hundred unit roundoffs of
+    the storage format (each stored value and each partial sum carries one)."""
+    A = mk()
+    v = np.random.default_rng(2).standard_normal(A.n)
+    z64 = oracle.gs2_apply(A, v, variant, sweeps, inner, 0.9)
+    e32 = np.linalg.norm(oracle.gs2_apply_lp(A, v, oracle.FP32, variant, sweeps, inner, 0.9) - z64) / np.linalg.norm(z64)
+    e16 = np.linalg.norm(oracle.gs2_apply_lp(A, v, oracle.FP16S, variant, sweeps, inner, 0.9) - z64) / np.linalg.norm(z64)
+    assert e32 < 300 * 2.0 ** -24
+    assert 2.0 ** -24 * 0.01 < e16 < 300 * 2.0 ** -11
+    assert e32 < e16
+
+
+def test_fp16_range_error():
+    """Scaled entries beyond binary16 range are rejected (not silently inf)."""
+    A = CSR(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([1e-6, 1.0, 1.0, 1e-6]))
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.gs2_apply_lp(A, np.ones(2), oracle.FP16S)
+    assert e.value.status == oracle.ERR_FP16_RANGE
+
+
+def test_gmres_reduced_precision_reaches_tolerance():
+    """The FP64 outer Krylov loop recovers full accuracy with an FP32 / FP16
+    preconditioner, with about the same iteration count (Section 9)."""
+    A = vardiff3d(10, seed=9)
+    b = np.random.default_rng(3).standard_normal(A.n)
+    its = {}
+    for p in (oracle.FP64, oracle.FP32, oracle.FP16S):
+        x, info = oracle.gmres(A, b, restart=50, rtol=1e-8, prec="gs2", variant=S, sweeps=1, inner=1, precision=p)
+        assert info["converged"] and info["relres"] <= 1e-8
+        its[p] = info["iterations"]
+    assert abs(its[oracle.FP32] - its[oracle.FP64]) <= 1
+    assert abs(its[oracle.FP16S] - its[oracle.FP64]) <= max(2, its[oracle.FP64] // 10)
