@@ -1,0 +1,228 @@
+/*
+ * gs2.h - C ABI of the MI355X (gfx950) two-stage Gauss-Seidel library.
+ *
+ * Two-stage Gauss-Seidel (GS2) replaces the sparse triangular solve of
+ * Gauss-Seidel with a fixed number of inner Jacobi-Richardson sweeps
+ * (Thomas et al., arXiv 2104.01196, Section 4, eqs. (two-stage),
+ * (jr-initial-guess), (jacobi)).  This library applies GS2 in forward,
+ * backward and symmetric form as the preconditioner of a restarted FP64
+ * GMRES, next to plain Jacobi-Richardson and an exact level-scheduled
+ * Gauss-Seidel as comparison paths, with FP32 / scaled-FP16 preconditioner
+ * storage and a batched solver for many independent systems.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named as device pointers must point to device memory of the
+ *    current HIP device; `stream` is a hipStream_t (NULL = default stream).
+ *  - Matrices are CSR, 0-based, square, column indices strictly increasing
+ *    within a row, diagonal entry present, float64 values.  The natural
+ *    ordering is respected and never permuted (the result of Gauss-Seidel
+ *    depends on it, Section 6).
+ *  - Return value: 0 on success, a negative GS2_ERR_* code on a hard error
+ *    (nothing was enqueued, outputs are untouched unless stated), a positive
+ *    code for a soft outcome of a solve.  No C++ exception crosses the ABI.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef GS2_H
+#define GS2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define GS2_OK 0
+#define GS2_ERR_ARG (-1)        /* invalid argument (NULL, size, enum)      */
+#define GS2_ERR_BAD_CSR (-2)    /* unsorted/duplicate/out-of-range columns  */
+#define GS2_ERR_ZERO_DIAG (-3)  /* diagonal entry missing or zero           */
+#define GS2_ERR_NONFINITE (-4)  /* NaN/Inf in the matrix, b, or the iterate */
+#define GS2_ERR_NOMEM (-5)      /* device allocation failed                 */
+#define GS2_ERR_HIP (-6)        /* a HIP runtime call failed                */
+#define GS2_ERR_FP16_RANGE (-7) /* scaled value outside binary16 range      */
+#define GS2_ERR_NO_LEVELS (-8)  /* trisolve on a handle built without levels */
+#define GS2_NOT_CONVERGED 1     /* maxit Arnoldi steps without reaching rtol */
+#define GS2_BREAKDOWN 2         /* singular Hessenberg (no usable direction) */
+
+/* variant: which triangle the inner sweeps invert (Section 3 splitting) */
+#define GS2_FORWARD 0   /* M = D + wL                                      */
+#define GS2_BACKWARD 1  /* M = D + wU                                      */
+#define GS2_SYMMETRIC 2 /* forward half, then backward half, per sweep     */
+
+/* preconditioner storage / arithmetic precision (Section 9) */
+#define GS2_FP64 0        /* values and vectors float64                    */
+#define GS2_FP32 1        /* values and vectors float32                    */
+#define GS2_FP16_SCALED 2 /* values binary16 after diagonal scaling,       */
+                          /* vectors and accumulation float32              */
+
+/* preconditioner kind for gmres_solve */
+#define GS2_PREC_NONE 0
+#define GS2_PREC_GS2 1
+#define GS2_PREC_JR 2
+#define GS2_PREC_GS_TRISOLVE 3
+
+typedef struct gs2_csr {
+    int64_t n;             /* rows = columns, 0 <= n < 2^31               */
+    int64_t nnz;           /* rowptr[n]                                   */
+    const int32_t *rowptr; /* device, n+1                                 */
+    const int32_t *colind; /* device, nnz                                 */
+    const double *val;     /* device, nnz                                 */
+} gs2_csr;
+
+typedef struct gs2_options {
+    int precision;        /* GS2_FP64 (default) / GS2_FP32 / GS2_FP16_SCALED */
+    double inner_damping; /* gamma of Section 4 (default 1.0)                */
+    int compact;          /* 1: compact form eq. (two-stage-3) (default 0)   */
+    int build_levels;     /* 1: build level sets for gs_trisolve_apply       */
+    int autotune;         /* 1: time candidate schedules at setup (default)  */
+    int lanes_per_row;    /* 0 = automatic; else 1,2,4,...,64 (forced)       */
+    int rhs_per_item;     /* batched: right-hand sides per work item, 0 =    */
+                          /* autotuned over {4,2,1} dividing nrhs            */
+} gs2_options;
+
+typedef struct gs2_solve_info {
+    int iterations; /* Arnoldi steps (preconditioner applications)          */
+    int restarts;   /* cycles after the first                               */
+    double relres;  /* final true ||b - A x||_2 / ||b||_2 (float64)         */
+    int converged;  /* 1 if relres <= rtol                                  */
+    int status;     /* same code as the return value                        */
+    double seconds; /* wall time of the solve on the host clock             */
+} gs2_solve_info;
+
+typedef struct gs2_handle gs2_handle;
+typedef struct gs2_batch gs2_batch;
+
+/* Fill *opt with the defaults listed above. */
+void gs2_default_options(gs2_options *opt);
+
+/*
+ * Build a GS2 preconditioner for A (setup, Sections 3 and 6).
+ * Validates A, extracts D, forms the scaled strictly-lower and strictly-upper
+ * parts Ah = S_l A S_r (S_r = |D|^-1/2, S_l = sign(D) S_r, unit diagonal),
+ * stores them apart from A in a sliced-ELL layout in the chosen precision,
+ * and allocates every temporary the applies need (they persist with the
+ * handle).  sweeps >= 1 outer sweeps (n_t n_k of Fig. code:two-stage on one
+ * GPU), inner >= 0 inner JR sweeps (inner = 0 is Jacobi-Richardson), damping
+ * w in (0, 2) (Section 4, damping factor), variant GS2_FORWARD/BACKWARD/
+ * SYMMETRIC, opt may be NULL.  A's arrays are only read during the call; the
+ * handle owns copies of everything it needs.  Synchronises `stream`.
+ * Errors: GS2_ERR_ARG, GS2_ERR_BAD_CSR, GS2_ERR_ZERO_DIAG, GS2_ERR_NONFINITE,
+ * GS2_ERR_FP16_RANGE, GS2_ERR_NOMEM, GS2_ERR_HIP; *out is NULL on error.
+ */
+int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
+              void *stream, gs2_handle **out);
+
+/*
+ * z = Mhat^{-1} v: `sweeps` GS2 sweeps on A z = v from z = 0, non-compact
+ * form eq. (two-stage) (or eq. (two-stage-3) if the handle is compact).
+ * v, z: device, n float64, must not alias.  Asynchronous on `stream`, no
+ * allocation, no host synchronisation.
+ */
+int gs2_apply(gs2_handle *h, const double *v, double *z, void *stream);
+
+/*
+ * Jacobi-Richardson (the inner = 0 case of Section 4): `sweeps` sweeps of
+ * x = x + w D^{-1}(v - A x) from x = 0, using the handle's stored parts.
+ * Asynchronous, no allocation.
+ */
+int jr_apply(gs2_handle *h, int sweeps, double damping, const double *v, double *z, void *stream);
+
+/*
+ * Exact Gauss-Seidel / SOR by level-scheduled triangular solves (Section 3,
+ * level-set scheduling): the handle's `sweeps` sweeps of the row update
+ * x_i = (1-w) x_i + w (v_i - sum_{j != i} a_ij x_j) / a_ii from x = 0, rows in
+ * ascending (forward), descending (backward) or both (symmetric) order; the
+ * result equals the sequential in-place loop of Section 6.  Requires a handle
+ * built with build_levels = 1 (else GS2_ERR_NO_LEVELS).  Asynchronous.
+ */
+int gs_trisolve_apply(gs2_handle *h, int variant, double damping, const double *v, double *z, void *stream);
+
+/*
+ * Restarted flexible GMRES(restart), right-preconditioned, all Krylov
+ * arithmetic in float64 (Arnoldi by classical Gram-Schmidt with one
+ * reorthogonalisation, Givens rotations on the device, true residual at the
+ * end of every cycle).  x: in = x0, out = solution (device).  b: device.
+ * prec_kind GS2_PREC_* uses `prec` (GS2: gs2_apply; JR: the handle's sweeps
+ * and damping; GS_TRISOLVE: gs_trisolve_apply with the handle's variant and
+ * damping); prec may be NULL only for GS2_PREC_NONE.  Work vectors are cached
+ * in `prec` (allocated once per restart length); with prec == NULL they are
+ * allocated per call.  Converged when ||b - A x||/||b|| <= rtol; b = 0 gives
+ * x = 0.  Synchronises `stream` once per restart cycle and before returning.
+ * Returns GS2_OK, GS2_NOT_CONVERGED (maxit reached), GS2_BREAKDOWN, or an
+ * error; `info` (host, may be NULL) is filled in every case.
+ */
+int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit, int prec_kind,
+                gs2_handle *prec, gs2_solve_info *info, void *stream);
+
+/* Free a handle (NULL is ignored).  Synchronises the device. */
+void gs2_destroy(gs2_handle *h);
+
+/* Static English text for a status code. */
+const char *gs2_status_string(int status);
+
+/*
+ * Introspection for tests and benchmarks: n, stored off-diagonal entries of
+ * L and U, bytes of padded storage, chosen lanes-per-row, number of levels
+ * of L and U (0 without build_levels).  Any pointer may be NULL.
+ */
+int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *nnz_u, int64_t *bytes_stored,
+                     int *lanes_per_row, int *levels_l, int *levels_u);
+
+/* --------------------------------------------------------------- batched
+ *
+ * Many independent systems of uneven sizes, each with nrhs right-hand sides,
+ * solved by GS2-preconditioned GMRES in one persistent kernel launch replayed
+ * from a HIP graph (the multiple right-hand sides of segregated systems,
+ * Section 10, motivate it).  Every system uses the same GS2 parameters.
+ */
+
+/*
+ * As gs2_setup for nsys matrices As[0..nsys) (host array of descriptors of
+ * device CSR arrays).  Allocates the workspace for GMRES(restart) with up to
+ * nrhs right-hand sides per system.  opt->precision applies to every system.
+ */
+int gs2_setup_batched(const gs2_csr *As, int nsys, int sweeps, int inner, double damping, int variant,
+                      const gs2_options *opt, int restart, int nrhs, void *stream, gs2_batch **out);
+
+/*
+ * Solve all systems for all nrhs right-hand sides.  B and X are device
+ * float64 arrays holding, system after system, an n_i x nrhs block in
+ * row-major order (entry (row, r) of system i at offset_i + row*nrhs + r,
+ * offset_i = nrhs * sum_{k<i} n_k).  X is the initial guess on input.
+ * infos: host array of nsys*nrhs records (system-major), may be NULL.
+ * Returns GS2_OK if every system converged, else the first non-OK status.
+ */
+int gmres_solve_batched(gs2_batch *bh, int nrhs, const double *B, double *X, double rtol, int maxit,
+                        gs2_solve_info *infos, void *stream);
+
+void gs2_destroy_batched(gs2_batch *bh);
+
+/* ----------------------------------------------------------- measurement
+ *
+ * Optional per-kernel timing: while enabled, every kernel the library
+ * launches is bracketed by a pair of HIP events recorded on its launch
+ * stream, and tagged with the algorithmic bytes it must move (each stored
+ * matrix entry and each vector element read or written once; sliced-ELL
+ * padding not counted).  Launches of Arnoldi steps that the device skipped
+ * after convergence are discarded.  Adds a few microseconds of host work
+ * per launch; off by default.
+ */
+
+/* enable != 0: clear previous records and start; 0: stop (records kept). */
+int gs2_profile(int enable);
+
+/* Number of kernel kinds; ids are 0 .. count-1. */
+int gs2_profile_kernel_count(void);
+
+/*
+ * Aggregate of kernel kind `kid` over the records: static name, number of
+ * launches, summed event time in ms, summed algorithmic bytes.  Waits for the
+ * recorded events.  Any output pointer may be NULL.
+ */
+int gs2_profile_read(int kid, const char **name, int64_t *launches, double *ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS2_H */

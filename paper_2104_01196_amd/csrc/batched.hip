@@ -1,0 +1,895 @@
+// Batched GS2-preconditioned GMRES for many independent systems of uneven
+// sizes, each with several right-hand sides (the segregated multiple-RHS
+// systems of Section 10 motivate it).
+//
+// One persistent kernel launch solves everything.  A work item is one system
+// together with a group of R right-hand sides; it is solved start to finish
+// by a single workgroup, so every reduction and every ordering point is a
+// workgroup barrier and no workgroup ever waits for another.  Workgroups pop
+// items from an atomic counter, largest systems first (longest processing
+// time first), and leave when the queue is empty.  The R right-hand sides of
+// an item are stored interleaved (row-major n x R), so each matrix entry is
+// loaded once per group and applied to R vectors (an SpMM-like access).
+// Each right-hand side keeps its own Hessenberg matrix, rotations and
+// convergence flag; a right-hand side that has converged stops contributing
+// while the others continue.  The launch is captured in a HIP graph at setup
+// and replayed by every solve; its arguments live in device memory.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <numeric>
+
+#include "gs2_internal.hpp"
+
+namespace gs2 {
+
+constexpr int BT = 512;        // threads per workgroup of the persistent solver
+constexpr int BNW = BT / WAVE; // wavefronts per workgroup
+constexpr int BMAXM = 32;      // longest restart of the batched solver
+constexpr int KC = 8;          // Krylov vectors per chunk of a multi-dot
+
+struct BSys {
+    int64_t n, nslices;
+    const int64_t *Lsp, *Usp;
+    const int32_t *Lcol, *Ucol;
+    const void *Lval, *Uval;
+    const double *sl, *sr;
+    const int32_t *rp, *ci;
+    const double *va;
+    int64_t row0; // rows of all earlier systems
+};
+
+struct BItem {
+    int sys, r0;
+    int64_t base; // scalar offset (row x rhs units) of this item's vectors
+};
+
+struct BParams {
+    const double *B;
+    double *X;
+    double rtol;
+    int maxit, pad;
+};
+
+struct BConst {
+    const BSys *sys;
+    const BItem *items;
+    int nitems, m, nrhs;
+    int sweeps, inner, variant, compact;
+    double omega, gamma;
+    double *V, *Z, *W; // float64 work: (m+1), m, 2 vectors per item
+    void *P;           // preconditioner vectors, 5 per item
+    unsigned *queue;
+    gs2_solve_info *info;
+    const BParams *prm;
+};
+
+enum : int { BD_G = 0, BD_XADD = 1, BD_XSET = 2, BD_ZADD = 3, BD_ZSET = 4 };
+
+template <typename AT, int R>
+__device__ __forceinline__ void bfinish(int dst, int64_t row, const AT (&g)[R], AT w, AT *gout, AT *xh, AT *xout,
+                                        double *z, const double *sr)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = row * R + r;
+        switch (dst) {
+        case BD_G: gout[i] = g[r]; break;
+        case BD_XADD: xout[i] = xh[i] + w * g[r]; break;
+        case BD_XSET: xout[i] = w * g[r]; break;
+        case BD_ZADD: z[i] = sr[row] * (double)(xh[i] + w * g[r]); break;
+        default: z[i] = sr[row] * (double)(w * g[r]); break;
+        }
+    }
+}
+
+// inner JR pass g = rh - w T g_old for R interleaved right-hand sides
+template <typename VT, typename AT, int R, int K>
+__device__ void bp_inner(const BSys &S, int lower, const AT *rh, const AT *gin, const double *v, int rv, int gv,
+                         int damp, AT w, AT gamma, int dst, AT *gout, AT *xh, double *z)
+{
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t *sp = lower ? S.Lsp : S.Usp;
+    const int32_t *col = lower ? S.Lcol : S.Ucol;
+    const VT *val = (const VT *)(lower ? S.Lval : S.Uval);
+    for (int64_t s = wv; s < S.nslices; s += BNW) {
+        const int64_t row = s * (WAVE / K) + lane / K;
+        AT acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = AT(0);
+        for (int64_t p = sp[s] + lane; p < sp[s + 1]; p += WAVE) {
+            const int c = col[p];
+            const AT a = (AT)val[p];
+            if (gv) {
+                const double sc = S.sl[c];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += a * (AT)(v[(int64_t)c * R + r] * sc);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += a * gin[(int64_t)c * R + r];
+            }
+        }
+        if (K > 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = group_sum<K>(acc[r]);
+        }
+        if ((K > 1 && (lane & (K - 1))) || row >= S.n) continue;
+        AT g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = row * R + r;
+            const AT rr = rv ? (AT)(v[i] * S.sl[row]) : rh[i];
+            g[r] = rr - w * acc[r];
+            if (damp) {
+                const AT go = gv ? (AT)(v[i] * S.sl[row]) : gin[i];
+                g[r] = (AT(1) - gamma) * go + gamma * g[r];
+            }
+        }
+        bfinish<AT, R>(dst, row, g, w, gout, xh, xh, z, S.sr);
+    }
+}
+
+// outer residual (non-compact: both triangles; compact: the opposite one)
+template <typename VT, typename AT, int R, int K>
+__device__ void bp_resid(const BSys &S, int lower, int compact, const AT *xh, const double *v, AT cdiag, AT w, int dst,
+                         AT *rh, AT *xout, double *z)
+{
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    for (int64_t s = wv; s < S.nslices; s += BNW) {
+        const int64_t row = s * (WAVE / K) + lane / K;
+        AT acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = AT(0);
+        for (int part = 0; part < 2; ++part) {
+            const bool useL = part == 0;
+            if (compact && (useL == (bool)lower)) continue; // compact: only the opposite triangle
+            const int64_t *sp = useL ? S.Lsp : S.Usp;
+            const int32_t *col = useL ? S.Lcol : S.Ucol;
+            const VT *val = (const VT *)(useL ? S.Lval : S.Uval);
+            for (int64_t p = sp[s] + lane; p < sp[s + 1]; p += WAVE) {
+                const int c = col[p];
+                const AT a = (AT)val[p];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += a * xh[(int64_t)c * R + r];
+            }
+        }
+        if (K > 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = group_sum<K>(acc[r]);
+        }
+        if ((K > 1 && (lane & (K - 1))) || row >= S.n) continue;
+        AT g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = row * R + r;
+            g[r] = ((AT)(v[i] * S.sl[row]) - cdiag * xh[i]) - acc[r];
+        }
+        bfinish<AT, R>(dst, row, g, w, rh, const_cast<AT *>(xh), xout, z, S.sr);
+    }
+}
+
+template <typename AT, int R>
+__device__ void bp_first_jr(const BSys &S, const double *v, AT w, int fin, AT *xh, double *z)
+{
+    for (int64_t i = threadIdx.x; i < S.n * R; i += BT) {
+        const int64_t row = i / R;
+        const AT r = (AT)(v[i] * S.sl[row]);
+        if (fin) z[i] = S.sr[row] * (double)(w * r);
+        else xh[i] = w * r;
+    }
+}
+
+// z = Mhat^{-1} v for the R right-hand sides of one system (the same pass
+// sequence as the single-system apply, with a workgroup barrier between
+// passes).
+template <typename VT, typename AT, int R, int K>
+__device__ void b_precond(const BConst &c, const BSys &S, const double *v, double *z, AT *P)
+{
+    const int64_t nR = S.n * R;
+    AT *xa = P, *xb = P + nR, *rh = P + 2 * nR, *ga = P + 3 * nR, *gb = P + 4 * nR;
+    AT *xc = xa, *xo = xb;
+    const int per = c.variant == GS2_SYMMETRIC ? 2 : 1;
+    const int H = c.sweeps * per;
+    const AT w = (AT)c.omega, gamma = (AT)c.gamma;
+    const int damp = c.gamma != 1.0;
+    const AT cdiag = c.compact ? (AT)(1.0 - 1.0 / c.omega) : AT(1);
+    bool xzero = true;
+    for (int t = 0; t < H; ++t) {
+        const int lower = (c.variant == GS2_FORWARD || (c.variant == GS2_SYMMETRIC && (t % 2) == 0)) ? 1 : 0;
+        const bool fin = t == H - 1;
+        const bool set = xzero || c.compact;
+        if (c.inner == 0) {
+            if (xzero) {
+                bp_first_jr<AT, R>(S, v, w, fin ? 1 : 0, xc, z);
+            } else {
+                const int dst = fin ? (set ? BD_ZSET : BD_ZADD) : (set ? BD_XSET : BD_XADD);
+                bp_resid<VT, AT, R, K>(S, lower, c.compact, xc, v, cdiag, w, dst, nullptr, xo, z);
+                AT *tmp = xc;
+                xc = xo;
+                xo = tmp;
+            }
+            __syncthreads();
+        } else {
+            int rv = 1;
+            if (!xzero) {
+                bp_resid<VT, AT, R, K>(S, lower, c.compact, xc, v, cdiag, w, BD_G, rh, nullptr, nullptr);
+                rv = 0;
+                __syncthreads();
+            }
+            const AT *gin = rh;
+            for (int j = 1; j <= c.inner; ++j) {
+                const bool last = j == c.inner;
+                const int gv = (j == 1 && xzero) ? 1 : 0;
+                AT *gout = (j & 1) ? ga : gb;
+                const int dst = !last ? BD_G : fin ? (set ? BD_ZSET : BD_ZADD) : (set ? BD_XSET : BD_XADD);
+                bp_inner<VT, AT, R, K>(S, lower, rh, gin, v, rv, gv, damp, w, gamma, dst, gout, xc, z);
+                gin = gout;
+                __syncthreads();
+            }
+        }
+        xzero = false;
+    }
+}
+
+// ------------------------------------------------- block-level Krylov pieces
+
+// w = A z (or w = b - A z with bstride > 0) for R interleaved vectors; thread per row.
+template <int R>
+__device__ void b_spmv(const BSys &S, const double *z, double *w, const double *b, int64_t bstride)
+{
+    for (int64_t row = threadIdx.x; row < S.n; row += BT) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        for (int p = S.rp[row]; p < S.rp[row + 1]; ++p) {
+            const double a = S.va[p];
+            const int64_t cc = (int64_t)S.ci[p] * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += a * z[cc + r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) w[row * R + r] = b ? b[row * bstride + r] - acc[r] : acc[r];
+    }
+}
+
+// out[k*R + r] = <V_k(:,r), w(:,r)> for k < nk, then (with_norm) out[nk*R + r]
+// = ||w(:,r)||^2.  Chunks of KC vectors; fixed-order reductions.
+template <int R>
+__device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, const double *w, int with_norm,
+                           double *out, double *red)
+{
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int stride_red = (KC + 1) * R;
+    for (int k0 = 0; k0 < nk || (k0 == 0 && with_norm); k0 += KC) {
+        const int kc = min(KC, nk - k0);
+        const bool nrm = with_norm && k0 == 0;
+        double acc[KC][R];
+        double nacc[R];
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[kk][r] = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) nacc[r] = 0.0;
+        for (int64_t row = threadIdx.x; row < n; row += BT) {
+            double wr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) wr[r] = w[row * R + r];
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) {
+                if (kk < kc) {
+                    const double *vk = V + (int64_t)(k0 + kk) * ldv + row * R;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[kk][r] += vk[r] * wr[r];
+                }
+            }
+            if (nrm) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) nacc[r] += wr[r] * wr[r];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            if (kk < kc) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double s = wave_sum(acc[kk][r]);
+                    if (lane == 0) red[wv * stride_red + kk * R + r] = s;
+                }
+            }
+        }
+        if (nrm) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double s = wave_sum(nacc[r]);
+                if (lane == 0) red[wv * stride_red + KC * R + r] = s;
+            }
+        }
+        __syncthreads();
+        const int cnt = max(kc, 0) * R;
+        for (int t = threadIdx.x; t < cnt + (nrm ? R : 0); t += BT) {
+            const int slot = t < cnt ? t : KC * R + (t - cnt);
+            double s = 0.0;
+            for (int q = 0; q < BNW; ++q) s += red[q * stride_red + slot];
+            if (t < cnt) out[k0 * R + t] = s;
+            else out[nk * R + (t - cnt)] = s;
+        }
+        __syncthreads();
+        if (nk <= 0) break;
+    }
+}
+
+// wout = win - sum_k h[k*R + r] V_k   (h in LDS)
+template <int R>
+__device__ void b_update(int64_t n, const double *V, int64_t ldv, int nk, const double *h, const double *win,
+                         double *wout)
+{
+    for (int64_t row = threadIdx.x; row < n; row += BT) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = win[row * R + r];
+        for (int k = 0; k < nk; ++k) {
+            const double *vk = V + (int64_t)k * ldv + row * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] -= h[k * R + r] * vk[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) wout[row * R + r] = acc[r];
+    }
+}
+
+struct BLds {
+    double *red, *hA, *hB, *H, *cs, *sn, *g, *y, *bnorm, *beta, *inv, *wn2, *nrm;
+    int *done, *kk, *iters, *restarts, *status, *conv, *flag;
+};
+
+__host__ __device__ inline size_t blds_bytes(int m, int R)
+{
+    const size_t d = (size_t)BNW * (KC + 1) * R + 2 * (size_t)(m + 2) * R + (size_t)(m + 1) * m * R +
+                     3 * (size_t)m * R + (size_t)(m + 2) * R + 5 * (size_t)R;
+    return d * sizeof(double) + (6 * (size_t)R + 2) * sizeof(int) + 64;
+}
+
+__device__ inline BLds blds_carve(double *base, int m, int R)
+{
+    BLds L;
+    double *p = base;
+    L.red = p; p += BNW * (KC + 1) * R;
+    L.hA = p; p += (m + 2) * R;
+    L.hB = p; p += (m + 2) * R;
+    L.H = p; p += (m + 1) * m * R;
+    L.cs = p; p += m * R;
+    L.sn = p; p += m * R;
+    L.y = p; p += m * R;
+    L.g = p; p += (m + 2) * R;
+    L.bnorm = p; p += R;
+    L.beta = p; p += R;
+    L.inv = p; p += R;
+    L.wn2 = p; p += R;
+    L.nrm = p; p += R;
+    int *q = (int *)p;
+    L.done = q; q += R;
+    L.kk = q; q += R;
+    L.iters = q; q += R;
+    L.restarts = q; q += R;
+    L.status = q; q += R;
+    L.conv = q; q += R;
+    L.flag = q;
+    return L;
+}
+
+template <typename VT, typename AT, int R, int K>
+__device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
+{
+    const BSys S = c.sys[it.sys];
+    const BParams prm = *c.prm;
+    const int m = c.m, nrhs = c.nrhs;
+    const int64_t n = S.n, nR = n * R;
+    const double *Bb = prm.B + S.row0 * nrhs + it.r0;
+    double *Xb = prm.X + S.row0 * nrhs + it.r0;
+    double *V = c.V + it.base * (m + 1);
+    double *Z = c.Z + it.base * m;
+    double *w = c.W + it.base * 2, *w2 = w + nR;
+    AT *P = (AT *)c.P + it.base * 5;
+    const int t = threadIdx.x;
+    const double rtol = prm.rtol;
+    const int maxit = prm.maxit;
+
+    // ||b|| per right-hand side: gather b into w (interleaved), then a norm pass
+    for (int64_t i = t; i < nR; i += BT) w[i] = Bb[(i / R) * nrhs + (i % R)];
+    __syncthreads();
+    b_multidot<R>(n, nullptr, 0, 0, w, 1, L.bnorm, L.red); // writes L.bnorm[0..R) = ||b||^2
+    if (t < R) {
+        L.bnorm[t] = sqrt(L.bnorm[t]);
+        L.iters[t] = 0;
+        L.restarts[t] = 0;
+        L.status[t] = GS2_OK;
+        L.conv[t] = 0;
+        L.done[t] = 0;
+        if (!isfinite(L.bnorm[t])) L.status[t] = GS2_ERR_NONFINITE;
+        else if (L.bnorm[t] == 0.0) L.conv[t] = 1;
+        L.beta[t] = 0.0;
+    }
+    __syncthreads();
+    // b = 0 -> x = 0
+    for (int64_t i = t; i < nR; i += BT)
+        if (L.conv[i % R]) Xb[(i / R) * nrhs + (i % R)] = 0.0;
+    // working copy of x in w2 (interleaved)
+    for (int64_t i = t; i < nR; i += BT) w2[i] = Xb[(i / R) * nrhs + (i % R)];
+    __syncthreads();
+
+    int cycle = 0;
+    for (;;) {
+        // true residual r = b - A x into V_0, ||r||^2
+        b_spmv<R>(S, w2, V, Bb, nrhs);
+        __syncthreads();
+        b_multidot<R>(n, nullptr, 0, 0, V, 1, L.beta, L.red);
+        if (t == 0) L.flag[0] = 0;
+        __syncthreads();
+        if (t < R) {
+            const double beta = sqrt(L.beta[t]);
+            L.beta[t] = beta;
+            bool act = false;
+            if (L.status[t] == GS2_OK && !L.conv[t]) {
+                const double rel = beta / L.bnorm[t];
+                if (!isfinite(beta)) L.status[t] = GS2_ERR_NONFINITE;
+                else if (rel <= rtol) L.conv[t] = 1;
+                else if (L.iters[t] >= maxit) L.status[t] = GS2_NOT_CONVERGED;
+                else act = true;
+            }
+            L.done[t] = act ? 0 : 1;
+            L.kk[t] = 0;
+            L.inv[t] = act ? 1.0 / beta : 0.0;
+            if (act) {
+                if (cycle > 0) L.restarts[t]++;
+                for (int k = 0; k < m + 2; ++k) L.g[k * R + t] = 0.0;
+                L.g[t] = beta;
+                atomicOr(L.flag, 1);
+            }
+        }
+        __syncthreads();
+        if (!L.flag[0]) break;
+        ++cycle;
+        for (int64_t i = t; i < nR; i += BT) V[i] = L.inv[i % R] == 0.0 ? 0.0 : V[i] * L.inv[i % R];
+        __syncthreads();
+        for (int j = 0; j < m; ++j) {
+            double *vj = V + (int64_t)j * nR;
+            double *zj = Z + (int64_t)j * nR;
+            b_precond<VT, AT, R, K>(c, S, vj, zj, P);
+            // w = A z_j ; hA = V^T w ; ||w||^2
+            b_spmv<R>(S, zj, w, nullptr, 0);
+            __syncthreads();
+            b_multidot<R>(n, V, nR, j + 1, w, 1, L.hA, L.red);
+            if (t < R) L.wn2[t] = L.hA[(j + 1) * R + t];
+            __syncthreads();
+            b_update<R>(n, V, nR, j + 1, L.hA, w, w);
+            __syncthreads();
+            b_multidot<R>(n, V, nR, j + 1, w, 0, L.hB, L.red);
+            double *vn = V + (int64_t)(j + 1) * nR;
+            b_update<R>(n, V, nR, j + 1, L.hB, w, vn);
+            __syncthreads();
+            b_multidot<R>(n, nullptr, 0, 0, vn, 1, L.nrm, L.red);
+            if (t == 0) L.flag[0] = 0;
+            __syncthreads();
+            if (t < R && !L.done[t]) {
+                const int r = t;
+                double col[BMAXM + 1];
+                for (int k = 0; k <= j; ++k) col[k] = L.hA[k * R + r] + L.hB[k * R + r];
+                const double hn = sqrt(L.nrm[r]);
+                const double wn0 = sqrt(L.wn2[r]);
+                for (int k = 0; k < j; ++k) {
+                    const double a = L.cs[k * R + r] * col[k] + L.sn[k * R + r] * col[k + 1];
+                    col[k + 1] = -L.sn[k * R + r] * col[k] + L.cs[k * R + r] * col[k + 1];
+                    col[k] = a;
+                }
+                const double rho = hypot(col[j], hn);
+                L.iters[r]++;
+                if (!isfinite(rho) || !isfinite(hn)) {
+                    L.status[r] = GS2_ERR_NONFINITE;
+                    L.done[r] = 1;
+                    L.iters[r]--;
+                } else if (rho == 0.0) {
+                    L.status[r] = GS2_BREAKDOWN;
+                    L.done[r] = 1;
+                    L.iters[r]--;
+                } else {
+                    L.cs[j * R + r] = col[j] / rho;
+                    L.sn[j * R + r] = hn / rho;
+                    col[j] = rho;
+                    for (int k = 0; k <= j; ++k) L.H[(k * m + j) * R + r] = col[k];
+                    L.g[(j + 1) * R + r] = -L.sn[j * R + r] * L.g[j * R + r];
+                    L.g[j * R + r] = L.cs[j * R + r] * L.g[j * R + r];
+                    L.kk[r] = j + 1;
+                    const bool bd = hn <= 1e-14 * wn0;
+                    L.inv[r] = bd ? 0.0 : 1.0 / hn;
+                    if (fabs(L.g[(j + 1) * R + r]) <= rtol * L.bnorm[r] || bd || j + 1 >= m || L.iters[r] >= maxit)
+                        L.done[r] = 1;
+                }
+                if (L.done[r]) L.inv[r] = 0.0;
+                else atomicOr(L.flag, 1);
+            }
+            __syncthreads();
+            const int more = L.flag[0];
+            for (int64_t i = t; i < nR; i += BT) vn[i] = L.inv[i % R] == 0.0 ? 0.0 : vn[i] * L.inv[i % R];
+            __syncthreads();
+            if (!more) break;
+        }
+        // y = R^{-1} g, x += Z y  (per right-hand side)
+        if (t < R) {
+            const int r = t, kk = L.kk[r];
+            for (int k = kk - 1; k >= 0; --k) {
+                double s = L.g[k * R + r];
+                for (int l = k + 1; l < kk; ++l) s -= L.H[(k * m + l) * R + r] * L.y[l * R + r];
+                L.y[k * R + r] = s / L.H[(k * m + k) * R + r];
+            }
+        }
+        __syncthreads();
+        for (int64_t i = t; i < nR; i += BT) {
+            const int r = (int)(i % R);
+            double acc = w2[i];
+            for (int k = 0; k < L.kk[r]; ++k) acc += L.y[k * R + r] * Z[(int64_t)k * nR + i];
+            w2[i] = acc;
+        }
+        __syncthreads();
+    }
+    // write back x and the per-right-hand-side records
+    for (int64_t i = t; i < nR; i += BT) Xb[(i / R) * nrhs + (i % R)] = w2[i];
+    if (t < R) {
+        gs2_solve_info f;
+        f.iterations = L.iters[t];
+        f.restarts = L.restarts[t];
+        f.relres = L.bnorm[t] > 0.0 ? L.beta[t] / L.bnorm[t] : 0.0;
+        f.converged = L.conv[t];
+        f.status = L.conv[t] ? GS2_OK : (L.status[t] != GS2_OK ? L.status[t] : GS2_NOT_CONVERGED);
+        f.seconds = 0.0;
+        c.info[(int64_t)it.sys * nrhs + it.r0 + t] = f;
+    }
+    __syncthreads();
+}
+
+template <typename VT, typename AT, int R, int K>
+__global__ __launch_bounds__(BT) void k_batched(BConst c)
+{
+    extern __shared__ double lds[];
+    __shared__ int s_item;
+    BLds L = blds_carve(lds, c.m, R);
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(c.queue, 1u);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= c.nitems) break;
+        b_solve_item<VT, AT, R, K>(c, c.items[item], L);
+    }
+}
+
+__global__ void k_reset_queue(unsigned *q)
+{
+    if (threadIdx.x == 0) q[0] = 0u;
+}
+
+// ---------------------------------------------------------------- host side
+
+typedef void (*BatchedKernel)(BConst);
+
+template <typename VT, typename AT>
+static BatchedKernel pick_kernel_t(int R, int K)
+{
+    if (K == 1) {
+        if (R == 1) return k_batched<VT, AT, 1, 1>;
+        if (R == 2) return k_batched<VT, AT, 2, 1>;
+        return k_batched<VT, AT, 4, 1>;
+    }
+    if (R == 1) return k_batched<VT, AT, 1, 4>;
+    if (R == 2) return k_batched<VT, AT, 2, 4>;
+    return k_batched<VT, AT, 4, 4>;
+}
+
+static BatchedKernel pick_kernel(int prec, int R, int K)
+{
+    if (prec == GS2_FP64) return pick_kernel_t<double, double>(R, K);
+    if (prec == GS2_FP32) return pick_kernel_t<float, float>(R, K);
+    return pick_kernel_t<_Float16, float>(R, K);
+}
+
+struct Batch {
+    int nsys = 0, m = 0, nrhs = 0, R = 1, K = 1, precision = GS2_FP32;
+    std::vector<Handle *> hs;
+    std::vector<int64_t> sizes;
+    int32_t *rp = nullptr, *ci = nullptr;
+    double *va = nullptr;
+    BSys *d_sys = nullptr;
+    BItem *d_items = nullptr;
+    int nitems = 0;
+    double *V = nullptr, *Z = nullptr, *W = nullptr;
+    void *P = nullptr;
+    unsigned *queue = nullptr;
+    gs2_solve_info *d_info = nullptr;
+    BParams *d_prm = nullptr, *h_prm = nullptr;
+    BConst cst{};
+    int grid = 1;
+    size_t lds = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (Handle *h : hs) delete h;
+        for (void *p : {(void *)rp, (void *)ci, (void *)va, (void *)d_sys, (void *)d_items, (void *)V, (void *)Z,
+                        (void *)W, P, (void *)queue, (void *)d_info, (void *)d_prm})
+            if (p) (void)hipFree(p);
+        if (h_prm) (void)hipHostFree(h_prm);
+    }
+};
+
+static int build_items(Batch &b, int R)
+{
+    if (b.d_items) (void)hipFree(b.d_items);
+    b.d_items = nullptr;
+    std::vector<int> order(b.nsys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b.sizes[a] > b.sizes[c]; });
+    std::vector<int64_t> row0(b.nsys + 1, 0);
+    for (int i = 0; i < b.nsys; ++i) row0[i + 1] = row0[i] + b.sizes[i];
+    std::vector<BItem> items;
+    for (int i : order)
+        for (int r0 = 0; r0 < b.nrhs; r0 += R) items.push_back(BItem{i, r0, row0[i] * b.nrhs + (int64_t)r0 * b.sizes[i]});
+    b.nitems = (int)items.size();
+    GS2_TRY_HIP(hipMalloc(&b.d_items, sizeof(BItem) * items.size()));
+    GS2_TRY_HIP(hipMemcpy(b.d_items, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice));
+    return GS2_OK;
+}
+
+static int configure(Batch &b, int R)
+{
+    b.R = R;
+    GS2_TRY(build_items(b, R));
+    b.lds = blds_bytes(b.m, R);
+    BatchedKernel kern = pick_kernel(b.precision, R, b.K);
+    if (b.lds > 48 * 1024)
+        GS2_TRY_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds));
+    int per_cu = 0;
+    GS2_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BT, b.lds));
+    int dev = 0, cus = 0;
+    GS2_TRY_HIP(hipGetDevice(&dev));
+    GS2_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b.grid = std::max(1, std::min(b.nitems, std::max(1, per_cu) * cus));
+    b.cst.items = b.d_items;
+    b.cst.nitems = b.nitems;
+    // (re)capture: queue reset + one persistent launch
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    GS2_TRY_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+    k_reset_queue<<<1, 64, 0, b.cap>>>(b.queue);
+    kern<<<b.grid, BT, b.lds, b.cap>>>(b.cst);
+    GS2_TRY_HIP(hipStreamEndCapture(b.cap, &b.graph));
+    GS2_TRY_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+    return GS2_OK;
+}
+
+static int run(Batch &b, const double *B, double *X, double rtol, int maxit, hipStream_t s)
+{
+    b.h_prm->B = B;
+    b.h_prm->X = X;
+    b.h_prm->rtol = rtol;
+    b.h_prm->maxit = maxit;
+    GS2_TRY_HIP(hipMemcpyAsync(b.d_prm, b.h_prm, sizeof(BParams), hipMemcpyHostToDevice, s));
+    Prof pr(s, PK_BATCHED, 0.0);
+    GS2_TRY_HIP(hipGraphLaunch(b.exec, s));
+    return GS2_OK;
+}
+
+static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps, int inner, double damping,
+                              int variant, const gs2_options &o, int restart, int nrhs, hipStream_t s)
+{
+    b.nsys = nsys;
+    b.m = restart;
+    b.nrhs = nrhs;
+    b.precision = o.precision;
+    int64_t rows = 0, nnz = 0, maxslices_rows = 0;
+    double maxavg = 0.0;
+    for (int i = 0; i < nsys; ++i) {
+        rows += As[i].n;
+        nnz += As[i].nnz;
+        maxslices_rows = std::max<int64_t>(maxslices_rows, As[i].n);
+        if (As[i].n) maxavg = std::max(maxavg, (double)(As[i].nnz - As[i].n) / (2.0 * As[i].n));
+    }
+    b.K = (o.lanes_per_row == 4 || (o.lanes_per_row == 0 && maxavg > 12.0)) ? 4 : 1;
+    gs2_options so = o;
+    so.autotune = 0;
+    so.build_levels = 0;
+    so.lanes_per_row = b.K;
+    GS2_TRY_HIP(hipMalloc(&b.rp, sizeof(int32_t) * (rows + nsys)));
+    GS2_TRY_HIP(hipMalloc(&b.ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
+    GS2_TRY_HIP(hipMalloc(&b.va, sizeof(double) * std::max<int64_t>(nnz, 1)));
+    std::vector<BSys> sys(nsys);
+    int64_t roff = 0, noff = 0, row0 = 0;
+    for (int i = 0; i < nsys; ++i) {
+        Handle *h = new (std::nothrow) Handle;
+        if (!h) return GS2_ERR_NOMEM;
+        b.hs.push_back(h);
+        h->n = As[i].n;
+        h->sweeps = sweeps;
+        h->inner = inner;
+        h->variant = variant;
+        h->omega = damping;
+        h->gamma = o.inner_damping;
+        h->precision = o.precision;
+        GS2_TRY(setup_handle(*h, As[i], so, s, false));
+        b.sizes.push_back(As[i].n);
+        GS2_TRY_HIP(hipMemcpyAsync(b.rp + roff, As[i].rowptr, sizeof(int32_t) * (As[i].n + 1), hipMemcpyDeviceToDevice, s));
+        GS2_TRY_HIP(hipMemcpyAsync(b.ci + noff, As[i].colind, sizeof(int32_t) * As[i].nnz, hipMemcpyDeviceToDevice, s));
+        GS2_TRY_HIP(hipMemcpyAsync(b.va + noff, As[i].val, sizeof(double) * As[i].nnz, hipMemcpyDeviceToDevice, s));
+        BSys &d = sys[i];
+        d.n = h->n;
+        d.nslices = h->L.nslices;
+        d.Lsp = h->L.slice_ptr;
+        d.Usp = h->U.slice_ptr;
+        d.Lcol = h->L.col;
+        d.Ucol = h->U.col;
+        d.Lval = h->L.val;
+        d.Uval = h->U.val;
+        d.sl = h->sl;
+        d.sr = h->sr;
+        d.rp = b.rp + roff;
+        d.ci = b.ci + noff;
+        d.va = b.va + noff;
+        d.row0 = row0;
+        roff += As[i].n + 1;
+        noff += As[i].nnz;
+        row0 += As[i].n;
+    }
+    // the copied row pointers index the copied arrays from 0: rowptr is relative per system, as given
+    GS2_TRY_HIP(hipMalloc(&b.d_sys, sizeof(BSys) * nsys));
+    GS2_TRY_HIP(hipMemcpyAsync(b.d_sys, sys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
+    const size_t tot = (size_t)std::max<int64_t>(rows, 1) * nrhs;
+    GS2_TRY_HIP(hipMalloc(&b.V, sizeof(double) * tot * (restart + 1)));
+    GS2_TRY_HIP(hipMalloc(&b.Z, sizeof(double) * tot * restart));
+    GS2_TRY_HIP(hipMalloc(&b.W, sizeof(double) * tot * 2));
+    GS2_TRY_HIP(hipMalloc(&b.P, prec_bytes(o.precision) * tot * 5));
+    GS2_TRY_HIP(hipMalloc(&b.queue, sizeof(unsigned) * 64));
+    GS2_TRY_HIP(hipMalloc(&b.d_info, sizeof(gs2_solve_info) * (size_t)nsys * nrhs));
+    GS2_TRY_HIP(hipMalloc(&b.d_prm, sizeof(BParams)));
+    GS2_TRY_HIP(hipHostMalloc((void **)&b.h_prm, sizeof(BParams), hipHostMallocDefault));
+    GS2_TRY_HIP(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    b.cst.sys = b.d_sys;
+    b.cst.m = restart;
+    b.cst.nrhs = nrhs;
+    b.cst.sweeps = sweeps;
+    b.cst.inner = inner;
+    b.cst.variant = variant;
+    b.cst.compact = o.compact ? 1 : 0;
+    b.cst.omega = damping;
+    b.cst.gamma = o.inner_damping;
+    b.cst.V = b.V;
+    b.cst.Z = b.Z;
+    b.cst.W = b.W;
+    b.cst.P = b.P;
+    b.cst.queue = b.queue;
+    b.cst.info = b.d_info;
+    b.cst.prm = b.d_prm;
+
+    // right-hand sides per work item: autotuned over the divisors of nrhs in {1, 2, 4}
+    std::vector<int> cands;
+    if (o.rhs_per_item) {
+        if ((o.rhs_per_item != 1 && o.rhs_per_item != 2 && o.rhs_per_item != 4) || nrhs % o.rhs_per_item)
+            return GS2_ERR_ARG;
+        cands.push_back(o.rhs_per_item);
+    } else {
+        for (int R : {4, 2, 1})
+            if (nrhs % R == 0) cands.push_back(R);
+    }
+    int bestR = cands.front();
+    if (o.autotune && cands.size() > 1) {
+        double *Bt = nullptr, *Xt = nullptr;
+        GS2_TRY_HIP(hipMalloc(&Bt, sizeof(double) * tot));
+        GS2_TRY_HIP(hipMalloc(&Xt, sizeof(double) * tot));
+        std::vector<double> ones(tot, 1.0);
+        GS2_TRY_HIP(hipMemcpy(Bt, ones.data(), sizeof(double) * tot, hipMemcpyHostToDevice));
+        hipEvent_t e0, e1;
+        GS2_TRY_HIP(hipEventCreate(&e0));
+        GS2_TRY_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        for (int R : cands) {
+            GS2_TRY(configure(b, R));
+            GS2_TRY_HIP(hipMemsetAsync(Xt, 0, sizeof(double) * tot, s));
+            GS2_TRY_HIP(hipEventRecord(e0, s));
+            GS2_TRY(run(b, Bt, Xt, 0.0, restart, s)); // one restart cycle per item
+            GS2_TRY_HIP(hipEventRecord(e1, s));
+            GS2_TRY_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            GS2_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) { best = ms; bestR = R; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipFree(Bt);
+        (void)hipFree(Xt);
+    }
+    GS2_TRY(configure(b, bestR));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    return GS2_OK;
+}
+
+} // namespace gs2
+
+using namespace gs2;
+
+struct gs2_batch {
+    Batch b;
+};
+
+extern "C" {
+
+int gs2_setup_batched(const gs2_csr *As, int nsys, int sweeps, int inner, double damping, int variant,
+                      const gs2_options *opt, int restart, int nrhs, void *stream, gs2_batch **out)
+{
+    if (!out) return GS2_ERR_ARG;
+    *out = nullptr;
+    if (!As || nsys < 1 || sweeps < 1 || inner < 0 || variant < GS2_FORWARD || variant > GS2_SYMMETRIC ||
+        !(damping > 0.0 && damping < 2.0) || restart < 1 || restart > BMAXM || nrhs < 1)
+        return GS2_ERR_ARG;
+    for (int i = 0; i < nsys; ++i)
+        if (As[i].n < 1 || As[i].n >= (int64_t(1) << 31) - 1 || !As[i].rowptr || !As[i].colind || !As[i].val ||
+            As[i].nnz < As[i].n)
+            return GS2_ERR_ARG;
+    gs2_options o;
+    gs2_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision < GS2_FP64 || o.precision > GS2_FP16_SCALED || !(o.inner_damping > 0.0 && o.inner_damping <= 2.0))
+        return GS2_ERR_ARG;
+    gs2_batch *B = new (std::nothrow) gs2_batch;
+    if (!B) return GS2_ERR_NOMEM;
+    int st = GS2_ERR_HIP;
+    try {
+        st = setup_batched_impl(B->b, As, nsys, sweeps, inner, damping, variant, o, restart, nrhs, (hipStream_t)stream);
+    } catch (const std::bad_alloc &) {
+        st = GS2_ERR_NOMEM;
+    } catch (...) {
+        st = GS2_ERR_HIP;
+    }
+    if (st != GS2_OK) {
+        (void)hipDeviceSynchronize();
+        delete B;
+        return st;
+    }
+    *out = B;
+    return GS2_OK;
+}
+
+int gmres_solve_batched(gs2_batch *B, int nrhs, const double *Bv, double *X, double rtol, int maxit,
+                        gs2_solve_info *infos, void *stream)
+{
+    if (!B || nrhs != B->b.nrhs || !Bv || !X || !(rtol >= 0.0) || maxit < 0) return GS2_ERR_ARG;
+    Batch &b = B->b;
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    GS2_TRY(run(b, Bv, X, rtol, maxit, s));
+    std::vector<gs2_solve_info> h((size_t)b.nsys * nrhs);
+    GS2_TRY_HIP(hipMemcpyAsync(h.data(), b.d_info, sizeof(gs2_solve_info) * h.size(), hipMemcpyDeviceToHost, s));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int st = GS2_OK;
+    for (auto &f : h) {
+        f.seconds = sec;
+        if (st == GS2_OK && f.status != GS2_OK) st = f.status;
+    }
+    if (infos) std::memcpy(infos, h.data(), sizeof(gs2_solve_info) * h.size());
+    return st;
+}
+
+void gs2_destroy_batched(gs2_batch *B)
+{
+    if (!B) return;
+    (void)hipDeviceSynchronize();
+    delete B;
+}
+
+} // extern "C"

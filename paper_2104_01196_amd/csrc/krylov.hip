@@ -1,0 +1,595 @@
+// Restarted flexible GMRES(m) in float64 (the Krylov solver the paper pairs
+// with GS2, Sections 1 and 8): right preconditioning with the preconditioned
+// vectors Z stored, Arnoldi by classical Gram-Schmidt with one full
+// reorthogonalisation (CGS2), Givens rotations applied on the device, and the
+// true residual ||b - A x|| at the end of every cycle.  The host synchronises
+// once per cycle; within a cycle every kernel reads a device-side stop flag
+// and returns at once after the residual estimate has met the tolerance.
+//
+// Reductions are deterministic: each workgroup writes one partial per
+// quantity (fixed row range, fixed butterfly), then one workgroup per
+// quantity sums the partials in a fixed order.  No floating-point atomics.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+
+#include "gs2_internal.hpp"
+
+namespace gs2 {
+
+constexpr int MAXM = 128;  // longest restart supported
+constexpr int RB = 1024;   // rows per workgroup in the vector kernels
+constexpr int KT = 256;    // threads per workgroup
+
+struct GState {
+    int j, done, kk, status;
+    int maxsteps, pad0, pad1, pad2;
+    double bnorm, beta, rtol, inv;
+    double hA[MAXM + 2], hB[MAXM + 2], nrm[2];
+    double g[MAXM + 2], cs[MAXM], sn[MAXM], y[MAXM];
+    double H[(MAXM + 1) * MAXM]; // H[k * MAXM + col], upper triangle R after rotations
+};
+
+struct GHeader {
+    int j, done, kk, status;
+    int maxsteps, pad0, pad1, pad2;
+    double bnorm, beta, rtol, inv;
+};
+
+struct GmresWork {
+    int64_t n = 0;
+    int m = 0;
+    int nb = 0; // workgroups of the vector kernels
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *w2 = nullptr, *part = nullptr;
+    GState *st = nullptr;
+    GHeader *hdr = nullptr; // pinned host copy
+};
+
+void free_gmres_work(GmresWork *g)
+{
+    if (!g) return;
+    for (void *p : {(void *)g->V, (void *)g->Z, (void *)g->w, (void *)g->w2, (void *)g->part, (void *)g->st})
+        if (p) (void)hipFree(p);
+    if (g->hdr) (void)hipHostFree(g->hdr);
+    delete g;
+}
+
+static int alloc_work(GmresWork **out, int64_t n, int m)
+{
+    GmresWork *g = new (std::nothrow) GmresWork;
+    if (!g) return GS2_ERR_NOMEM;
+    g->n = n;
+    g->m = m;
+    g->nb = (int)std::max<int64_t>(1, (n + RB - 1) / RB);
+    const size_t N = (size_t)std::max<int64_t>(n, 1);
+    int st = GS2_OK;
+    auto A = [&](void **p, size_t bytes) {
+        if (st == GS2_OK && hipMalloc(p, bytes) != hipSuccess) st = GS2_ERR_NOMEM;
+    };
+    A((void **)&g->V, sizeof(double) * N * (m + 1));
+    A((void **)&g->Z, sizeof(double) * N * m);
+    A((void **)&g->w, sizeof(double) * N);
+    A((void **)&g->w2, sizeof(double) * N);
+    A((void **)&g->part, sizeof(double) * (size_t)g->nb * (MAXM + 2));
+    A((void **)&g->st, sizeof(GState));
+    if (st == GS2_OK && hipHostMalloc((void **)&g->hdr, sizeof(GHeader), hipHostMallocDefault) != hipSuccess)
+        st = GS2_ERR_NOMEM;
+    if (st != GS2_OK) {
+        free_gmres_work(g);
+        return st;
+    }
+    *out = g;
+    return GS2_OK;
+}
+
+// ---------------------------------------------------------------- kernels
+
+// Sum of one value per thread over the workgroup; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int wv = threadIdx.x / WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < KT / WAVE; ++i) s += red[i];
+    return s;
+}
+
+// partial dots of the rows [r0, r0 + RB) held in wl (LDS) against V[0..nk),
+// plus the squared norm of wl when with_norm; written k-major: part[k*nb + b].
+__device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const double *wl, const double *__restrict__ V,
+                                               int64_t ldv, int nk, int with_norm, double *__restrict__ part, int nb,
+                                               double *red /* [MAXM+2][4] */)
+{
+    const int t = threadIdx.x, wv = t / WAVE, ln = t & (WAVE - 1);
+    double wr[RB / KT];
+#pragma unroll
+    for (int u = 0; u < RB / KT; ++u) {
+        const int64_t row = r0 + t + u * KT;
+        wr[u] = row < n ? wl[t + u * KT] : 0.0;
+    }
+    for (int k = 0; k < nk; ++k) {
+        const double *__restrict__ vk = V + (int64_t)k * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < RB / KT; ++u) {
+            const int64_t row = r0 + t + u * KT;
+            if (row < n) s += vk[row] * wr[u];
+        }
+        s = wave_sum(s);
+        if (ln == 0) red[k * 4 + wv] = s;
+    }
+    if (with_norm) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < RB / KT; ++u) s += wr[u] * wr[u];
+        s = wave_sum(s);
+        if (ln == 0) red[nk * 4 + wv] = s;
+    }
+    __syncthreads();
+    const int tot = nk + (with_norm ? 1 : 0);
+    for (int k = t; k < tot; k += KT)
+        part[(int64_t)k * nb + blockIdx.x] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+}
+
+// w = A z (CSR, K lanes per row) fused with h = V^T w and ||w||^2 partials.
+template <int K>
+__global__ __launch_bounds__(KT) void k_spmv_dot(int64_t n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                 const double *__restrict__ z, double *__restrict__ w,
+                                                 const double *__restrict__ V, int64_t ldv, const GState *__restrict__ st,
+                                                 double *__restrict__ part, int nb, int fixed_nk)
+{
+    __shared__ double wl[RB];
+    __shared__ double red[(MAXM + 2) * 4];
+    if (st && st->done) return;
+    const int nk = st ? st->j + 1 : fixed_nk;
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int t = threadIdx.x, q = t & (K - 1);
+    constexpr int RPP = KT / K; // rows per pass
+    for (int pass = 0; pass < RB / RPP; ++pass) {
+        const int lr = pass * RPP + t / K;
+        const int64_t row = r0 + lr;
+        double acc = 0.0;
+        if (row < n) {
+            const int b = rp[row], e = rp[row + 1];
+            for (int p = b + q; p < e; p += K) acc += va[p] * z[ci[p]];
+        }
+        acc = group_sum<K>(acc);
+        if (q == 0) {
+            wl[lr] = acc;
+            if (row < n) w[row] = acc;
+        }
+    }
+    __syncthreads();
+    block_multidot(n, r0, wl, V, ldv, nk, 1, part, nb, red);
+}
+
+// r = b - A x written to out, with ||r||^2 partials.
+template <int K>
+__global__ __launch_bounds__(KT) void k_true_resid(int64_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                   const double *__restrict__ x, const double *__restrict__ b,
+                                                   double *__restrict__ out, double *__restrict__ part, int nb)
+{
+    __shared__ double wl[RB];
+    __shared__ double red[4 * 4];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int t = threadIdx.x, q = t & (K - 1);
+    constexpr int RPP = KT / K;
+    for (int pass = 0; pass < RB / RPP; ++pass) {
+        const int lr = pass * RPP + t / K;
+        const int64_t row = r0 + lr;
+        double acc = 0.0;
+        if (row < n) {
+            const int bb = rp[row], e = rp[row + 1];
+            for (int p = bb + q; p < e; p += K) acc += va[p] * x[ci[p]];
+        }
+        acc = group_sum<K>(acc);
+        if (q == 0) {
+            const double r = row < n ? b[row] - acc : 0.0;
+            wl[lr] = r;
+            if (row < n) out[row] = r;
+        }
+    }
+    __syncthreads();
+    block_multidot(n, r0, wl, nullptr, 0, 0, 1, part, nb, red);
+}
+
+// ||b||^2 partials
+__global__ __launch_bounds__(KT) void k_norm_part(int64_t n, const double *__restrict__ b, double *__restrict__ part, int nb)
+{
+    __shared__ double red[4];
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    double s = 0.0;
+    for (int u = 0; u < RB / KT; ++u) {
+        const int64_t row = r0 + threadIdx.x + u * KT;
+        if (row < n) s += b[row] * b[row];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// CGS pass: wout = win - V h (h = first nk entries of hsrc), then partial
+// dots V^T wout (and ||wout||^2 if with_norm).  wout may be a column of V.
+__global__ __launch_bounds__(KT) void k_update_dot(int64_t n, const double *__restrict__ V, int64_t ldv,
+                                                   const GState *__restrict__ st, int which_h,
+                                                   const double *__restrict__ win, double *__restrict__ wout,
+                                                   int do_dot, int with_norm, double *__restrict__ part, int nb)
+{
+    __shared__ double wl[RB];
+    __shared__ double red[(MAXM + 2) * 4];
+    __shared__ double hs[MAXM + 2];
+    if (st->done) return;
+    const int nk = st->j + 1;
+    const double *hsrc = which_h == 0 ? st->hA : st->hB;
+    for (int k = threadIdx.x; k < nk; k += KT) hs[k] = hsrc[k];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < RB / KT; ++u) {
+        const int64_t row = r0 + t + u * KT;
+        double acc = 0.0;
+        if (row < n) {
+            acc = win[row];
+            for (int k = 0; k < nk; ++k) acc -= hs[k] * V[(int64_t)k * ldv + row];
+            wout[row] = acc;
+        }
+        wl[t + u * KT] = acc;
+    }
+    __syncthreads();
+    if (do_dot || with_norm) block_multidot(n, r0, wl, V, ldv, do_dot ? nk : 0, with_norm, part, nb, red);
+}
+
+// out[k] = sum_b part[k*nb + b] for k < cnt (one workgroup per k).  dst
+// selects a GState field; cnt is read from the state when cnt_from_j.
+__global__ __launch_bounds__(KT) void k_reduce(const double *__restrict__ part, int nb, GState *__restrict__ st,
+                                               int dst, int cnt_extra, int fixed_cnt)
+{
+    __shared__ double red[4];
+    if (dst != 9 && dst != 8 && st->done) return;
+    const int cnt = fixed_cnt > 0 ? fixed_cnt : st->j + 1 + cnt_extra;
+    const int k = blockIdx.x;
+    if (k >= cnt) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += KT) s += part[(int64_t)k * nb + b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        switch (dst) {
+        case 0: st->hA[k] = s; break;
+        case 1: st->hB[k] = s; break;
+        case 2: st->nrm[k] = s; break;
+        case 8: st->bnorm = sqrt(s); break;
+        case 9: st->beta = sqrt(s); break;
+        }
+    }
+}
+
+// Hessenberg column j = hA + hB, h_{j+1,j} = ||w||; apply the previous
+// rotations, form a new one, update the residual estimate g, and decide
+// whether the cycle stops (single thread; O(j) work).
+__global__ void k_givens(GState *__restrict__ st)
+{
+    if (threadIdx.x != 0 || st->done) return;
+    const int j = st->j;
+    double *c = st->hA;
+    for (int k = 0; k <= j; ++k) c[k] += st->hB[k];
+    const double hn = sqrt(st->nrm[0]);
+    const double wn0 = sqrt(st->hA[j + 1]); // ||A z_j|| (slot j+1 of the first pass)
+    for (int k = 0; k < j; ++k) {
+        const double a = st->cs[k] * c[k] + st->sn[k] * c[k + 1];
+        c[k + 1] = -st->sn[k] * c[k] + st->cs[k] * c[k + 1];
+        c[k] = a;
+    }
+    const double rho = hypot(c[j], hn);
+    if (!isfinite(rho) || !isfinite(hn)) {
+        st->status = GS2_ERR_NONFINITE;
+        st->done = 1;
+        st->kk = j; // discard this column
+        return;
+    }
+    if (rho == 0.0) {
+        st->status = GS2_BREAKDOWN;
+        st->done = 1;
+        st->kk = j;
+        return;
+    }
+    st->cs[j] = c[j] / rho;
+    st->sn[j] = hn / rho;
+    c[j] = rho;
+    for (int k = 0; k <= j; ++k) st->H[k * MAXM + j] = c[k];
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    st->kk = j + 1;
+    const bool breakdown = hn <= 1e-14 * wn0;
+    st->inv = breakdown ? 0.0 : 1.0 / hn;
+    if (fabs(st->g[j + 1]) <= st->rtol * st->bnorm || breakdown || j + 1 >= st->maxsteps) st->done = 1;
+    else st->j = j + 1;
+}
+
+// v_{j+1} *= 1/h_{j+1,j}  (skipped once the cycle has stopped)
+__global__ void k_scale_next(int64_t n, double *__restrict__ V, int64_t ldv, const GState *__restrict__ st)
+{
+    if (st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) V[(int64_t)st->j * ldv + i] *= st->inv;
+}
+
+__global__ void k_cycle_init(GState *__restrict__ st, int maxsteps, double rtol)
+{
+    if (threadIdx.x != 0) return;
+    st->j = 0;
+    st->done = 0;
+    st->kk = 0;
+    st->status = GS2_OK;
+    st->maxsteps = maxsteps;
+    st->rtol = rtol;
+    st->inv = 1.0 / st->beta;
+    for (int k = 0; k < MAXM + 2; ++k) st->g[k] = 0.0;
+    st->g[0] = st->beta;
+}
+
+__global__ void k_scale0(int64_t n, double *__restrict__ v, const GState *__restrict__ st)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] *= st->inv;
+}
+
+// y = R^{-1} g over the kk columns of this cycle (single thread).
+__global__ void k_backsolve(GState *__restrict__ st)
+{
+    if (threadIdx.x != 0) return;
+    const int kk = st->kk;
+    for (int k = kk - 1; k >= 0; --k) {
+        double s = st->g[k];
+        for (int l = k + 1; l < kk; ++l) s -= st->H[k * MAXM + l] * st->y[l];
+        st->y[k] = s / st->H[k * MAXM + k];
+    }
+}
+
+// x += Z y
+__global__ __launch_bounds__(KT) void k_update_x(int64_t n, const double *__restrict__ Z, int64_t ldz,
+                                                 const GState *__restrict__ st, double *__restrict__ x)
+{
+    __shared__ double ys[MAXM];
+    const int kk = st->kk;
+    for (int k = threadIdx.x; k < kk; k += KT) ys[k] = st->y[k];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = x[i];
+    for (int k = 0; k < kk; ++k) acc += ys[k] * Z[(int64_t)k * ldz + i];
+    x[i] = acc;
+}
+
+__global__ void k_zero64(int64_t n, double *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+__global__ void k_copy_stop(int64_t n, const double *__restrict__ a, double *__restrict__ b,
+                            const GState *__restrict__ st)
+{
+    if (st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// ------------------------------------------------------------- host side
+
+static int spmv_lanes(const gs2_csr &A)
+{
+    const double avg = A.n ? (double)A.nnz / (double)A.n : 1.0;
+    if (avg <= 8.0) return 4;
+    if (avg <= 16.0) return 8;
+    if (avg <= 32.0) return 16;
+    if (avg <= 64.0) return 32;
+    return 64;
+}
+
+#define GS2_SPMV_DISPATCH(K, kern, grid, ...)                                \
+    do {                                                                     \
+        switch (K) {                                                         \
+        case 4: kern<4><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
+        case 8: kern<8><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
+        case 16: kern<16><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
+        case 32: kern<32><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
+        default: kern<64><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
+        }                                                                    \
+    } while (0)
+
+static int precondition(int kind, gs2_handle *P, const double *v, double *z, int64_t n, const GState *st,
+                        hipStream_t s)
+{
+    switch (kind) {
+    case GS2_PREC_GS2: return apply_gs2(P->h, v, z, s);
+    case GS2_PREC_JR: return apply_jr(P->h, P->h.sweeps, P->h.omega, v, z, s);
+    case GS2_PREC_GS_TRISOLVE: return apply_trisolve(P->h, P->h.variant, P->h.omega, v, z, s);
+    default:
+        k_copy_stop<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, v, z, st);
+        return GS2_OK;
+    }
+}
+
+static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, double rtol, int maxit, int kind,
+                      gs2_handle *P, gs2_solve_info *info, hipStream_t s)
+{
+    const int64_t n = A.n;
+    GmresWork *own = nullptr;
+    GmresWork *W = nullptr;
+    if (P) {
+        if (!P->h.gw || P->h.gw->n != n || P->h.gw->m < m) {
+            if (P->h.gw) free_gmres_work(P->h.gw);
+            P->h.gw = nullptr;
+            GS2_TRY(alloc_work(&P->h.gw, n, m));
+        }
+        W = P->h.gw;
+    } else {
+        GS2_TRY(alloc_work(&own, n, m));
+        W = own;
+    }
+    struct Guard {
+        GmresWork *g;
+        ~Guard() { if (g) free_gmres_work(g); }
+    } guard{own};
+
+    const int nb = W->nb;
+    const unsigned gN = (unsigned)nb;
+    const unsigned gE = (unsigned)((n + 255) / 256);
+    const int K = spmv_lanes(A);
+    GState *st = W->st;
+    GHeader *hdr = W->hdr;
+    if (P) P->h.stop = &st->done;
+    struct StopReset {
+        gs2_handle *P;
+        ~StopReset() { if (P) P->h.stop = nullptr; }
+    } stop_reset{P};
+
+    auto read_hdr = [&]() -> int {
+        GS2_TRY_HIP(hipMemcpyAsync(hdr, st, sizeof(GHeader), hipMemcpyDeviceToHost, s));
+        GS2_TRY_HIP(hipStreamSynchronize(s));
+        return GS2_OK;
+    };
+
+    info->iterations = 0;
+    info->restarts = 0;
+    info->converged = 0;
+    info->relres = 0.0;
+    k_norm_part<<<gN, KT, 0, s>>>(n, b, W->part, nb);
+    k_reduce<<<1, KT, 0, s>>>(W->part, nb, st, 8, 0, 1);
+    GS2_TRY_HIP(hipGetLastError());
+    GS2_TRY(read_hdr());
+    const double bnorm = hdr->bnorm;
+    if (!std::isfinite(bnorm)) return GS2_ERR_NONFINITE;
+    if (bnorm == 0.0) {
+        k_zero64<<<gE, 256, 0, s>>>(n, x);
+        GS2_TRY_HIP(hipStreamSynchronize(s));
+        info->converged = 1;
+        return GS2_OK;
+    }
+    const bool none = kind == GS2_PREC_NONE;
+    double *Zb = none ? W->V : W->Z; // unpreconditioned: z_j = v_j, no copy
+    int total = 0, cycles = 0, status = GS2_OK;
+    bool have_prev = false;
+    // algorithmic bytes: CSR SpMV with A, and one pass over nk Krylov vectors
+    const double spmv_b = 12.0 * (double)A.nnz + 4.0 * (n + 1) + 16.0 * n;
+    const double red_b = 8.0 * nb;
+    for (;;) {
+        prof_set_step(cycles, -1);
+        {
+            Prof pr(s, PK_TRUE_RESID, spmv_b + 8.0 * n);
+            GS2_SPMV_DISPATCH(K, k_true_resid, gN, n, A.rowptr, A.colind, A.val, x, b, W->V, W->part, nb);
+        }
+        {
+            Prof pr(s, PK_REDUCE, red_b);
+            k_reduce<<<1, KT, 0, s>>>(W->part, nb, st, 9, 0, 1);
+        }
+        GS2_TRY_HIP(hipGetLastError());
+        GS2_TRY(read_hdr());
+        if (have_prev) {
+            total += hdr->kk;
+            prof_drop_from_step(cycles - 1, hdr->kk);
+            if (hdr->status != GS2_OK) { status = hdr->status; break; }
+        }
+        const double beta = hdr->beta;
+        info->relres = beta / bnorm;
+        if (!std::isfinite(beta)) { status = GS2_ERR_NONFINITE; break; }
+        if (info->relres <= rtol) { info->converged = 1; break; }
+        if (total >= maxit) { status = GS2_NOT_CONVERGED; break; }
+        if (cycles > 0) info->restarts++;
+        cycles++;
+        const int steps = std::min(m, maxit - total);
+        k_cycle_init<<<1, 64, 0, s>>>(st, steps, rtol);
+        k_scale0<<<gE, 256, 0, s>>>(n, W->V, st);
+        for (int j = 0; j < steps; ++j) {
+            prof_set_step(cycles - 1, j);
+            const double *vj = W->V + (int64_t)j * n;
+            double *zj = Zb + (int64_t)j * n;
+            const double vb = 8.0 * n * (j + 1);
+            if (!none) GS2_TRY(precondition(kind, P, vj, zj, n, st, s));
+            {   // w = A z_j, hA = V^T w, ||w||^2
+                Prof pr(s, PK_SPMV_DOT, spmv_b + vb);
+                GS2_SPMV_DISPATCH(K, k_spmv_dot, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st, W->part,
+                                  nb, 0);
+            }
+            {
+                Prof pr(s, PK_REDUCE, red_b * (j + 2));
+                k_reduce<<<j + 2, KT, 0, s>>>(W->part, nb, st, 0, 1, 0);
+            }
+            {   // w2 = w - V hA ; hB = V^T w2
+                Prof pr(s, PK_CGS, vb + 16.0 * n);
+                k_update_dot<<<gN, KT, 0, s>>>(n, W->V, n, st, 0, W->w, W->w2, 1, 0, W->part, nb);
+            }
+            {
+                Prof pr(s, PK_REDUCE, red_b * (j + 1));
+                k_reduce<<<j + 1, KT, 0, s>>>(W->part, nb, st, 1, 0, 0);
+            }
+            {   // v_{j+1} = w2 - V hB ; ||v_{j+1}||^2
+                Prof pr(s, PK_CGS, vb + 16.0 * n);
+                k_update_dot<<<gN, KT, 0, s>>>(n, W->V, n, st, 1, W->w2, W->V + (int64_t)(j + 1) * n, 0, 1, W->part,
+                                               nb);
+            }
+            {
+                Prof pr(s, PK_REDUCE, red_b);
+                k_reduce<<<1, KT, 0, s>>>(W->part, nb, st, 2, 0, 1);
+            }
+            {
+                Prof pr(s, PK_GIVENS, 0.0);
+                k_givens<<<1, 64, 0, s>>>(st);
+            }
+            {
+                Prof pr(s, PK_SCALE, 16.0 * n);
+                k_scale_next<<<gE, 256, 0, s>>>(n, W->V, n, st);
+            }
+            GS2_TRY_HIP(hipGetLastError());
+        }
+        prof_set_step(cycles - 1, -1);
+        k_backsolve<<<1, 64, 0, s>>>(st);
+        {
+            Prof pr(s, PK_UPDATE_X, 8.0 * n * steps + 16.0 * n);
+            k_update_x<<<gE, KT, 0, s>>>(n, Zb, n, st, x);
+        }
+        GS2_TRY_HIP(hipGetLastError());
+        have_prev = true;
+    }
+    prof_set_step(0, -1);
+    info->iterations = total;
+    return status;
+}
+
+} // namespace gs2
+
+using namespace gs2;
+
+extern "C" int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit,
+                           int prec_kind, gs2_handle *prec, gs2_solve_info *info, void *stream)
+{
+    gs2_solve_info local;
+    gs2_solve_info *inf = info ? info : &local;
+    std::memset(inf, 0, sizeof(*inf));
+    int st = GS2_ERR_ARG;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!A || A->n <= 0 || A->n >= (int64_t(1) << 31) - 1 || !A->rowptr || !A->colind || !A->val || !b || !x ||
+        restart < 1 || restart > MAXM || !(rtol >= 0.0) || maxit < 0 || prec_kind < GS2_PREC_NONE ||
+        prec_kind > GS2_PREC_GS_TRISOLVE || (prec_kind != GS2_PREC_NONE && !prec) ||
+        (prec && prec->h.n != A->n) || (prec_kind == GS2_PREC_GS_TRISOLVE && prec->h.nlev_l == 0)) {
+        st = (prec_kind == GS2_PREC_GS_TRISOLVE && prec && prec->h.nlev_l == 0) ? GS2_ERR_NO_LEVELS : GS2_ERR_ARG;
+    } else {
+        try {
+            st = gmres_impl(*A, b, x, restart, rtol, maxit, prec_kind, prec, inf, (hipStream_t)stream);
+        } catch (const std::bad_alloc &) {
+            st = GS2_ERR_NOMEM;
+        } catch (...) {
+            st = GS2_ERR_HIP;
+        }
+    }
+    inf->status = st;
+    inf->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}

@@ -1,0 +1,522 @@
+// GS2 setup (Sections 3 and 6): validate the CSR input, extract D, build the
+// scaling vectors, split the scaled matrix into its strictly lower and upper
+// triangles in sliced-ELL layout and the requested precision, optionally
+// build level sets, and pick a lane-per-row schedule.  The paper notes that
+// GS2 needs no eigenvalue estimate and only this cheap setup (Section 11).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+
+#include "gs2_internal.hpp"
+
+namespace gs2 {
+
+enum : int { ERRF_BAD_CSR = 1, ERRF_ZERO_DIAG = 2, ERRF_NONFINITE = 4, ERRF_FP16 = 8 };
+
+static int flags_to_status(int f)
+{
+    if (f & ERRF_BAD_CSR) return GS2_ERR_BAD_CSR;
+    if (f & ERRF_ZERO_DIAG) return GS2_ERR_ZERO_DIAG;
+    if (f & ERRF_NONFINITE) return GS2_ERR_NONFINITE;
+    if (f & ERRF_FP16) return GS2_ERR_FP16_RANGE;
+    return GS2_OK;
+}
+
+// One thread per row: structural checks, triangle counts, diagonal.
+__global__ void k_validate(int64_t n, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ va, int32_t *__restrict__ lcnt, int32_t *__restrict__ ucnt,
+                           double *__restrict__ d, int *__restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(err, ERRF_BAD_CSR);
+    if (i >= n) return;
+    const int64_t b = rp[i], e = rp[i + 1];
+    if (b < 0 || e < b || e > nnz) {
+        atomicOr(err, ERRF_BAD_CSR);
+        return;
+    }
+    int prev = -1, nl = 0, nu = 0, found = 0, f = 0;
+    double dv = 0.0;
+    for (int64_t k = b; k < e; ++k) {
+        const int c = ci[k];
+        if (c <= prev || c >= n) f |= ERRF_BAD_CSR;
+        prev = c;
+        const double v = va[k];
+        if (!isfinite(v)) f |= ERRF_NONFINITE;
+        if (c < i) ++nl;
+        else if (c == i) { found = 1; dv = v; }
+        else ++nu;
+    }
+    if (!found || dv == 0.0) f |= ERRF_ZERO_DIAG;
+    if (f) atomicOr(err, f);
+    lcnt[i] = nl;
+    ucnt[i] = nu;
+    d[i] = dv;
+}
+
+__global__ void k_scaling(int64_t n, const double *__restrict__ d, double *__restrict__ sl, double *__restrict__ sr)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = 1.0 / sqrt(fabs(d[i]));
+    sr[i] = s;
+    sl[i] = d[i] < 0.0 ? -s : s;
+}
+
+// Stored entries of each slice: 64 * ceil(longest row / K).  The extra
+// element at index nslices is zero so that an exclusive scan yields the end.
+__global__ void k_slice_len(int64_t n, int64_t nslices, int K, const int32_t *__restrict__ cnt,
+                            int64_t *__restrict__ len)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > nslices) return;
+    if (s == nslices) { len[s] = 0; return; }
+    const int C = WAVE / K;
+    int m = 0;
+    for (int r = 0; r < C; ++r) {
+        const int64_t row = s * C + r;
+        if (row < n) m = max(m, cnt[row]);
+    }
+    len[s] = (int64_t)WAVE * ((m + K - 1) / K);
+}
+
+// IEEE binary16 round-to-nearest-even of a float64, by integer manipulation of
+// the binary64 encoding.  Returns the 16-bit pattern; sets *ovf if the
+// result is infinite or NaN.
+__device__ __forceinline__ uint16_t f64_to_f16_bits(double x, int *ovf)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+    const int ex = (int)((b >> 52) & 0x7ff);
+    const uint64_t man = b & ((1ull << 52) - 1);
+    if (ex == 0x7ff) { *ovf = 1; return sign | 0x7e00u; }
+    if (ex == 0) return sign; // binary64 zero / subnormal: far below half's range
+    const int e = ex - 1023;
+    if (e > 15) { *ovf = 1; return sign | 0x7c00u; }
+    const int E = e < -14 ? -14 : e;
+    const int shift = 42 + (E - e); // bits of the 53-bit significand below half's quantum
+    if (shift >= 54) return sign;
+    const uint64_t m = man | (1ull << 52);
+    uint64_t N = m >> shift;
+    const uint64_t rem = m & ((1ull << shift) - 1), halfq = 1ull << (shift - 1);
+    if (rem > halfq || (rem == halfq && (N & 1))) ++N;
+    const uint32_t bits = ((uint32_t)(E + 14) << 10) + (uint32_t)N;
+    if (bits >= 0x7c00u) { *ovf = 1; return sign | 0x7c00u; }
+    return sign | (uint16_t)bits;
+}
+
+template <typename VT>
+__device__ __forceinline__ VT convert_scaled(double v, int *ovf);
+template <>
+__device__ __forceinline__ double convert_scaled<double>(double v, int *) { return v; }
+template <>
+__device__ __forceinline__ float convert_scaled<float>(double v, int *ovf)
+{
+    const float f = (float)v;
+    if (!isfinite(f)) *ovf = 1;
+    return f;
+}
+template <>
+__device__ __forceinline__ _Float16 convert_scaled<_Float16>(double v, int *ovf)
+{
+    const uint16_t bits = f64_to_f16_bits(v, ovf);
+    _Float16 h;
+    __builtin_memcpy(&h, &bits, 2);
+    return h;
+}
+
+// One thread per (slice, lane): writes the lane's entries of its row, the
+// value (s_l[i] * a_ij) * s_r[j] rounded once to VT, padding with
+// (own column, 0).
+template <typename VT>
+__global__ void k_fill(int64_t n, int64_t nslices, int K, int lower, const int32_t *__restrict__ rp,
+                       const int32_t *__restrict__ ci, const double *__restrict__ va, const int32_t *__restrict__ lcnt,
+                       const int32_t *__restrict__ cnt, const double *__restrict__ sl, const double *__restrict__ sr,
+                       const int64_t *__restrict__ sp, int32_t *__restrict__ col, VT *__restrict__ val,
+                       int *__restrict__ err)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = gid / WAVE;
+    if (s >= nslices) return;
+    const int l = (int)(gid % WAVE);
+    const int C = WAVE / K;
+    const int r = l / K, q = l % K;
+    const int64_t row = s * C + r;
+    const int64_t beg = sp[s];
+    const int steps = (int)((sp[s + 1] - beg) / WAVE);
+    const int c_row = row < n ? cnt[row] : 0;
+    const int64_t base = row < n ? (int64_t)rp[row] + (lower ? 0 : lcnt[row] + 1) : 0;
+    const int32_t pad_col = (int32_t)(row < n ? row : n - 1);
+    const double srow = row < n ? sl[row] : 0.0;
+    int ovf = 0;
+    for (int t = 0; t < steps; ++t) {
+        const int e = t * K + q;
+        const int64_t pos = beg + (int64_t)t * WAVE + l;
+        if (e < c_row) {
+            const int32_t c = ci[base + e];
+            const double sc = (srow * va[base + e]) * sr[c];
+            col[pos] = c;
+            val[pos] = convert_scaled<VT>(sc, &ovf);
+        } else {
+            col[pos] = pad_col;
+            val[pos] = VT(0);
+        }
+    }
+    if (ovf) atomicOr(err, ERRF_FP16);
+}
+
+void free_sell(Sell &S)
+{
+    if (S.slice_ptr) (void)hipFree(S.slice_ptr);
+    if (S.col) (void)hipFree(S.col);
+    if (S.val) (void)hipFree(S.val);
+    S.slice_ptr = nullptr;
+    S.col = nullptr;
+    S.val = nullptr;
+}
+
+int choose_lanes(double avg_len, int max_len)
+{
+    (void)max_len;
+    if (avg_len <= 12.0) return 1;
+    if (avg_len <= 24.0) return 2;
+    if (avg_len <= 48.0) return 4;
+    if (avg_len <= 96.0) return 8;
+    return 16;
+}
+
+static int build_one(Sell &S, int64_t n, int K, int lower, int precision, const gs2_csr &A, const int32_t *lcnt,
+                     const int32_t *cnt, const double *sl, const double *sr, int *err, hipStream_t s)
+{
+    free_sell(S);
+    S.n = n;
+    S.K = K;
+    S.C = WAVE / K;
+    S.nslices = (n + S.C - 1) / S.C;
+    S.val_bytes = precision == GS2_FP64 ? 8 : precision == GS2_FP32 ? 4 : 2;
+    int64_t *len = nullptr;
+    GS2_TRY_HIP(hipMalloc(&S.slice_ptr, sizeof(int64_t) * (S.nslices + 1)));
+    GS2_TRY_HIP(hipMalloc(&len, sizeof(int64_t) * (S.nslices + 1)));
+    const int tb = 256;
+    k_slice_len<<<(unsigned)((S.nslices + 1 + tb - 1) / tb), tb, 0, s>>>(n, S.nslices, K, cnt, len);
+    size_t tmp_bytes = 0;
+    GS2_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, len, S.slice_ptr, (int)(S.nslices + 1), s));
+    void *tmp = nullptr;
+    GS2_TRY_HIP(hipMalloc(&tmp, tmp_bytes + 16));
+    GS2_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, len, S.slice_ptr, (int)(S.nslices + 1), s));
+    GS2_TRY_HIP(hipMemcpyAsync(&S.padded, S.slice_ptr + S.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    (void)hipFree(tmp);
+    (void)hipFree(len);
+    const int64_t alloc = std::max<int64_t>(S.padded, WAVE);
+    GS2_TRY_HIP(hipMalloc(&S.col, sizeof(int32_t) * alloc));
+    GS2_TRY_HIP(hipMalloc(&S.val, (size_t)S.val_bytes * alloc));
+    const int64_t threads = S.nslices * WAVE;
+    const unsigned grid = (unsigned)((threads + tb - 1) / tb);
+    if (S.nslices > 0) {
+        if (precision == GS2_FP64)
+            k_fill<double><<<grid, tb, 0, s>>>(n, S.nslices, K, lower, A.rowptr, A.colind, A.val, lcnt, cnt, sl, sr,
+                                               S.slice_ptr, S.col, (double *)S.val, err);
+        else if (precision == GS2_FP32)
+            k_fill<float><<<grid, tb, 0, s>>>(n, S.nslices, K, lower, A.rowptr, A.colind, A.val, lcnt, cnt, sl, sr,
+                                              S.slice_ptr, S.col, (float *)S.val, err);
+        else
+            k_fill<_Float16><<<grid, tb, 0, s>>>(n, S.nslices, K, lower, A.rowptr, A.colind, A.val, lcnt, cnt, sl,
+                                                 sr, S.slice_ptr, S.col, (_Float16 *)S.val, err);
+        GS2_TRY_HIP(hipGetLastError());
+    }
+    return GS2_OK;
+}
+
+// Process-wide cache of autotuned lane counts, keyed by the size bucket,
+// rounded mean row length, longest-row bucket and precision.
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+
+static std::string tune_key(int64_t n, double avg, int maxlen, int prec)
+{
+    int nb = 0;
+    while ((int64_t(1) << nb) < n) ++nb;
+    int mb = 0;
+    while ((1 << mb) < maxlen) ++mb;
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "n%d_a%d_m%d_p%d", nb, (int)std::lround(avg), mb, prec);
+    return buf;
+}
+
+struct SetupScratch {
+    int32_t *lcnt = nullptr, *ucnt = nullptr;
+    double *d = nullptr;
+    int *err = nullptr;
+    ~SetupScratch()
+    {
+        if (lcnt) (void)hipFree(lcnt);
+        if (ucnt) (void)hipFree(ucnt);
+        if (d) (void)hipFree(d);
+        if (err) (void)hipFree(err);
+    }
+};
+
+static int read_err(int *err, hipStream_t s)
+{
+    int f = 0;
+    GS2_TRY_HIP(hipMemcpyAsync(&f, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    return flags_to_status(f);
+}
+
+// Level sets of the DAGs of L (ascending) and U (descending), computed on the
+// host from a copy of the pattern: level_i = 1 + max level over the
+// triangle's entries of row i.  Rows are then grouped level by level.
+static int build_levels(Handle &h, const gs2_csr &A, hipStream_t s)
+{
+    const int64_t n = A.n;
+    std::vector<int32_t> rp(n + 1), ci(A.nnz);
+    GS2_TRY_HIP(hipMemcpyAsync(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    if (A.nnz) GS2_TRY_HIP(hipMemcpyAsync(ci.data(), A.colind, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, s));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> lev(n);
+    for (int lower = 1; lower >= 0; --lower) {
+        int nlev = 0;
+        for (int64_t q = 0; q < n; ++q) {
+            const int64_t i = lower ? q : n - 1 - q;
+            int lv = 0;
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+                const int32_t c = ci[k];
+                if (lower ? c < i : c > i) lv = std::max(lv, lev[c] + 1);
+            }
+            lev[i] = lv;
+            nlev = std::max(nlev, lv + 1);
+        }
+        std::vector<int64_t> ptr(nlev + 1, 0);
+        for (int64_t i = 0; i < n; ++i) ptr[lev[i] + 1]++;
+        for (int l = 0; l < nlev; ++l) ptr[l + 1] += ptr[l];
+        std::vector<int32_t> rows(std::max<int64_t>(n, 1));
+        std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i) rows[pos[lev[i]]++] = (int32_t)i;
+        int32_t *d_rows = nullptr;
+        GS2_TRY_HIP(hipMalloc(&d_rows, sizeof(int32_t) * rows.size()));
+        GS2_TRY_HIP(hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, s));
+        GS2_TRY_HIP(hipStreamSynchronize(s));
+        if (lower) {
+            h.nlev_l = nlev;
+            h.lev_rows_l = d_rows;
+            h.lev_ptr_l = std::move(ptr);
+        } else {
+            h.nlev_u = nlev;
+            h.lev_rows_u = d_rows;
+            h.lev_ptr_u = std::move(ptr);
+        }
+    }
+    return GS2_OK;
+}
+
+static int alloc_vectors(Handle &h)
+{
+    const size_t vb = prec_bytes(h.precision) * (size_t)std::max<int64_t>(h.n, 1);
+    GS2_TRY_HIP(hipMalloc(&h.xh, vb));
+    GS2_TRY_HIP(hipMalloc(&h.xh2, vb));
+    GS2_TRY_HIP(hipMalloc(&h.rh, vb));
+    GS2_TRY_HIP(hipMalloc(&h.ga, vb));
+    GS2_TRY_HIP(hipMalloc(&h.gb, vb));
+    return GS2_OK;
+}
+
+int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t s, bool alloc_vecs)
+{
+    const int64_t n = A.n;
+    if (n == 0) return GS2_OK;
+    SetupScratch sc;
+    const size_t nb = (size_t)std::max<int64_t>(n, 1);
+    GS2_TRY_HIP(hipMalloc(&sc.lcnt, sizeof(int32_t) * nb));
+    GS2_TRY_HIP(hipMalloc(&sc.ucnt, sizeof(int32_t) * nb));
+    GS2_TRY_HIP(hipMalloc(&sc.d, sizeof(double) * nb));
+    GS2_TRY_HIP(hipMalloc(&sc.err, sizeof(int)));
+    GS2_TRY_HIP(hipMalloc(&h.sl, sizeof(double) * nb));
+    GS2_TRY_HIP(hipMalloc(&h.sr, sizeof(double) * nb));
+    GS2_TRY_HIP(hipMemsetAsync(sc.err, 0, sizeof(int), s));
+    const int tb = 256;
+    const unsigned g = (unsigned)((n + tb) / tb);
+    k_validate<<<g, tb, 0, s>>>(n, A.nnz, A.rowptr, A.colind, A.val, sc.lcnt, sc.ucnt, sc.d, sc.err);
+    GS2_TRY_HIP(hipGetLastError());
+    GS2_TRY(read_err(sc.err, s));
+    k_scaling<<<g, tb, 0, s>>>(n, sc.d, h.sl, h.sr);
+    GS2_TRY_HIP(hipGetLastError());
+
+    // row-length statistics of L (U has the same count for symmetric patterns)
+    const double avg = n ? (double)(A.nnz - n) / (2.0 * n) : 0.0;
+    int maxlen = 0;
+    {
+        std::vector<int32_t> rp(n + 1);
+        GS2_TRY_HIP(hipMemcpyAsync(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        GS2_TRY_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n; ++i) maxlen = std::max(maxlen, rp[i + 1] - rp[i] - 1);
+    }
+    if (alloc_vecs) GS2_TRY(alloc_vectors(h));
+
+    int K = o.lanes_per_row;
+    if (K != 0 && (K < 1 || K > 64 || (K & (K - 1)))) return GS2_ERR_ARG;
+    if (K == 0) {
+        K = choose_lanes(avg, maxlen);
+        if (o.autotune && alloc_vecs && n >= 4096) {
+            const std::string key = tune_key(n, avg, maxlen, h.precision);
+            int cached = 0;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                auto it = g_tune_cache.find(key);
+                if (it != g_tune_cache.end()) cached = it->second;
+            }
+            if (cached) {
+                K = cached;
+            } else {
+                float best = 1e30f;
+                int bestK = K;
+                for (int cand = 1; cand <= 16; cand *= 2) {
+                    if (cand > 1 && cand > 2 * std::max(1.0, avg)) break;
+                    GS2_TRY(build_one(h.L, n, cand, 1, h.precision, A, sc.lcnt, sc.lcnt, h.sl, h.sr, sc.err, s));
+                    float ms = 0.f;
+                    GS2_TRY(time_inner_pass(h, s, &ms));
+                    if (ms < best) { best = ms; bestK = cand; }
+                }
+                K = bestK;
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune_cache[key] = K;
+            }
+        }
+    }
+    GS2_TRY(build_one(h.L, n, K, 1, h.precision, A, sc.lcnt, sc.lcnt, h.sl, h.sr, sc.err, s));
+    GS2_TRY(build_one(h.U, n, K, 0, h.precision, A, sc.lcnt, sc.ucnt, h.sl, h.sr, sc.err, s));
+    GS2_TRY(read_err(sc.err, s));
+    // real entry counts
+    h.L.nnz = h.U.nnz = 0;
+    {
+        std::vector<int32_t> lc(n), uc(n);
+        if (n) {
+            GS2_TRY_HIP(hipMemcpyAsync(lc.data(), sc.lcnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            GS2_TRY_HIP(hipMemcpyAsync(uc.data(), sc.ucnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+            GS2_TRY_HIP(hipStreamSynchronize(s));
+        }
+        for (int64_t i = 0; i < n; ++i) { h.L.nnz += lc[i]; h.U.nnz += uc[i]; }
+    }
+    if (o.build_levels) GS2_TRY(build_levels(h, A, s));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    return GS2_OK;
+}
+
+} // namespace gs2
+
+using namespace gs2;
+
+Handle::~Handle()
+{
+    free_sell(L);
+    free_sell(U);
+    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, (void *)lev_rows_l, (void *)lev_rows_u})
+        if (p) (void)hipFree(p);
+    if (gw) free_gmres_work(gw);
+}
+
+extern "C" {
+
+void gs2_default_options(gs2_options *opt)
+{
+    if (!opt) return;
+    opt->precision = GS2_FP64;
+    opt->inner_damping = 1.0;
+    opt->compact = 0;
+    opt->build_levels = 0;
+    opt->autotune = 1;
+    opt->lanes_per_row = 0;
+    opt->rhs_per_item = 0;
+}
+
+int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
+              void *stream, gs2_handle **out)
+{
+    if (!out) return GS2_ERR_ARG;
+    *out = nullptr;
+    if (!A || A->n < 0 || A->n >= (int64_t(1) << 31) - 1 || A->nnz < A->n || A->nnz >= (int64_t(1) << 31) - 1)
+        return GS2_ERR_ARG;
+    if ((A->n > 0) && (!A->rowptr || !A->colind || !A->val)) return GS2_ERR_ARG;
+    if (sweeps < 1 || inner < 0 || variant < GS2_FORWARD || variant > GS2_SYMMETRIC) return GS2_ERR_ARG;
+    if (!(damping > 0.0 && damping < 2.0)) return GS2_ERR_ARG;
+    gs2_options o;
+    gs2_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision < GS2_FP64 || o.precision > GS2_FP16_SCALED) return GS2_ERR_ARG;
+    if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
+    gs2_handle *H = new (std::nothrow) gs2_handle;
+    if (!H) return GS2_ERR_NOMEM;
+    Handle &h = H->h;
+    h.n = A->n;
+    h.sweeps = sweeps;
+    h.inner = inner;
+    h.variant = variant;
+    h.omega = damping;
+    h.gamma = o.inner_damping;
+    h.compact = o.compact ? 1 : 0;
+    h.precision = o.precision;
+    hipStream_t s = (hipStream_t)stream;
+    int st = GS2_ERR_HIP;
+    try {
+        st = setup_handle(h, *A, o, s, true);
+    } catch (const std::bad_alloc &) {
+        st = GS2_ERR_NOMEM;
+    } catch (...) {
+        st = GS2_ERR_HIP;
+    }
+    if (st != GS2_OK) {
+        (void)hipStreamSynchronize(s);
+        delete H;
+        return st;
+    }
+    *out = H;
+    return GS2_OK;
+}
+
+void gs2_destroy(gs2_handle *H)
+{
+    if (!H) return;
+    (void)hipDeviceSynchronize();
+    delete H;
+}
+
+const char *gs2_status_string(int status)
+{
+    switch (status) {
+    case GS2_OK: return "success";
+    case GS2_ERR_ARG: return "invalid argument";
+    case GS2_ERR_BAD_CSR: return "malformed CSR (unsorted, duplicate or out-of-range column, bad row pointer)";
+    case GS2_ERR_ZERO_DIAG: return "diagonal entry missing or zero";
+    case GS2_ERR_NONFINITE: return "non-finite value (NaN or Inf)";
+    case GS2_ERR_NOMEM: return "device allocation failed";
+    case GS2_ERR_HIP: return "HIP runtime error";
+    case GS2_ERR_FP16_RANGE: return "scaled matrix value outside binary16 range";
+    case GS2_ERR_NO_LEVELS: return "handle was built without level sets";
+    case GS2_NOT_CONVERGED: return "not converged within maxit iterations";
+    case GS2_BREAKDOWN: return "GMRES breakdown (singular Hessenberg)";
+    default: return "unknown status";
+    }
+}
+
+int gs2_handle_query(const gs2_handle *H, int64_t *n, int64_t *nnz_l, int64_t *nnz_u, int64_t *bytes_stored,
+                     int *lanes_per_row, int *levels_l, int *levels_u)
+{
+    if (!H) return GS2_ERR_ARG;
+    const Handle &h = H->h;
+    if (n) *n = h.n;
+    if (nnz_l) *nnz_l = h.L.nnz;
+    if (nnz_u) *nnz_u = h.U.nnz;
+    if (bytes_stored)
+        *bytes_stored = (h.L.padded + h.U.padded) * (int64_t)(4 + h.L.val_bytes) +
+                        8 * (h.L.nslices + h.U.nslices + 2) + 16 * h.n;
+    if (lanes_per_row) *lanes_per_row = h.L.K;
+    if (levels_l) *levels_l = h.nlev_l;
+    if (levels_u) *levels_u = h.nlev_u;
+    return GS2_OK;
+}
+
+} // extern "C"

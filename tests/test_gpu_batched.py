@@ -1,0 +1,154 @@
+"""GPU parity of the batched persistent GS2-GMRES solver: every (system,
+right-hand side) pair against an independent oracle solve of that system
+(the systems are independent, so this is exact parity of the method).
+
+Bar: iteration count within +-1 of the oracle (CGS2 on the GPU, MGS in the
+oracle), true relative residual <= rtol recomputed on the host, and the
+solution within 1e-5 (relative) of the oracle's.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2104_01196_amd as g  # noqa: E402
+from gen import convdiff2d, rng_streams, random_sparse  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def make_batch(sides, nrhs, seed):
+    r_pe, r_th, r_b = rng_streams(3, seed)
+    mats = [convdiff2d(int(s), float(r_pe.uniform(0, 50)), float(r_th.uniform(0, 2 * np.pi))) for s in sides]
+    rhs = [r_b.standard_normal((A.n, nrhs)) for A in mats]
+    return mats, rhs
+
+
+def run_batch(mats, rhs, nrhs, X0=None, **kw):
+    dm = [g.DeviceCSR.from_host(A) for A in mats]
+    bh = g.gs2_setup_batched(dm, nrhs=nrhs, **kw)
+    B = torch.as_tensor(np.concatenate([r.ravel() for r in rhs]), device=DEV)
+    X = torch.zeros_like(B) if X0 is None else torch.as_tensor(X0, device=DEV).clone()
+    st, infos = g.gmres_solve_batched(bh, nrhs, B, X, 1e-8, 5000)
+    torch.cuda.synchronize()
+    xs, off = [], 0
+    Xh = X.cpu().numpy()
+    for A in mats:
+        xs.append(Xh[off:off + A.n * nrhs].reshape(A.n, nrhs))
+        off += A.n * nrhs
+    return st, infos, xs, bh, B, X
+
+
+def check_against_oracle(mats, rhs, nrhs, infos, xs, precision, sweeps, inner, restart, x0s=None):
+    for i, A in enumerate(mats):
+        S = A.to_scipy()
+        for r in range(nrhs):
+            b = rhs[i][:, r]
+            f = infos[i * nrhs + r]
+            x0 = None if x0s is None else x0s[i][:, r]
+            xo, io = oracle.gmres(A, b, x0, restart=restart, rtol=1e-8, prec="gs2", sweeps=sweeps, inner=inner,
+                                  precision=precision)
+            assert f["converged"] and io["converged"], (i, r, f, io)
+            assert abs(f["iterations"] - io["iterations"]) <= 1, (i, r, f, io)
+            x = xs[i][:, r]
+            assert np.linalg.norm(b - S @ x) / np.linalg.norm(b) <= 1e-8
+            assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-5
+
+
+@pytest.mark.parametrize("rhs_per_item", [1, 2, 4])
+def test_batched_fp32_matches_oracle(rhs_per_item):
+    sides = [8, 13, 20, 31, 40, 9, 23]
+    mats, rhs = make_batch(sides, 4, 7)
+    st, infos, xs, *_ = run_batch(mats, rhs, 4, sweeps=2, inner=2, precision=g.FP32, restart=20,
+                                  rhs_per_item=rhs_per_item)
+    assert st == 0
+    check_against_oracle(mats, rhs, 4, infos, xs, oracle.FP32, 2, 2, 20)
+
+
+@pytest.mark.parametrize("precision", [g.FP64, g.FP16_SCALED])
+def test_batched_other_precisions(precision):
+    mats, rhs = make_batch([17, 33, 12], 2, 8)
+    st, infos, xs, *_ = run_batch(mats, rhs, 2, sweeps=1, inner=1, precision=precision, restart=15)
+    assert st == 0
+    check_against_oracle(mats, rhs, 2, infos, xs, {g.FP64: oracle.FP64, g.FP16_SCALED: oracle.FP16S}[precision],
+                         1, 1, 15)
+
+
+def test_batched_initial_guess_zero_rhs_and_replays():
+    """Nonzero initial guesses are honoured, an all-zero right-hand side gives
+    x = 0 with no iteration, and replaying the captured graph several times
+    (with other GPU work and synchronisations in between) gives bitwise-equal
+    results every time."""
+    mats, rhs = make_batch([15, 26, 11], 4, 9)
+    rhs[1][:, 2] = 0.0
+    rng = np.random.default_rng(3)
+    x0s = [rng.standard_normal((A.n, 4)) for A in mats]
+    X0 = np.concatenate([x.ravel() for x in x0s])
+    st, infos, xs, bh, B, X = run_batch(mats, rhs, 4, X0=X0, sweeps=2, inner=2, precision=g.FP32, restart=20)
+    assert st == 0
+    f = infos[1 * 4 + 2]
+    assert f["converged"] and f["iterations"] == 0 and not xs[1][:, 2].any()
+    x0c = [x.copy() for x in x0s]
+    x0c[1][:, 2] = 0.0  # the zero column's result is zero whatever its x0
+    keep = [(i, r) for i in range(3) for r in range(4) if not (i == 1 and r == 2)]
+    for i, r in keep:
+        xo, io = oracle.gmres(mats[i], rhs[i][:, r], x0s[i][:, r], restart=20, rtol=1e-8, prec="gs2", sweeps=2,
+                              inner=2, precision=oracle.FP32)
+        assert abs(infos[i * 4 + r]["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(xs[i][:, r] - xo) / np.linalg.norm(xo) <= 1e-5
+    first = X.clone()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=DEV, dtype=torch.float64)
+        _ = (junk * 2).sum().item()  # eager work and a synchronisation between replays
+        X.copy_(torch.as_tensor(X0, device=DEV))
+        st2, infos2 = g.gmres_solve_batched(bh, 4, B, X, 1e-8, 5000)
+        torch.cuda.synchronize()
+        assert st2 == 0 and torch.equal(X, first)
+        assert [q["iterations"] for q in infos2] == [q["iterations"] for q in infos]
+
+
+def test_batched_not_converged_and_general_rows():
+    """maxit reached -> GS2_NOT_CONVERGED per right-hand side; a random
+    nonsymmetric matrix with long rows uses the 4-lanes-per-row schedule."""
+    A = random_sparse(300, seed=12, avg_offdiag=30, long_rows=3, long_len=120)
+    mats = [A, convdiff2d(10, 5.0, 1.0)]
+    rng = np.random.default_rng(5)
+    rhs = [rng.standard_normal((M.n, 2)) for M in mats]
+    dm = [g.DeviceCSR.from_host(M) for M in mats]
+    bh = g.gs2_setup_batched(dm, nrhs=2, sweeps=1, inner=1, precision=g.FP64, restart=10)
+    B = torch.as_tensor(np.concatenate([r.ravel() for r in rhs]), device=DEV)
+    X = torch.zeros_like(B)
+    st, infos = g.gmres_solve_batched(bh, 2, B, X, 1e-14, 3)
+    assert st == 1 and all(f["status"] == 1 and f["iterations"] == 3 for f in infos)
+    X.zero_()
+    st, infos = g.gmres_solve_batched(bh, 2, B, X, 1e-8, 5000)
+    assert st == 0
+    Xh = X.cpu().numpy()
+    for r in range(2):
+        xo, io = oracle.gmres(A, rhs[0][:, r], restart=10, rtol=1e-8, prec="gs2", sweeps=1, inner=1)
+        assert abs(infos[r]["iterations"] - io["iterations"]) <= 1
+        assert np.linalg.norm(Xh[:A.n * 2].reshape(A.n, 2)[:, r] - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+@pytest.mark.slow
+def test_batched_full_size_sampled():
+    """The full 512-system workload (sides 16..256, 4 right-hand sides):
+    every pair reaches 1e-8 (true residual recomputed on the host) and a
+    sample of pairs matches independent oracle solves."""
+    from gen import config_problem
+
+    p = config_problem(5)
+    mats, rhs = p["mats"], p["rhs"]
+    st, infos, xs, *_ = run_batch(mats, rhs, 4, sweeps=2, inner=2, precision=g.FP32, restart=20)
+    assert st == 0
+    for i, A in enumerate(mats):
+        S = A.to_scipy()
+        R = rhs[i] - S @ xs[i]
+        assert np.all(np.linalg.norm(R, axis=0) / np.linalg.norm(rhs[i], axis=0) <= 1e-8)
+    for i in (0, 100, 257, 511):
+        for r in (0, 3):
+            xo, io = oracle.gmres(mats[i], rhs[i][:, r], restart=20, rtol=1e-8, prec="gs2", sweeps=2, inner=2,
+                                  precision=oracle.FP32)
+            assert abs(infos[i * 4 + r]["iterations"] - io["iterations"]) <= 1

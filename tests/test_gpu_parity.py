@@ -1,0 +1,341 @@
+"""GPU parity: every entry point of the HIP library against the CPU oracle on
+the same seeded inputs, through the C ABI.
+
+Tolerances (infinity norm of the difference over the infinity norm of the
+oracle result):
+  FP64 preconditioner applies: 1e-12 per sweep (the scaled-space kernels and
+    the textbook oracle differ only in rounding order, O(nnz_row * eps)).
+  FP32 / FP16-scaled applies vs the oracle's reduced-precision form (same
+    stored values and rounding points, different summation order):
+    2e-5 / 1e-4 (tens of float32 unit roundoffs; FP16 allows a rare
+    one-ulp difference in a stored value).
+  GMRES: iteration count within +-1 of the oracle (MGS vs the GPU's CGS2),
+    true residual <= rtol, solutions agree to what the tolerance allows.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2104_01196_amd as g  # noqa: E402
+from gen import (laplace3d, poisson2d, random_sparse, vardiff3d, elasticity_q1, convdiff2d,  # noqa: E402
+                 config_problem, CSR)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_inf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+MATS = {
+    "rand_long_rows": lambda: random_sparse(700, seed=31, avg_offdiag=6, long_rows=5, long_len=150, diag_only_rows=9),
+    "rand_negdiag": lambda: random_sparse(333, seed=32, avg_offdiag=4, neg_diag_rows=20),
+    "poisson2d_64": lambda: poisson2d(64),
+    "laplace3d_17": lambda: laplace3d(17),
+    "vardiff3d_11": lambda: vardiff3d(11, seed=3),
+    "elasticity_5": lambda: elasticity_q1(5, 5, 5, seed=4),
+    "convdiff_37": lambda: convdiff2d(37, 40.0, 3.9),
+}
+_cache = {}
+
+
+def mat(name):
+    if name not in _cache:
+        A = MATS[name]()
+        _cache[name] = (A, g.DeviceCSR.from_host(A))
+    return _cache[name]
+
+
+def vec(n, seed=0):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+CASES = [  # variant, sweeps, inner, omega
+    (g.FORWARD, 1, 1, 1.0), (g.FORWARD, 2, 3, 0.8), (g.BACKWARD, 1, 2, 1.0), (g.SYMMETRIC, 1, 1, 1.0),
+    (g.SYMMETRIC, 2, 2, 0.9), (g.FORWARD, 3, 0, 0.7), (g.SYMMETRIC, 1, 0, 1.0),
+]
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("variant,sweeps,inner,w", CASES)
+def test_gs2_apply_fp64(name, variant, sweeps, inner, w):
+    A, dA = mat(name)
+    v = vec(A.n, 1)
+    ref = oracle.gs2_apply(A, v, variant, sweeps, inner, w)
+    h = g.gs2_setup(dA, sweeps, inner, w, variant)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    halves = sweeps * (2 if variant == g.SYMMETRIC else 1)
+    assert rel_inf(host(z), ref) <= 1e-12 * halves
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("name", ["rand_long_rows", "elasticity_5", "poisson2d_64"])
+def test_gs2_apply_every_lane_count(name, lanes):
+    A, dA = mat(name)
+    v = vec(A.n, 2)
+    ref = oracle.gs2_apply(A, v, g.SYMMETRIC, 2, 2, 0.9)
+    h = g.gs2_setup(dA, 2, 2, 0.9, g.SYMMETRIC, lanes_per_row=lanes)
+    assert g.gs2_handle_query(h)["lanes_per_row"] == lanes
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), ref) <= 4e-12
+
+
+@pytest.mark.parametrize("name", ["rand_long_rows", "vardiff3d_11", "convdiff_37"])
+@pytest.mark.parametrize("gamma", [0.5, 0.8])
+def test_gs2_inner_damping(name, gamma):
+    A, dA = mat(name)
+    v = vec(A.n, 3)
+    ref = oracle.gs2_apply(A, v, g.SYMMETRIC, 2, 3, 0.9, gamma)
+    h = g.gs2_setup(dA, 2, 3, 0.9, g.SYMMETRIC, inner_damping=gamma)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), ref) <= 4e-12
+
+
+@pytest.mark.parametrize("name", ["rand_negdiag", "poisson2d_64", "elasticity_5"])
+@pytest.mark.parametrize("variant,sweeps,inner,w", [(g.FORWARD, 2, 1, 1.0), (g.SYMMETRIC, 2, 2, 0.8),
+                                                     (g.BACKWARD, 1, 0, 0.7)])
+def test_gs2_compact(name, variant, sweeps, inner, w):
+    A, dA = mat(name)
+    v = vec(A.n, 4)
+    ref = oracle.gs2c_sweep(A, v, np.zeros(A.n), variant, sweeps, inner, w)
+    h = g.gs2_setup(dA, sweeps, inner, w, variant, compact=True)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), ref) <= 1e-12 * sweeps * 2
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("prec,tol", [(g.FP32, 2e-5), (g.FP16_SCALED, 1e-4)])
+@pytest.mark.parametrize("variant,sweeps,inner,w", [(g.FORWARD, 2, 1, 1.0), (g.SYMMETRIC, 1, 2, 0.9),
+                                                     (g.FORWARD, 2, 0, 0.8)])
+def test_gs2_apply_reduced_precision(name, prec, tol, variant, sweeps, inner, w):
+    A, dA = mat(name)
+    v = vec(A.n, 5)
+    try:
+        ref = oracle.gs2_apply_lp(A, v, prec, variant, sweeps, inner, w)
+    except oracle.OracleError as e:
+        assert e.status == oracle.ERR_FP16_RANGE
+        with pytest.raises(g.Gs2Error) as ge:
+            g.gs2_setup(dA, sweeps, inner, w, variant, precision=prec)
+        assert ge.value.status == -7
+        return
+    h = g.gs2_setup(dA, sweeps, inner, w, variant, precision=prec)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), ref) <= tol
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("sweeps,w", [(1, 1.0), (3, 0.7)])
+def test_jr_apply(name, sweeps, w):
+    A, dA = mat(name)
+    v = vec(A.n, 6)
+    ref = oracle.jr_sweep(A, v, np.zeros(A.n), sweeps, w)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.jr_apply(h, sweeps, w, dev(v), z)
+    assert rel_inf(host(z), ref) <= 1e-12 * sweeps
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("variant,sweeps,w", [(g.FORWARD, 1, 1.0), (g.BACKWARD, 1, 1.2), (g.SYMMETRIC, 2, 0.8)])
+def test_trisolve_equals_sequential_gs(name, variant, sweeps, w):
+    A, dA = mat(name)
+    v = vec(A.n, 7)
+    ref = oracle.sor_sweep(A, v, np.zeros(A.n), variant, sweeps, w)
+    h = g.gs2_setup(dA, sweeps, 1, 1.0, g.FORWARD, build_levels=True)
+    q = g.gs2_handle_query(h)
+    assert q["levels_l"] == oracle.levels(A, True)[1] and q["levels_u"] == oracle.levels(A, False)[1]
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs_trisolve_apply(h, variant, w, dev(v), z)
+    assert rel_inf(host(z), ref) <= 1e-11
+
+
+def test_trisolve_requires_levels():
+    A, dA = mat("poisson2d_64")
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    with pytest.raises(g.Gs2Error) as e:
+        g.gs_trisolve_apply(h, g.FORWARD, 1.0, dev(vec(A.n)), z)
+    assert e.value.status == -8
+
+
+def test_deterministic_and_no_alias_state():
+    """Two applies give bitwise-equal results; a different apply in between
+    does not leak state (persistent temporaries are fully rewritten)."""
+    A, dA = mat("laplace3d_17")
+    h = g.gs2_setup(dA, 2, 2, 1.0, g.SYMMETRIC)
+    v1, v2 = dev(vec(A.n, 8)), dev(vec(A.n, 9))
+    z1, z2, z3 = (torch.empty(A.n, dtype=torch.float64, device=DEV) for _ in range(3))
+    g.gs2_apply(h, v1, z1)
+    g.gs2_apply(h, v2, z2)
+    g.gs2_apply(h, v1, z3)
+    assert torch.equal(z1, z3)
+
+
+def test_ragged_and_tiny_sizes():
+    for n in (1, 2, 63, 65, 129):
+        A = random_sparse(n, seed=40 + n, avg_offdiag=min(3, n - 1) if n > 1 else 0)
+        dA = g.DeviceCSR.from_host(A)
+        v = vec(n, n)
+        for variant, sw, inner in [(g.FORWARD, 1, 1), (g.SYMMETRIC, 2, 2)]:
+            ref = oracle.gs2_apply(A, v, variant, sw, inner, 1.0)
+            h = g.gs2_setup(dA, sw, inner, 1.0, variant, build_levels=True)
+            z = torch.empty(n, dtype=torch.float64, device=DEV)
+            g.gs2_apply(h, dev(v), z)
+            assert rel_inf(host(z), ref) <= 1e-12 * sw * 2
+            g.gs_trisolve_apply(h, variant, 1.0, dev(v), z)
+            assert rel_inf(host(z), oracle.sor_sweep(A, v, np.zeros(n), variant, sw, 1.0)) <= 1e-11
+
+
+def test_setup_errors():
+    A = poisson2d(6)
+    # zero diagonal
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    B.val[np.nonzero(B.colind == rows)[0][5]] = 0.0
+    with pytest.raises(g.Gs2Error) as e:
+        g.gs2_setup(g.DeviceCSR.from_host(B), 1, 1, 1.0, g.FORWARD)
+    assert e.value.status == -3
+    # unsorted columns
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    B.colind[[0, 1]] = B.colind[[1, 0]]
+    with pytest.raises(g.Gs2Error) as e:
+        g.gs2_setup(g.DeviceCSR.from_host(B), 1, 1, 1.0, g.FORWARD)
+    assert e.value.status == -2
+    # NaN value
+    B = CSR(A.n, A.rowptr.copy(), A.colind.copy(), A.val.copy())
+    B.val[7] = np.nan
+    with pytest.raises(g.Gs2Error) as e:
+        g.gs2_setup(g.DeviceCSR.from_host(B), 1, 1, 1.0, g.FORWARD)
+    assert e.value.status == -4
+    # FP16 range
+    B = CSR(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([1e-6, 1.0, 1.0, 1e-6]))
+    with pytest.raises(g.Gs2Error) as e:
+        g.gs2_setup(g.DeviceCSR.from_host(B), 1, 1, 1.0, g.FORWARD, precision=g.FP16_SCALED)
+    assert e.value.status == -7
+
+
+# ------------------------------------------------------------------ GMRES
+
+def gmres_pair(A, b, restart, prec, kind, **kw):
+    xo, io = oracle.gmres(A, b, restart=restart, rtol=1e-8, prec=prec, **kw)
+    dA = g.DeviceCSR.from_host(A)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    h = None
+    if kind != g.PREC_NONE:
+        h = g.gs2_setup(dA, kw.get("sweeps", 1), kw.get("inner", 1), kw.get("omega", 1.0),
+                        kw.get("variant", g.FORWARD), precision=kw.get("precision", g.FP64),
+                        build_levels=(kind == g.PREC_GS_TRISOLVE))
+    info = g.gmres_solve(dA, dev(b), x, restart, 1e-8, 10000, kind, h)
+    return xo, io, host(x), info
+
+
+@pytest.mark.parametrize("prec,kind,kw", [
+    ("gs2", g.PREC_GS2, dict(sweeps=1, inner=1)),
+    ("gs2", g.PREC_GS2, dict(variant=g.SYMMETRIC, sweeps=1, inner=1)),
+    ("jr", g.PREC_JR, dict(sweeps=1)),
+    ("jr", g.PREC_JR, dict(sweeps=3)),
+    ("sor", g.PREC_GS_TRISOLVE, dict(sweeps=1)),
+    ("none", g.PREC_NONE, dict()),
+    ("gs2", g.PREC_GS2, dict(sweeps=1, inner=1, precision=g.FP32)),
+    ("gs2", g.PREC_GS2, dict(sweeps=1, inner=1, precision=g.FP16_SCALED)),
+])
+def test_gmres_config1(prec, kind, kw):
+    p = config_problem(1)
+    A, b = p["A"], p["b"]
+    xo, io, x, info = gmres_pair(A, b, 30, prec, kind, **kw)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    r = np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b)
+    assert r <= 1e-8 and abs(r - info["relres"]) <= 1e-3 * r
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-5
+
+
+@pytest.mark.parametrize("variant,inner", [(g.FORWARD, 1), (g.FORWARD, 3), (g.SYMMETRIC, 2)])
+def test_gmres_laplace3d_reduced(variant, inner):
+    p = config_problem(2, size=24)
+    A, b = p["A"], p["b"]
+    xo, io, x, info = gmres_pair(A, b, 50, "gs2", g.PREC_GS2, variant=variant, sweeps=2, inner=inner)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1e-8
+
+
+def test_gmres_status_paths():
+    p = config_problem(1, size=16)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 5, 1e-12, 7, g.PREC_GS2, h)
+    _, io = oracle.gmres(A, b, restart=5, rtol=1e-12, maxit=7, prec="gs2")
+    assert info["status"] == 1 and info["iterations"] == 7 == io["iterations"] and not info["converged"]
+    x.zero_()
+    info = g.gmres_solve(dA, torch.zeros(A.n, dtype=torch.float64, device=DEV), x, 5, 1e-8, 50, g.PREC_GS2, h)
+    assert info["converged"] and info["iterations"] == 0 and not host(x).any()
+    bn = b.copy()
+    bn[3] = np.inf
+    with pytest.raises(g.Gs2Error) as e:
+        g.gmres_solve(dA, dev(bn), x, 5, 1e-8, 50, g.PREC_GS2, h)
+    assert e.value.status == -4
+    # initial guess honoured: starting from the solution needs no iteration
+    xs = torch.as_tensor(p["x_true"], device=DEV).clone()
+    info = g.gmres_solve(dA, dev(b), xs, 5, 1e-8, 50, g.PREC_GS2, h)
+    assert info["converged"] and info["iterations"] == 0
+
+
+def test_gmres_restart_lengths_and_prec_reuse():
+    """One handle serves solves with different restart lengths (workspace is
+    re-cached) and repeated solves give bitwise-equal results."""
+    p = config_problem(1, size=32)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC)
+    xs = []
+    for m in (10, 40, 10):
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        info = g.gmres_solve(dA, dev(b), x, m, 1e-8, 5000, g.PREC_GS2, h)
+        _, io = oracle.gmres(A, b, restart=m, rtol=1e-8, prec="gs2", variant=g.SYMMETRIC)
+        assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1
+        xs.append(host(x))
+    assert np.array_equal(xs[0], xs[2])
+
+
+@pytest.mark.slow
+def test_full_size_laplace3d_apply_and_solve():
+    """128^3 Laplacian (the benchmark workload): one GS2(2,1) apply compared
+    element by element with the oracle, and the GPU solve checked through
+    properties that hold at any size (true residual recomputed on the host)."""
+    p = config_problem(2)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    v = vec(A.n, 11)
+    for prec, tol in [(g.FP64, 2e-12), (g.FP32, 2e-5), (g.FP16_SCALED, 1e-4)]:
+        h = g.gs2_setup(dA, 2, 1, 1.0, g.FORWARD, precision=prec)
+        z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+        g.gs2_apply(h, dev(v), z)
+        ref = oracle.gs2_apply(A, v, g.FORWARD, 2, 1, 1.0) if prec == g.FP64 else \
+            oracle.gs2_apply_lp(A, v, prec, g.FORWARD, 2, 1, 1.0)
+        assert rel_inf(host(z), ref) <= tol
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        info = g.gmres_solve(dA, dev(b), x, 50, 1e-8, 5000, g.PREC_GS2, h)
+        assert info["converged"]
+        xh = host(x)
+        assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
+        assert np.linalg.norm(xh - p["x_true"]) / np.linalg.norm(p["x_true"]) <= 1e-4
