@@ -78,6 +78,9 @@ typedef struct gs2_options {
     int lanes_per_row;    /* 0 = automatic; else 1,2,4,...,64 (forced)       */
     int rhs_per_item;     /* batched: right-hand sides per work item, 0 =    */
                           /* autotuned over {4,2,1} dividing nrhs            */
+    int orthogonalization; /* gmres_solve with this handle: 0 = CGS2 with    */
+                           /* delayed reorthogonalisation (two passes over   */
+                           /* the basis per step, default), 1 = CGS2 (four)  */
 } gs2_options;
 
 typedef struct gs2_solve_info {

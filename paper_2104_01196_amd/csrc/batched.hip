@@ -27,7 +27,13 @@ namespace gs2 {
 constexpr int BT = 512;        // threads per workgroup of the persistent solver
 constexpr int BNW = BT / WAVE; // wavefronts per workgroup
 constexpr int BMAXM = 32;      // longest restart of the batched solver
-constexpr int KC = 8;          // Krylov vectors per chunk of a multi-dot
+// Krylov vectors per chunk of a multi-dot: 16 accumulators per thread
+template <int R>
+constexpr int kc_of()
+{
+    return 8 / R;
+}
+constexpr int RED_STRIDE = 20; // >= (16/R + 1) * R for R in {1, 2, 4}
 
 struct BSys {
     int64_t n, nslices;
@@ -260,7 +266,8 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
                            double *out, double *red)
 {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    const int stride_red = (KC + 1) * R;
+    constexpr int KC = kc_of<R>();
+    const int stride_red = RED_STRIDE;
     for (int k0 = 0; k0 < nk || (k0 == 0 && with_norm); k0 += KC) {
         const int kc = min(KC, nk - k0);
         const bool nrm = with_norm && k0 == 0;
@@ -340,13 +347,13 @@ __device__ void b_update(int64_t n, const double *V, int64_t ldv, int nk, const 
 }
 
 struct BLds {
-    double *red, *hA, *hB, *H, *cs, *sn, *g, *y, *bnorm, *beta, *inv, *wn2, *nrm;
+    double *red, *hA, *hB, *H, *cs, *sn, *g, *y, *bnorm, *beta, *inv, *wn2, *nrm, *col;
     int *done, *kk, *iters, *restarts, *status, *conv, *flag;
 };
 
 __host__ __device__ inline size_t blds_bytes(int m, int R)
 {
-    const size_t d = (size_t)BNW * (KC + 1) * R + 2 * (size_t)(m + 2) * R + (size_t)(m + 1) * m * R +
+    const size_t d = (size_t)BNW * RED_STRIDE + 3 * (size_t)(m + 2) * R + (size_t)(m + 1) * m * R +
                      3 * (size_t)m * R + (size_t)(m + 2) * R + 5 * (size_t)R;
     return d * sizeof(double) + (6 * (size_t)R + 2) * sizeof(int) + 64;
 }
@@ -355,7 +362,8 @@ __device__ inline BLds blds_carve(double *base, int m, int R)
 {
     BLds L;
     double *p = base;
-    L.red = p; p += BNW * (KC + 1) * R;
+    L.red = p; p += BNW * RED_STRIDE;
+    L.col = p; p += (m + 2) * R; // Givens work column per right-hand side
     L.hA = p; p += (m + 2) * R;
     L.hB = p; p += (m + 2) * R;
     L.H = p; p += (m + 1) * m * R;
@@ -474,7 +482,7 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
             __syncthreads();
             if (t < R && !L.done[t]) {
                 const int r = t;
-                double col[BMAXM + 1];
+                double *col = L.col + r * (m + 2);
                 for (int k = 0; k <= j; ++k) col[k] = L.hA[k * R + r] + L.hB[k * R + r];
                 const double hn = sqrt(L.nrm[r]);
                 const double wn0 = sqrt(L.wn2[r]);

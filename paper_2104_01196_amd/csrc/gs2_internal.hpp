@@ -127,6 +127,7 @@ struct Handle {
     int sweeps = 1, inner = 1, variant = GS2_FORWARD, precision = GS2_FP64;
     double omega = 1.0, gamma = 1.0;
     int compact = 0;
+    int orth = 0;        // GMRES orthogonalisation (0 delayed CGS2, 1 CGS2)
     int block_waves = 4; // wavefronts per workgroup in the sweep kernels
     Sell L, U;
     double *sl = nullptr, *sr = nullptr; // scaling vectors (float64)

@@ -29,6 +29,9 @@ struct GState {
     double hA[MAXM + 2], hB[MAXM + 2], nrm[2];
     double g[MAXM + 2], cs[MAXM], sn[MAXM], y[MAXM];
     double H[(MAXM + 1) * MAXM]; // H[k * MAXM + col], upper triangle R after rotations
+    // delayed CGS2: scalars of the current step and the tentative column
+    double bb, dd, wn2, nu, inv_alpha, e;
+    double ht[MAXM + 2];
 };
 
 struct GHeader {
@@ -264,6 +267,15 @@ __global__ __launch_bounds__(KT) void k_reduce(const double *__restrict__ part, 
         case 0: st->hA[k] = s; break;
         case 1: st->hB[k] = s; break;
         case 2: st->nrm[k] = s; break;
+        case 3: { // delayed CGS2 pass-1 sums: a[0..j), c[0..j), u.u, u.w, w.w
+            const int j = st->j;
+            if (k < j) st->hA[k] = s;
+            else if (k < 2 * j) st->hB[k - j] = s;
+            else if (k == 2 * j) st->bb = s;
+            else if (k == 2 * j + 1) st->dd = s;
+            else st->wn2 = s;
+            break;
+        }
         case 8: st->bnorm = sqrt(s); break;
         case 9: st->beta = sqrt(s); break;
         }
@@ -314,6 +326,259 @@ __global__ void k_givens(GState *__restrict__ st)
 
 // v_{j+1} *= 1/h_{j+1,j}  (skipped once the cycle has stopped)
 __global__ void k_scale_next(int64_t n, double *__restrict__ V, int64_t ldv, const GState *__restrict__ st)
+{
+    if (st->done) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) V[(int64_t)st->j * ldv + i] *= st->inv;
+}
+
+// ------------------------------------------------------------ delayed CGS2
+//
+// Two passes over V per Arnoldi step instead of four.  Step j starts from the
+// tentative vector u = V[j]: the previous step's projected vector, normalised
+// but not yet reorthogonalised.  Pass 1, fused with w = A z_j, forms
+// a = Q^T u, c = Q^T w, u.u, u.w and w.w (Q = V[0..j)) in one read of Q.
+// Then q_j = (u - Q a)/alpha with alpha^2 = u.u - |a|^2, the coefficient of
+// w on q_j is e = (u.w - a.c)/alpha, and the previous step's tentative
+// Hessenberg column is corrected now that its vector's reorthogonalisation
+// is known: column j-1 = [ht + nu a; nu alpha].  Pass 2 writes q_j and the
+// next tentative vector w' = w - Q c - e q_j in one read of Q.  The
+// convergence estimate of step j uses the tentative column [c, e; ||w'||],
+// equal to the final column in exact arithmetic; when the cycle stops the
+// tentative column is committed as it stands.
+
+template <int K>
+__global__ __launch_bounds__(KT) void k_spmv_dot2(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                  const double *__restrict__ z, double *__restrict__ w,
+                                                  const double *__restrict__ V, int64_t ldv,
+                                                  const GState *__restrict__ st, double *__restrict__ part, int nb)
+{
+    __shared__ double wl[RB];
+    __shared__ double red[(2 * MAXM + 3) * 4];
+    if (st->done) return;
+    const int j = st->j;
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int t = threadIdx.x, q = t & (K - 1);
+    constexpr int RPP = KT / K;
+    for (int pass = 0; pass < RB / RPP; ++pass) {
+        const int lr = pass * RPP + t / K;
+        const int64_t row = r0 + lr;
+        double acc = 0.0;
+        if (row < n) {
+            const int b = rp[row], e = rp[row + 1];
+            for (int p = b + q; p < e; p += K) acc += va[p] * z[ci[p]];
+        }
+        acc = group_sum<K>(acc);
+        if (q == 0) {
+            wl[lr] = acc;
+            if (row < n) w[row] = acc;
+        }
+    }
+    __syncthreads();
+    const int wv = t / WAVE, ln = t & (WAVE - 1);
+    const double *__restrict__ u = V + (int64_t)j * ldv;
+    double wr[RB / KT], ur[RB / KT];
+#pragma unroll
+    for (int s = 0; s < RB / KT; ++s) {
+        const int64_t row = r0 + t + s * KT;
+        wr[s] = row < n ? wl[t + s * KT] : 0.0;
+        ur[s] = row < n ? u[row] : 0.0;
+    }
+    for (int k = 0; k < j; ++k) {
+        const double *__restrict__ vk = V + (int64_t)k * ldv;
+        double sa = 0.0, sc = 0.0;
+#pragma unroll
+        for (int s = 0; s < RB / KT; ++s) {
+            const int64_t row = r0 + t + s * KT;
+            if (row < n) {
+                const double x = vk[row];
+                sa += x * ur[s];
+                sc += x * wr[s];
+            }
+        }
+        sa = wave_sum(sa);
+        sc = wave_sum(sc);
+        if (ln == 0) {
+            red[k * 4 + wv] = sa;
+            red[(j + k) * 4 + wv] = sc;
+        }
+    }
+    double sb = 0.0, sd = 0.0, sw = 0.0;
+#pragma unroll
+    for (int s = 0; s < RB / KT; ++s) {
+        sb += ur[s] * ur[s];
+        sd += ur[s] * wr[s];
+        sw += wr[s] * wr[s];
+    }
+    sb = wave_sum(sb);
+    sd = wave_sum(sd);
+    sw = wave_sum(sw);
+    if (ln == 0) {
+        red[(2 * j) * 4 + wv] = sb;
+        red[(2 * j + 1) * 4 + wv] = sd;
+        red[(2 * j + 2) * 4 + wv] = sw;
+    }
+    __syncthreads();
+    for (int k = t; k < 2 * j + 3; k += KT)
+        part[(int64_t)k * nb + blockIdx.x] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+}
+
+// Apply the committed rotations 0..jc-1 to col (jc+2 entries), form rotation
+// jc, store column jc of R and advance the residual recurrence g.
+__device__ bool commit_column(GState *st, double *col, int jc)
+{
+    for (int k = 0; k < jc; ++k) {
+        const double a = st->cs[k] * col[k] + st->sn[k] * col[k + 1];
+        col[k + 1] = -st->sn[k] * col[k] + st->cs[k] * col[k + 1];
+        col[k] = a;
+    }
+    const double rho = hypot(col[jc], col[jc + 1]);
+    if (!isfinite(rho)) {
+        st->status = GS2_ERR_NONFINITE;
+        return false;
+    }
+    if (rho == 0.0) {
+        st->status = GS2_BREAKDOWN;
+        return false;
+    }
+    st->cs[jc] = col[jc] / rho;
+    st->sn[jc] = col[jc + 1] / rho;
+    col[jc] = rho;
+    for (int k = 0; k <= jc; ++k) st->H[k * MAXM + jc] = col[k];
+    st->g[jc + 1] = -st->sn[jc] * st->g[jc];
+    st->g[jc] = st->cs[jc] * st->g[jc];
+    return true;
+}
+
+// Between the passes: reorthogonalisation scalars of u, correction and
+// commit of column j-1, the new tentative column j (single thread).
+__global__ void k_dcgs_scalar(GState *__restrict__ st)
+{
+    if (threadIdx.x != 0 || st->done) return;
+    const int j = st->j;
+    double col[MAXM + 2];
+    if (j == 0) {
+        st->inv_alpha = 1.0;
+        st->e = st->dd;
+        st->ht[0] = st->dd;
+        return;
+    }
+    double aa = 0.0, ac = 0.0;
+    for (int k = 0; k < j; ++k) {
+        aa += st->hA[k] * st->hA[k];
+        ac += st->hA[k] * st->hB[k];
+    }
+    const double a2 = st->bb - aa;
+    if (!isfinite(a2)) {
+        st->status = GS2_ERR_NONFINITE;
+        st->done = 1;
+        st->kk = j - 1;
+        return;
+    }
+    if (!(a2 > 0.0)) { // u fell into span(Q): end the cycle on the tentative column j-1
+        for (int k = 0; k < j; ++k) col[k] = st->ht[k];
+        col[j] = st->nu;
+        st->kk = commit_column(st, col, j - 1) ? j : j - 1;
+        st->done = 1;
+        return;
+    }
+    const double alpha = sqrt(a2);
+    for (int k = 0; k < j; ++k) col[k] = st->ht[k] + st->nu * st->hA[k];
+    col[j] = st->nu * alpha;
+    if (!commit_column(st, col, j - 1)) {
+        st->kk = j - 1;
+        st->done = 1;
+        return;
+    }
+    st->inv_alpha = 1.0 / alpha;
+    st->e = (st->dd - ac) / alpha;
+    for (int k = 0; k < j; ++k) st->ht[k] = st->hB[k];
+    st->ht[j] = st->e;
+}
+
+// Pass 2: q_j = (u - Q a)/alpha over u's slot, w' = w - Q c - e q_j into
+// V[j+1], partial ||w'||^2.
+__global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restrict__ V, int64_t ldv,
+                                                    const GState *__restrict__ st, const double *__restrict__ w,
+                                                    double *__restrict__ part)
+{
+    __shared__ double as[MAXM + 2], cs_[MAXM + 2], red[4];
+    if (st->done) return;
+    const int j = st->j;
+    for (int k = threadIdx.x; k < j; k += KT) {
+        as[k] = st->hA[k];
+        cs_[k] = st->hB[k];
+    }
+    __syncthreads();
+    const double ia = st->inv_alpha, e = st->e;
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    double s = 0.0;
+    double *__restrict__ u = V + (int64_t)j * ldv;
+    double *__restrict__ wn = V + (int64_t)(j + 1) * ldv;
+#pragma unroll
+    for (int q = 0; q < RB / KT; ++q) {
+        const int64_t row = r0 + threadIdx.x + q * KT;
+        if (row >= n) continue;
+        double aq = u[row], aw = w[row];
+        for (int k = 0; k < j; ++k) {
+            const double vk = V[(int64_t)k * ldv + row];
+            aq -= as[k] * vk;
+            aw -= cs_[k] * vk;
+        }
+        const double qv = aq * ia;
+        const double wp = aw - e * qv;
+        u[row] = qv;
+        wn[row] = wp;
+        s += wp * wp;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ||w'||, tentative rotation of column j and the stopping decision.
+__global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
+{
+    __shared__ double red[4];
+    if (st->done) return;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += KT) s += part[b];
+    s = block_sum(s, red);
+    if (threadIdx.x != 0) return;
+    const int j = st->j;
+    const double nu = sqrt(s);
+    st->nu = nu;
+    double col[MAXM + 2];
+    for (int k = 0; k <= j; ++k) col[k] = st->ht[k];
+    col[j + 1] = nu;
+    for (int k = 0; k < j; ++k) {
+        const double a = st->cs[k] * col[k] + st->sn[k] * col[k + 1];
+        col[k + 1] = -st->sn[k] * col[k] + st->cs[k] * col[k + 1];
+        col[k] = a;
+    }
+    const double rho = hypot(col[j], col[j + 1]);
+    if (!isfinite(rho) || !isfinite(nu)) {
+        st->status = GS2_ERR_NONFINITE;
+        st->done = 1;
+        st->kk = j;
+        return;
+    }
+    const double est = rho > 0.0 ? fabs(col[j + 1] / rho * st->g[j]) : 0.0;
+    const bool breakdown = nu <= 1e-14 * sqrt(st->wn2);
+    st->kk = j + 1;
+    if (est <= st->rtol * st->bnorm || breakdown || j + 1 >= st->maxsteps) {
+        for (int k = 0; k <= j; ++k) col[k] = st->ht[k];
+        col[j + 1] = nu;
+        if (!commit_column(st, col, j)) st->kk = j;
+        st->done = 1;
+    } else {
+        st->inv = 1.0 / nu;
+        st->j = j + 1;
+    }
+}
+
+// V[j] *= 1/||w'|| of the previous step (the tentative vector's scale)
+__global__ void k_normalize(int64_t n, double *__restrict__ V, int64_t ldv, const GState *__restrict__ st)
 {
     if (st->done) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -473,8 +738,10 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         info->converged = 1;
         return GS2_OK;
     }
-    const bool none = kind == GS2_PREC_NONE;
-    double *Zb = none ? W->V : W->Z; // unpreconditioned: z_j = v_j, no copy
+    // orthogonalisation: 0 = delayed CGS2 (default), 1 = CGS2
+    const int orth = P ? P->h.orth : 0;
+    // z_j is always a copy: the delayed variant rewrites v_j after z_j was formed
+    double *Zb = W->Z;
     int total = 0, cycles = 0, status = GS2_OK;
     bool have_prev = false;
     // algorithmic bytes: CSR SpMV with A, and one pass over nk Krylov vectors
@@ -512,7 +779,37 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
             const double *vj = W->V + (int64_t)j * n;
             double *zj = Zb + (int64_t)j * n;
             const double vb = 8.0 * n * (j + 1);
-            if (!none) GS2_TRY(precondition(kind, P, vj, zj, n, st, s));
+            if (orth == 0) { // delayed CGS2
+                if (j > 0) {
+                    Prof pr(s, PK_SCALE, 16.0 * n);
+                    k_normalize<<<gE, 256, 0, s>>>(n, W->V, n, st);
+                }
+                GS2_TRY(precondition(kind, P, vj, zj, n, st, s));
+                {
+                    Prof pr(s, PK_SPMV_DOT, spmv_b + vb);
+                    GS2_SPMV_DISPATCH(K, k_spmv_dot2, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st,
+                                      W->part, nb);
+                }
+                {
+                    Prof pr(s, PK_REDUCE, red_b * (2 * j + 3));
+                    k_reduce<<<2 * j + 3, KT, 0, s>>>(W->part, nb, st, 3, 0, 2 * j + 3);
+                }
+                {
+                    Prof pr(s, PK_GIVENS, 0.0);
+                    k_dcgs_scalar<<<1, 64, 0, s>>>(st);
+                }
+                {
+                    Prof pr(s, PK_CGS, 8.0 * n * (j + 4));
+                    k_dcgs_update<<<gN, KT, 0, s>>>(n, W->V, n, st, W->w, W->part);
+                }
+                {
+                    Prof pr(s, PK_GIVENS, red_b);
+                    k_dcgs_finish<<<1, KT, 0, s>>>(W->part, nb, st);
+                }
+                GS2_TRY_HIP(hipGetLastError());
+                continue;
+            }
+            GS2_TRY(precondition(kind, P, vj, zj, n, st, s));
             {   // w = A z_j, hA = V^T w, ||w||^2
                 Prof pr(s, PK_SPMV_DOT, spmv_b + vb);
                 GS2_SPMV_DISPATCH(K, k_spmv_dot, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st, W->part,

@@ -431,6 +431,7 @@ void gs2_default_options(gs2_options *opt)
     opt->autotune = 1;
     opt->lanes_per_row = 0;
     opt->rhs_per_item = 0;
+    opt->orthogonalization = 0;
 }
 
 int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
@@ -447,6 +448,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     gs2_default_options(&o);
     if (opt) o = *opt;
     if (o.precision < GS2_FP64 || o.precision > GS2_FP16_SCALED) return GS2_ERR_ARG;
+    if (o.orthogonalization < 0 || o.orthogonalization > 1) return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;
     if (!H) return GS2_ERR_NOMEM;
@@ -458,6 +460,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     h.omega = damping;
     h.gamma = o.inner_damping;
     h.compact = o.compact ? 1 : 0;
+    h.orth = o.orthogonalization;
     h.precision = o.precision;
     hipStream_t s = (hipStream_t)stream;
     int st = GS2_ERR_HIP;

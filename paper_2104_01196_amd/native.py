@@ -37,7 +37,7 @@ class CsrDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("inner_damping", C.c_double), ("compact", C.c_int),
                 ("build_levels", C.c_int), ("autotune", C.c_int), ("lanes_per_row", C.c_int),
-                ("rhs_per_item", C.c_int)]
+                ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -164,8 +164,10 @@ class Handle:
 
 
 def gs2_setup(A: DeviceCSR, sweeps=1, inner=1, damping=1.0, variant=FORWARD, precision=FP64, inner_damping=1.0,
-              compact=False, build_levels=False, autotune=True, lanes_per_row=0, stream=None) -> Handle:
-    opt = Options(precision, inner_damping, int(compact), int(build_levels), int(autotune), lanes_per_row)
+              compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0,
+              stream=None) -> Handle:
+    opt = Options(precision, inner_damping, int(compact), int(build_levels), int(autotune), lanes_per_row, 0,
+                  orthogonalization)
     out = C.c_void_p()
     d = A.desc()
     st = lib().gs2_setup(C.byref(d), sweeps, inner, damping, variant, C.byref(opt), _stream(stream), C.byref(out))

@@ -277,6 +277,26 @@ def test_gmres_laplace3d_reduced(variant, inner):
     assert np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b) <= 1e-8
 
 
+@pytest.mark.parametrize("orth", [0, 1])
+@pytest.mark.parametrize("cfg,size,m,kw", [(1, 64, 30, dict(variant=g.SYMMETRIC, sweeps=1, inner=1)),
+                                          (2, 20, 50, dict(variant=g.FORWARD, sweeps=2, inner=1)),
+                                          (1, 40, 8, dict(variant=g.FORWARD, sweeps=1, inner=2))])
+def test_gmres_orthogonalization_variants(orth, cfg, size, m, kw):
+    """Delayed CGS2 (two passes over the basis) and CGS2 (four) both match
+    the oracle's MGS iteration count within one, also with short restarts."""
+    p = config_problem(cfg, size=size)
+    A, b = p["A"], p["b"]
+    xo, io = oracle.gmres(A, b, restart=m, rtol=1e-8, prec="gs2", **kw)
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, kw["sweeps"], kw["inner"], 1.0, kw["variant"], orthogonalization=orth)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, m, 1e-8, 20000, g.PREC_GS2, h)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    xh = host(x)
+    assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) <= 1e-5
+
+
 def test_gmres_status_paths():
     p = config_problem(1, size=16)
     A, b = p["A"], p["b"]
