@@ -60,6 +60,7 @@ extern "C" {
 #define GS2_PREC_GS2 1
 #define GS2_PREC_JR 2
 #define GS2_PREC_GS_TRISOLVE 3
+#define GS2_PREC_MTGS 4
 
 typedef struct gs2_csr {
     int64_t n;             /* rows = columns, 0 <= n < 2^31               */
@@ -73,7 +74,8 @@ typedef struct gs2_options {
     int precision;        /* GS2_FP64 (default) / GS2_FP32 / GS2_FP16_SCALED */
     double inner_damping; /* gamma of Section 4 (default 1.0)                */
     int compact;          /* 1: compact form eq. (two-stage-3) (default 0)   */
-    int build_levels;     /* 1: build level sets for gs_trisolve_apply       */
+    int build_levels;     /* 1: build level sets (gs_trisolve_apply) and the */
+                          /* multicolor ordering (mtgs_apply)                */
     int autotune;         /* 1: time candidate schedules at setup (default)  */
     int lanes_per_row;    /* 0 = automatic; else 1,2,4,...,64 (forced)       */
     int rhs_per_item;     /* batched: right-hand sides per work item, 0 =    */
@@ -141,6 +143,18 @@ int jr_apply(gs2_handle *h, int sweeps, double damping, const double *v, double 
 int gs_trisolve_apply(gs2_handle *h, int variant, double damping, const double *v, double *z, void *stream);
 
 /*
+ * Multicolor Gauss-Seidel / SOR (Section 6, multi-threaded Gauss-Seidel):
+ * rows are colored greedily (first fit, natural order, symmetrised pattern)
+ * so that rows of one color are uncoupled; the handle's `sweeps` sweeps from
+ * x = 0 visit the colors in ascending (forward), descending (backward) or
+ * both (symmetric) order, updating the rows of a color in parallel with
+ * x_i = (1-w) x_i + w (v_i - sum_{j != i} a_ij x_j) / a_ii.  Equals
+ * sequential GS/SOR on the color-permuted matrix.  Requires build_levels = 1
+ * (else GS2_ERR_NO_LEVELS).  Asynchronous, no allocation.
+ */
+int mtgs_apply(gs2_handle *h, int variant, double damping, const double *v, double *z, void *stream);
+
+/*
  * Restarted flexible GMRES(restart), right-preconditioned, all Krylov
  * arithmetic in float64 (Arnoldi by classical Gram-Schmidt with one
  * reorthogonalisation, Givens rotations on the device, true residual at the
@@ -156,6 +170,19 @@ int gs_trisolve_apply(gs2_handle *h, int variant, double damping, const double *
  */
 int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit, int prec_kind,
                 gs2_handle *prec, gs2_solve_info *info, void *stream);
+
+/*
+ * Preconditioned conjugate gradients in float64 for symmetric positive
+ * definite A (the Krylov solver of the paper's SPD experiments, Sections 8
+ * and 9), normally with a GS2_SYMMETRIC handle (the symmetric two-stage
+ * operator is symmetric for symmetric A).  Same arguments and conventions as
+ * gmres_solve without the restart length; iterations counts products A p.
+ * The recurrence residual stops the iteration, the true residual is then
+ * checked and the iteration restarts from it if it has drifted above rtol.
+ * Synchronises `stream` once per chunk of iterations.
+ */
+int cg_solve(const gs2_csr *A, const double *b, double *x, double rtol, int maxit, int prec_kind, gs2_handle *prec,
+             gs2_solve_info *info, void *stream);
 
 /* Free a handle (NULL is ignored).  Synchronises the device. */
 void gs2_destroy(gs2_handle *h);

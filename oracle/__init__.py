@@ -8,7 +8,7 @@ module only marshals numpy arrays through ctypes.
 
 Parity status per function (what pins it lives in tests/test_oracle_*.py):
   spmv, gs2_apply / gs2_sweep, jr_sweep, sor_sweep, levels, gmres,
-  round_f16, gs2_apply_lp (FP32 / FP16-scaled), gs2c_sweep (compact form):
+  round_f16, gs2_apply_lp (FP32 / FP16-scaled), gs2c_sweep (compact form), pcg:
   all pinned.  inner_residuals: pinned only by its n_j -> depth limit.
 """
 from __future__ import annotations
@@ -26,7 +26,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-shared", "-fPIC"]
 
 FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
-PREC_NONE, PREC_GS2, PREC_JR, PREC_SOR = 0, 1, 2, 3
+PREC_NONE, PREC_GS2, PREC_JR, PREC_SOR, PREC_MTGS = 0, 1, 2, 3, 4
+_PREC = {"none": PREC_NONE, "gs2": PREC_GS2, "jr": PREC_JR, "sor": PREC_SOR, "mtgs": PREC_MTGS}
 FP64, FP32, FP16S = 0, 1, 2
 OK, ERR_ARG, ERR_ZERO_DIAG, ERR_NONFINITE, ERR_NOMEM, ERR_FP16_RANGE = 0, -1, -3, -4, -5, -7
 NOT_CONVERGED, BREAKDOWN = 1, 2
@@ -76,6 +77,9 @@ def lib():
         L.or_gs2_apply_lp.argtypes = csr + [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _f64p, _f64p]
         L.or_gmres.argtypes = csr + [_f64p, _f64p, C.c_int, C.c_double, C.c_int, C.POINTER(_Prec), C.c_int,
                                      C.POINTER(_Info), C.c_void_p]
+        L.or_pcg.argtypes = csr + [_f64p, _f64p, C.c_double, C.c_int, C.POINTER(_Prec), C.POINTER(_Info)]
+        L.or_colors.argtypes = [C.c_int, _i32p, _i32p, _i32p]
+        L.or_mtgs_sweep.argtypes = csr + [C.c_int, C.c_int, C.c_double, _f64p, _f64p]
         _lib = L
     return _lib
 
@@ -153,6 +157,22 @@ def levels(A, lower=True):
     return lv, nlev
 
 
+def colors(A):
+    """Greedy first-fit coloring in natural order on the symmetrised pattern."""
+    c = np.empty(A.n, np.int32)
+    ncol = lib().or_colors(int(A.n), np.ascontiguousarray(A.rowptr, np.int32),
+                           np.ascontiguousarray(A.colind, np.int32), c)
+    _chk(ncol)
+    return c, ncol
+
+
+def mtgs_sweep(A, b, x0, variant=FORWARD, sweeps=1, omega=1.0):
+    """Multicolor Gauss-Seidel / SOR sweeps from x0."""
+    x = _vec(x0).copy()
+    _chk(lib().or_mtgs_sweep(*_csr(A), variant, sweeps, omega, _vec(b), x))
+    return x
+
+
 def inner_residuals(A, r, inner, omega=1.0):
     out = np.empty(inner + 1)
     _chk(lib().or_inner_residuals(*_csr(A), inner, omega, _vec(r), out))
@@ -178,7 +198,7 @@ def gmres(A, b, x0=None, restart=30, rtol=1e-8, maxit=10000, prec="none", varian
     status, seconds (wall time of the solve, setup included), and history
     (relative residual estimates) when requested.
     """
-    kind = {"none": PREC_NONE, "gs2": PREC_GS2, "jr": PREC_JR, "sor": PREC_SOR}[prec]
+    kind = _PREC[prec]
     P = _Prec(kind, variant, sweeps, inner, omega, gamma, precision, 1 if compact else 0)
     info = _Info()
     x = np.zeros(A.n) if x0 is None else _vec(x0).copy()
@@ -192,3 +212,17 @@ def gmres(A, b, x0=None, restart=30, rtol=1e-8, maxit=10000, prec="none", varian
     if history:
         out["history"] = hist[: info.iterations + 1]
     return x, out
+
+
+def pcg(A, b, x0=None, rtol=1e-8, maxit=10000, prec="none", variant=SYMMETRIC, sweeps=1, inner=1, omega=1.0,
+        gamma=1.0, precision=FP64, compact=False):
+    """Preconditioned conjugate gradients.  Returns (x, info dict)."""
+    kind = _PREC[prec]
+    P = _Prec(kind, variant, sweeps, inner, omega, gamma, precision, 1 if compact else 0)
+    info = _Info()
+    x = np.zeros(A.n) if x0 is None else _vec(x0).copy()
+    t0 = time.perf_counter()
+    lib().or_pcg(*_csr(A), _vec(b), x, rtol, maxit, C.byref(P), C.byref(info))
+    dt = time.perf_counter() - t0
+    return x, {"iterations": info.iterations, "restarts": info.restarts, "relres": info.relres,
+               "converged": bool(info.converged), "status": info.status, "seconds": dt}

@@ -31,6 +31,7 @@
 #define OR_PREC_GS2 1
 #define OR_PREC_JR 2
 #define OR_PREC_SOR 3
+#define OR_PREC_MTGS 4
 
 #define OR_FP64 0
 #define OR_FP32 1
@@ -50,6 +51,9 @@ typedef struct {
     const int32_t *rp, *ci;
     const double *va;
 } or_csr;
+
+int or_mtgs_sweep(int n, const int32_t *rp, const int32_t *ci, const double *va, int variant, int sweeps, double w,
+                  const double *b, double *x);
 
 /* ------------------------------------------------------------------ basics */
 
@@ -536,6 +540,9 @@ static int prec_apply(prec_ctx *C, const double *v, double *z)
     case OR_PREC_SOR:
         memset(z, 0, sizeof(double) * (size_t)n);
         return or_sor_sweep(n, A->rp, A->ci, A->va, P->variant, P->sweeps, P->omega, v, z);
+    case OR_PREC_MTGS:
+        memset(z, 0, sizeof(double) * (size_t)n);
+        return or_mtgs_sweep(n, A->rp, A->ci, A->va, P->variant, P->sweeps, P->omega, v, z);
     }
     return OR_ERR_ARG;
 }
@@ -665,6 +672,166 @@ done:
     if (info->converged) status = OR_OK;
     info->status = status;
     free(V); free(Z); free(w); free(H); free(cs); free(sn); free(g); free(y); free(hc);
+    if (C.have_scaled) { scaled_free(&C.S); free(C.work); }
+    return status;
+}
+
+/* ------------------------------------------------------- multicolor GS
+ *
+ * Multicolor Gauss-Seidel (Section 6, multi-threaded Gauss-Seidel): rows get
+ * colors such that two rows of one color are never coupled (a_ij = a_ji = 0);
+ * colors are then swept one after the other and the rows of a color are
+ * independent.  Coloring: greedy first fit in natural row order on the
+ * symmetrised pattern (row i takes the smallest color not used by any
+ * earlier row j < i with a_ij != 0 or a_ji != 0).  Returns the color count.
+ */
+int or_colors(int n, const int32_t *rp, const int32_t *ci, int32_t *color)
+{
+    /* transpose pattern to see a_ji */
+    int32_t *tp = calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *tc = malloc(sizeof(int32_t) * ((size_t)rp[n] + 1));
+    int32_t *fill = malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *mark = malloc(sizeof(int32_t) * ((size_t)n + 2));
+    if (!tp || !tc || !fill || !mark) { free(tp); free(tc); free(fill); free(mark); return OR_ERR_NOMEM; }
+    for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) tp[ci[k] + 1]++;
+    for (int i = 0; i < n; ++i) tp[i + 1] += tp[i];
+    for (int i = 0; i < n; ++i) fill[i] = tp[i];
+    for (int i = 0; i < n; ++i)
+        for (int k = rp[i]; k < rp[i + 1]; ++k) tc[fill[ci[k]]++] = i;
+    for (int c = 0; c <= n; ++c) mark[c] = -1;
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] < i) mark[color[ci[k]]] = i;
+        for (int k = tp[i]; k < tp[i + 1]; ++k)
+            if (tc[k] < i) mark[color[tc[k]]] = i;
+        int c = 0;
+        while (mark[c] == i) ++c;
+        color[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(tp); free(tc); free(fill); free(mark);
+    return ncol;
+}
+
+/* Multicolor GS/SOR sweeps: colors ascending (forward), descending
+ * (backward) or both (symmetric); within a color every row takes the same
+ * damped update as the sequential loop, x_i = (1-w) x_i + w (b_i -
+ * sum_{j != i} a_ij x_j) / a_ii. */
+int or_mtgs_sweep(int n, const int32_t *rp, const int32_t *ci, const double *va, int variant, int sweeps, double w,
+                  const double *b, double *x)
+{
+    int32_t *color = malloc(sizeof(int32_t) * ((size_t)n + 1));
+    double *d = malloc(sizeof(double) * ((size_t)n + 1));
+    if (!color || !d) { free(color); free(d); return OR_ERR_NOMEM; }
+    int st = or_diag(n, rp, ci, va, d);
+    int ncol = st == OR_OK ? or_colors(n, rp, ci, color) : 0;
+    if (ncol < 0) st = ncol;
+    for (int t = 0; st == OR_OK && t < sweeps; ++t) {
+        for (int pass = 0; pass < 2; ++pass) {
+            int fwd = (pass == 0);
+            if (fwd && variant == OR_BACKWARD) continue;
+            if (!fwd && variant == OR_FORWARD) continue;
+            for (int q = 0; q < ncol; ++q) {
+                int c = fwd ? q : ncol - 1 - q;
+                for (int i = 0; i < n; ++i) {
+                    if (color[i] != c) continue;
+                    double s = 0.0;
+                    for (int k = rp[i]; k < rp[i + 1]; ++k)
+                        if (ci[k] != i) s += va[k] * x[ci[k]];
+                    x[i] = (1.0 - w) * x[i] + w * ((b[i] - s) / d[i]);
+                }
+            }
+        }
+    }
+    free(color);
+    free(d);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- CG
+ *
+ * Preconditioned conjugate gradients (the Krylov solver of the paper's
+ * symmetric positive definite experiments, Sections 8 and 9) in the
+ * textbook form:
+ *   r = b - A x, z = M^{-1} r, p = z, rz = r.z
+ *   repeat: q = A p, alpha = rz / p.q, x += alpha p, r -= alpha q,
+ *           stop if ||r|| <= rtol ||b||, z = M^{-1} r, beta = r.z_new / rz,
+ *           p = z + beta p
+ * The recurrence residual decides when to stop; the true residual is then
+ * checked and, if it has drifted above rtol, the iteration restarts from it.
+ * iterations counts preconditioner applications after the first
+ * (= the number of A p products).
+ */
+int or_pcg(int n, const int32_t *rp, const int32_t *ci, const double *va, const double *b, double *x, double rtol,
+           int maxit, const or_prec *P, or_info *info)
+{
+    or_csr A = {n, rp, ci, va};
+    memset(info, 0, sizeof(*info));
+    if (n <= 0 || maxit < 0) return info->status = OR_ERR_ARG;
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(b[i]) || !isfinite(x[i])) return info->status = OR_ERR_NONFINITE;
+    prec_ctx C;
+    memset(&C, 0, sizeof(C));
+    C.P = P;
+    C.A = &A;
+    if ((P->kind == OR_PREC_GS2 || P->kind == OR_PREC_JR) && P->precision != OR_FP64) {
+        int st = scaled_build(&A, P->precision, P->omega, &C.S);
+        if (st != OR_OK) return info->status = st;
+        C.have_scaled = 1;
+        C.work = malloc(sizeof(float) * (size_t)n * 4 + 16);
+        if (!C.work) { scaled_free(&C.S); return info->status = OR_ERR_NOMEM; }
+    }
+    size_t N = (size_t)n;
+    double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
+    double *p = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * N);
+    int status = OR_OK, total = 0;
+    double bnorm = 0.0;
+    if (!r || !z || !p || !q) { status = OR_ERR_NOMEM; goto done; }
+    bnorm = nrm2(n, b);
+    if (bnorm == 0.0) {
+        memset(x, 0, sizeof(double) * N);
+        info->converged = 1;
+        goto done;
+    }
+    for (;;) {
+        or_spmv(n, rp, ci, va, x, r);
+        for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
+        double rn = nrm2(n, r);
+        info->relres = rn / bnorm;
+        if (!isfinite(rn)) { status = OR_ERR_NONFINITE; break; }
+        if (info->relres <= rtol) { info->converged = 1; break; }
+        if (total >= maxit) { status = OR_NOT_CONVERGED; break; }
+        if (total > 0) info->restarts++;
+        int st = prec_apply(&C, r, z);
+        if (st != OR_OK) { status = st; break; }
+        memcpy(p, z, sizeof(double) * N);
+        double rz = dot(n, r, z);
+        while (total < maxit) {
+            or_spmv(n, rp, ci, va, p, q);
+            double pq = dot(n, p, q);
+            double alpha = rz / pq;
+            for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+            for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+            total++;
+            double rr = nrm2(n, r);
+            if (!isfinite(rr) || !isfinite(alpha)) { status = OR_ERR_NONFINITE; goto done; }
+            if (rr <= rtol * bnorm) break;
+            st = prec_apply(&C, r, z);
+            if (st != OR_OK) { status = st; goto done; }
+            double rzn = dot(n, r, z);
+            double beta = rzn / rz;
+            rz = rzn;
+            for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        }
+    }
+done:
+    info->iterations = total;
+    if (status == OR_OK && !info->converged) status = OR_NOT_CONVERGED;
+    if (info->converged) status = OR_OK;
+    info->status = status;
+    free(r); free(z); free(p); free(q);
     if (C.have_scaled) { scaled_free(&C.S); free(C.work); }
     return status;
 }

@@ -6,8 +6,8 @@ package only builds it and binds it through ctypes.
 from .native import (  # noqa: F401
     gs2_profile, gs2_profile_read,
     BACKWARD, FORWARD, SYMMETRIC, FP16_SCALED, FP32, FP64,
-    PREC_GS2, PREC_GS_TRISOLVE, PREC_JR, PREC_NONE,
+    PREC_GS2, PREC_GS_TRISOLVE, PREC_JR, PREC_NONE, PREC_MTGS, mtgs_apply,
     DeviceCSR, Gs2Error, Handle, BatchHandle,
-    gs2_setup, gs2_apply, jr_apply, gs_trisolve_apply, gmres_solve, gs2_destroy, gs2_handle_query,
+    gs2_setup, gs2_apply, jr_apply, gs_trisolve_apply, gmres_solve, cg_solve, gs2_destroy, gs2_handle_query,
     gs2_setup_batched, gmres_solve_batched, gs2_destroy_batched, status_string, lib,
 )

@@ -119,8 +119,8 @@ struct Sell {
     int val_bytes = 8;
 };
 
-struct GmresWork;      // krylov.hip
-struct TrisolveGraph;  // sweep.hip
+struct GmresWork; // krylov.hip
+struct CgWork;    // cg.hip
 
 struct Handle {
     int64_t n = 0;
@@ -137,7 +137,12 @@ struct Handle {
     int nlev_l = 0, nlev_u = 0;
     int32_t *lev_rows_l = nullptr, *lev_rows_u = nullptr; // rows grouped by level
     std::vector<int64_t> lev_ptr_l, lev_ptr_u;            // host offsets
+    // multicolor ordering (optional)
+    int ncolors = 0;
+    int32_t *color_rows = nullptr; // rows grouped by color
+    std::vector<int64_t> color_ptr;
     GmresWork *gw = nullptr;
+    CgWork *cw = nullptr;
     const int *stop = nullptr; // device flag: kernels return at once when set (GMRES)
     ~Handle();
 };
@@ -151,10 +156,12 @@ int choose_lanes(double avg_len, int max_len);
 int apply_gs2(Handle &h, const double *v, double *z, hipStream_t s);
 int apply_jr(Handle &h, int sweeps, double omega, const double *v, double *z, hipStream_t s);
 int apply_trisolve(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s);
+int apply_mtgs(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s);
 int time_inner_pass(Handle &h, hipStream_t s, float *ms);
 
-// krylov.hip
+// krylov.hip, cg.hip
 void free_gmres_work(GmresWork *w);
+void free_cg_work(CgWork *w);
 
 inline size_t prec_bytes(int precision) { return precision == GS2_FP64 ? 8 : 4; }
 

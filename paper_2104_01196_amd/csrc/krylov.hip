@@ -676,6 +676,7 @@ static int precondition(int kind, gs2_handle *P, const double *v, double *z, int
     case GS2_PREC_GS2: return apply_gs2(P->h, v, z, s);
     case GS2_PREC_JR: return apply_jr(P->h, P->h.sweeps, P->h.omega, v, z, s);
     case GS2_PREC_GS_TRISOLVE: return apply_trisolve(P->h, P->h.variant, P->h.omega, v, z, s);
+    case GS2_PREC_MTGS: return apply_mtgs(P->h, P->h.variant, P->h.omega, v, z, s);
     default:
         k_copy_stop<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, v, z, st);
         return GS2_OK;
@@ -874,9 +875,11 @@ extern "C" int gmres_solve(const gs2_csr *A, const double *b, double *x, int res
     const auto t0 = std::chrono::steady_clock::now();
     if (!A || A->n <= 0 || A->n >= (int64_t(1) << 31) - 1 || !A->rowptr || !A->colind || !A->val || !b || !x ||
         restart < 1 || restart > MAXM || !(rtol >= 0.0) || maxit < 0 || prec_kind < GS2_PREC_NONE ||
-        prec_kind > GS2_PREC_GS_TRISOLVE || (prec_kind != GS2_PREC_NONE && !prec) ||
-        (prec && prec->h.n != A->n) || (prec_kind == GS2_PREC_GS_TRISOLVE && prec->h.nlev_l == 0)) {
-        st = (prec_kind == GS2_PREC_GS_TRISOLVE && prec && prec->h.nlev_l == 0) ? GS2_ERR_NO_LEVELS : GS2_ERR_ARG;
+        prec_kind > GS2_PREC_MTGS || (prec_kind != GS2_PREC_NONE && !prec) || (prec && prec->h.n != A->n)) {
+        st = GS2_ERR_ARG;
+    } else if ((prec_kind == GS2_PREC_GS_TRISOLVE && prec->h.nlev_l == 0) ||
+               (prec_kind == GS2_PREC_MTGS && prec->h.ncolors == 0)) {
+        st = GS2_ERR_NO_LEVELS;
     } else {
         try {
             st = gmres_impl(*A, b, x, restart, rtol, maxit, prec_kind, prec, inf, (hipStream_t)stream);

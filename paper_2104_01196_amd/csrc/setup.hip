@@ -271,6 +271,47 @@ static int read_err(int *err, hipStream_t s)
 // Level sets of the DAGs of L (ascending) and U (descending), computed on the
 // host from a copy of the pattern: level_i = 1 + max level over the
 // triangle's entries of row i.  Rows are then grouped level by level.
+// Multicolor ordering (Section 6, multi-threaded Gauss-Seidel): greedy first
+// fit in natural row order on the symmetrised pattern; a row takes the
+// smallest color not held by an earlier row it is coupled to (a_ij or a_ji
+// nonzero).  Rows are then grouped color by color.
+static int build_colors(Handle &h, const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, hipStream_t s)
+{
+    const int64_t n = h.n;
+    // transpose pattern (column -> rows), to see couplings a_ji from earlier rows j
+    std::vector<int32_t> tp(n + 1, 0), tc(std::max<size_t>(ci.size(), 1));
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) tp[ci[k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tp[i + 1] += tp[i];
+    std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) tc[fill[ci[k]]++] = (int32_t)i;
+    std::vector<int32_t> color(n), seen(n + 2, -1);
+    int ncol = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+            if (ci[k] < i) seen[color[ci[k]]] = (int32_t)i;
+        for (int32_t k = tp[i]; k < tp[i + 1]; ++k)
+            if (tc[k] < i) seen[color[tc[k]]] = (int32_t)i;
+        int c = 0;
+        while (seen[c] == i) ++c;
+        color[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    std::vector<int64_t> ptr(ncol + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ptr[color[i] + 1]++;
+    for (int c = 0; c < ncol; ++c) ptr[c + 1] += ptr[c];
+    std::vector<int32_t> rows(std::max<int64_t>(n, 1));
+    std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i) rows[pos[color[i]]++] = (int32_t)i;
+    GS2_TRY_HIP(hipMalloc(&h.color_rows, sizeof(int32_t) * rows.size()));
+    GS2_TRY_HIP(hipMemcpyAsync(h.color_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, s));
+    GS2_TRY_HIP(hipStreamSynchronize(s));
+    h.ncolors = ncol;
+    h.color_ptr = std::move(ptr);
+    return GS2_OK;
+}
+
 static int build_levels(Handle &h, const gs2_csr &A, hipStream_t s)
 {
     const int64_t n = A.n;
@@ -297,21 +338,19 @@ static int build_levels(Handle &h, const gs2_csr &A, hipStream_t s)
         std::vector<int32_t> rows(std::max<int64_t>(n, 1));
         std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
         for (int64_t i = 0; i < n; ++i) rows[pos[lev[i]]++] = (int32_t)i;
-        int32_t *d_rows = nullptr;
+        int32_t *&d_rows = lower ? h.lev_rows_l : h.lev_rows_u; // owned by the handle from here on
         GS2_TRY_HIP(hipMalloc(&d_rows, sizeof(int32_t) * rows.size()));
         GS2_TRY_HIP(hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, s));
         GS2_TRY_HIP(hipStreamSynchronize(s));
         if (lower) {
             h.nlev_l = nlev;
-            h.lev_rows_l = d_rows;
             h.lev_ptr_l = std::move(ptr);
         } else {
             h.nlev_u = nlev;
-            h.lev_rows_u = d_rows;
             h.lev_ptr_u = std::move(ptr);
         }
     }
-    return GS2_OK;
+    return build_colors(h, rp, ci, s);
 }
 
 static int alloc_vectors(Handle &h)
@@ -414,9 +453,11 @@ Handle::~Handle()
 {
     free_sell(L);
     free_sell(U);
-    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, (void *)lev_rows_l, (void *)lev_rows_u})
+    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, (void *)lev_rows_l, (void *)lev_rows_u,
+                    (void *)color_rows})
         if (p) (void)hipFree(p);
     if (gw) free_gmres_work(gw);
+    if (cw) free_cg_work(cw);
 }
 
 extern "C" {

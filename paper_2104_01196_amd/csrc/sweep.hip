@@ -189,6 +189,34 @@ __global__ void k_tri_level(const int *__restrict__ stop, const int32_t *__restr
     xnew[i] = (AT(1) - w) * xo + w * ((AT)(v[i] * sl[i]) - acc);
 }
 
+// One color of a multicolor Gauss-Seidel / SOR sweep: rows of one color are
+// never coupled, so they update in place from the current iterate,
+//   x_i = (1 - w) x_i + w (S_l v_i - sum_{j != i} ah_ij x_j)   (scaled space).
+template <typename VT, typename AT>
+__global__ void k_color(const int *__restrict__ stop, const int32_t *__restrict__ rows, int64_t cnt, int K,
+                        SellView L, SellView U, AT *x, const double *__restrict__ v, const double *__restrict__ sl,
+                        AT w)
+{
+    if (stop && *stop) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    const int i = rows[t];
+    const int C = WAVE / K;
+    const int64_t s = i / C;
+    const int lb = (i % C) * K;
+    AT acc = AT(0);
+    for (int part = 0; part < 2; ++part) {
+        const SellView &M = part ? U : L;
+        const int64_t beg = M.sp[s], steps = (M.sp[s + 1] - beg) / WAVE;
+        for (int64_t st = 0; st < steps; ++st)
+            for (int q = 0; q < K; ++q) {
+                const int64_t p = beg + st * WAVE + lb + q;
+                acc += (AT)((const VT *)M.val)[p] * x[M.col[p]];
+            }
+    }
+    x[i] = (AT(1) - w) * x[i] + w * ((AT)(v[i] * sl[i]) - acc);
+}
+
 // ------------------------------------------------------------ host drivers
 
 constexpr int TB = 256; // 4 wavefronts per workgroup, one slice each
@@ -354,6 +382,31 @@ struct Launch {
         return GS2_OK;
     }
 
+    // multicolor GS/SOR: `sweeps` sweeps from x = 0, colors ascending
+    // (forward), descending (backward) or both (symmetric)
+    static int mtgs(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s)
+    {
+        AT *x = (AT *)h.xh;
+        const AT w = (AT)omega;
+        k_fill_zero<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, x);
+        for (int t = 0; t < h.sweeps; ++t)
+            for (int half = 0; half < 2; ++half) {
+                const bool fwd = half == 0;
+                if (fwd && variant == GS2_BACKWARD) continue;
+                if (!fwd && variant == GS2_FORWARD) continue;
+                for (int q = 0; q < h.ncolors; ++q) {
+                    const int c = fwd ? q : h.ncolors - 1 - q;
+                    const int64_t cnt = h.color_ptr[c + 1] - h.color_ptr[c];
+                    if (cnt <= 0) continue;
+                    Prof pr(s, PK_TRI, (double)cnt * (16.0 + 2 * sizeof(AT)));
+                    k_color<VT, AT><<<(unsigned)((cnt + TB - 1) / TB), TB, 0, s>>>(
+                        h.stop, h.color_rows + h.color_ptr[c], cnt, h.L.K, view(h.L), view(h.U), x, v, h.sl, w);
+                }
+            }
+        k_unscale<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, x, h.sr, z);
+        return GS2_OK;
+    }
+
     static int time_inner(Handle &h, hipStream_t s, float *ms)
     {
         hipEvent_t e0, e1;
@@ -403,6 +456,13 @@ int apply_trisolve(Handle &h, int variant, double omega, const double *v, double
     return st;
 }
 
+int apply_mtgs(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s)
+{
+    int st = GS2_DISPATCH(h, mtgs(h, variant, omega, v, z, s));
+    GS2_TRY_HIP(hipGetLastError());
+    return st;
+}
+
 int time_inner_pass(Handle &h, hipStream_t s, float *ms)
 {
     int st = GS2_DISPATCH(h, time_inner(h, s, ms));
@@ -439,6 +499,16 @@ int gs_trisolve_apply(gs2_handle *H, int variant, double damping, const double *
     if (H->h.n == 0) return GS2_OK;
     if (H->h.nlev_l == 0) return GS2_ERR_NO_LEVELS;
     return apply_trisolve(H->h, variant, damping, v, z, (hipStream_t)stream);
+}
+
+int mtgs_apply(gs2_handle *H, int variant, double damping, const double *v, double *z, void *stream)
+{
+    if (!H || variant < GS2_FORWARD || variant > GS2_SYMMETRIC || !(damping > 0.0 && damping < 2.0) ||
+        (H->h.n > 0 && (!v || !z)) || v == z)
+        return GS2_ERR_ARG;
+    if (H->h.n == 0) return GS2_OK;
+    if (H->h.ncolors == 0) return GS2_ERR_NO_LEVELS;
+    return apply_mtgs(H->h, variant, damping, v, z, (hipStream_t)stream);
 }
 
 } // extern "C"

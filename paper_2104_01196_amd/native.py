@@ -20,7 +20,7 @@ OK, ERR_ARG, ERR_BAD_CSR, ERR_ZERO_DIAG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_
 NOT_CONVERGED, BREAKDOWN = 1, 2
 FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
 FP64, FP32, FP16_SCALED = 0, 1, 2
-PREC_NONE, PREC_GS2, PREC_JR, PREC_GS_TRISOLVE = 0, 1, 2, 3
+PREC_NONE, PREC_GS2, PREC_JR, PREC_GS_TRISOLVE, PREC_MTGS = 0, 1, 2, 3, 4
 
 
 class Gs2Error(RuntimeError):
@@ -65,7 +65,9 @@ def lib():
         L.gs2_apply.argtypes = [vp, vp, vp, vp]
         L.jr_apply.argtypes = [vp, i, d, vp, vp, vp]
         L.gs_trisolve_apply.argtypes = [vp, i, d, vp, vp, vp]
+        L.mtgs_apply.argtypes = [vp, i, d, vp, vp, vp]
         L.gmres_solve.argtypes = [C.POINTER(CsrDesc), vp, vp, i, d, i, i, vp, C.POINTER(SolveInfo), vp]
+        L.cg_solve.argtypes = [C.POINTER(CsrDesc), vp, vp, d, i, i, vp, C.POINTER(SolveInfo), vp]
         L.gs2_destroy.argtypes = [vp]
         L.gs2_destroy.restype = None
         L.gs2_status_string.argtypes = [i]
@@ -202,6 +204,15 @@ def gs_trisolve_apply(h: Handle, variant, damping, v, z, stream=None):
         raise Gs2Error(st, "gs_trisolve_apply")
 
 
+def mtgs_apply(h: Handle, variant, damping, v, z, stream=None):
+    import torch
+
+    st = lib().mtgs_apply(h.ptr, variant, damping, _ptr(v, torch.float64, h.n, "v"),
+                          _ptr(z, torch.float64, h.n, "z"), _stream(stream))
+    if st != OK:
+        raise Gs2Error(st, "mtgs_apply")
+
+
 def gmres_solve(A: DeviceCSR, b, x, restart=30, rtol=1e-8, maxit=10000, prec_kind=PREC_GS2, prec: Handle = None,
                 stream=None, raise_on_error=True) -> dict:
     """Returns the gs2_solve_info fields as a dict.  Hard errors raise;
@@ -215,6 +226,21 @@ def gmres_solve(A: DeviceCSR, b, x, restart=30, rtol=1e-8, maxit=10000, prec_kin
                            _stream(stream))
     if st < 0 and raise_on_error:
         raise Gs2Error(st, "gmres_solve")
+    return {"iterations": info.iterations, "restarts": info.restarts, "relres": info.relres,
+            "converged": bool(info.converged), "status": info.status, "seconds": info.seconds}
+
+
+def cg_solve(A: DeviceCSR, b, x, rtol=1e-8, maxit=10000, prec_kind=PREC_GS2, prec: Handle = None, stream=None,
+             raise_on_error=True) -> dict:
+    """Preconditioned CG; returns the gs2_solve_info fields as a dict."""
+    import torch
+
+    info = SolveInfo()
+    d = A.desc()
+    st = lib().cg_solve(C.byref(d), _ptr(b, torch.float64, A.n, "b"), _ptr(x, torch.float64, A.n, "x"), rtol, maxit,
+                        prec_kind, prec.ptr if prec is not None else None, C.byref(info), _stream(stream))
+    if st < 0 and raise_on_error:
+        raise Gs2Error(st, "cg_solve")
     return {"iterations": info.iterations, "restarts": info.restarts, "relres": info.relres,
             "converged": bool(info.converged), "status": info.status, "seconds": info.seconds}
 

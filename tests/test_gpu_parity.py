@@ -359,3 +359,48 @@ def test_full_size_laplace3d_apply_and_solve():
         xh = host(x)
         assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
         assert np.linalg.norm(xh - p["x_true"]) / np.linalg.norm(p["x_true"]) <= 1e-4
+
+
+# -------------------------------------------------------------------- PCG
+
+@pytest.mark.parametrize("prec,kind,kw", [
+    ("gs2", g.PREC_GS2, dict(variant=g.SYMMETRIC, sweeps=1, inner=1)),
+    ("gs2", g.PREC_GS2, dict(variant=g.SYMMETRIC, sweeps=2, inner=2, precision=g.FP32)),
+    ("gs2", g.PREC_GS2, dict(variant=g.SYMMETRIC, sweeps=1, inner=1, precision=g.FP16_SCALED)),
+    ("jr", g.PREC_JR, dict(sweeps=1)),
+    ("sor", g.PREC_GS_TRISOLVE, dict(variant=g.SYMMETRIC)),
+    ("none", g.PREC_NONE, dict()),
+])
+@pytest.mark.parametrize("cfg,size", [(1, 64), (4, 14)])
+def test_pcg_matches_oracle(prec, kind, kw, cfg, size):
+    p = config_problem(cfg, size=size)
+    A, b = p["A"], p["b"]
+    okw = dict(kw)
+    if "precision" in okw:
+        okw["precision"] = {g.FP32: oracle.FP32, g.FP16_SCALED: oracle.FP16S}[okw["precision"]]
+    xo, io = oracle.pcg(A, b, rtol=1e-8, prec=prec, **okw)
+    dA = g.DeviceCSR.from_host(A)
+    h = None
+    if kind != g.PREC_NONE:
+        h = g.gs2_setup(dA, kw.get("sweeps", 1), kw.get("inner", 1), 1.0, kw.get("variant", g.FORWARD),
+                        precision=kw.get("precision", g.FP64), build_levels=(kind == g.PREC_GS_TRISOLVE))
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.cg_solve(dA, dev(b), x, 1e-8, 20000, kind, h)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    xh = host(x)
+    assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
+    assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_pcg_status_paths():
+    p = config_problem(1, size=16)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.cg_solve(dA, dev(b), x, 1e-14, 5, g.PREC_GS2, h)
+    assert info["status"] == 1 and info["iterations"] == 5
+    x.zero_()
+    info = g.cg_solve(dA, torch.zeros(A.n, dtype=torch.float64, device=DEV), x, 1e-8, 50, g.PREC_GS2, h)
+    assert info["converged"] and info["iterations"] == 0
