@@ -79,6 +79,8 @@ def lib():
                                      C.POINTER(_Info), C.c_void_p]
         L.or_pcg.argtypes = csr + [_f64p, _f64p, C.c_double, C.c_int, C.POINTER(_Prec), C.POINTER(_Info)]
         L.or_colors.argtypes = [C.c_int, _i32p, _i32p, _i32p]
+        L.or_gs2_block_sweep.argtypes = csr + [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                               _f64p, _f64p]
         L.or_mtgs_sweep.argtypes = csr + [C.c_int, C.c_int, C.c_double, _f64p, _f64p]
         _lib = L
     return _lib
@@ -155,6 +157,14 @@ def levels(A, lower=True):
     nlev = lib().or_levels(int(A.n), np.ascontiguousarray(A.rowptr, np.int32),
                            np.ascontiguousarray(A.colind, np.int32), 1 if lower else 0, lv)
     return lv, nlev
+
+
+def gs2_block_sweep(A, b, x0, blocks=1, variant=FORWARD, sweeps=1, local_sweeps=1, inner=1, omega=1.0, gamma=1.0):
+    """Hybrid block-Jacobi GS2: `sweeps` global sweeps, each freezing the
+    off-block values and running `local_sweeps` local GS2 sweeps per block."""
+    x = _vec(x0).copy()
+    _chk(lib().or_gs2_block_sweep(*_csr(A), blocks, variant, sweeps, local_sweeps, inner, omega, gamma, _vec(b), x))
+    return x
 
 
 def colors(A):
