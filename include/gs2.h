@@ -83,6 +83,10 @@ typedef struct gs2_options {
     int orthogonalization; /* gmres_solve with this handle: 0 = CGS2 with    */
                            /* delayed reorthogonalisation (two passes over   */
                            /* the basis per step, default), 1 = CGS2 (four)  */
+    int blocks;           /* hybrid relaxation (Section 3): number of        */
+                          /* contiguous row blocks (0 or 1 = global GS2)     */
+    int local_sweeps;     /* n_k local sweeps per global sweep with frozen   */
+                          /* off-block values (0 or 1 = one)                 */
 } gs2_options;
 
 typedef struct gs2_solve_info {

@@ -50,7 +50,8 @@ _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 class _Prec(C.Structure):
     _fields_ = [("kind", C.c_int), ("variant", C.c_int), ("sweeps", C.c_int), ("inner", C.c_int),
-                ("omega", C.c_double), ("gamma", C.c_double), ("precision", C.c_int), ("compact", C.c_int)]
+                ("omega", C.c_double), ("gamma", C.c_double), ("precision", C.c_int), ("compact", C.c_int),
+                ("blocks", C.c_int), ("local_sweeps", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -201,7 +202,7 @@ def gs2_apply_lp(A, v, precision=FP32, variant=FORWARD, sweeps=1, inner=1, omega
 
 
 def gmres(A, b, x0=None, restart=30, rtol=1e-8, maxit=10000, prec="none", variant=FORWARD, sweeps=1, inner=1,
-          omega=1.0, gamma=1.0, precision=FP64, compact=False, cgs2=False, history=False):
+          omega=1.0, gamma=1.0, precision=FP64, compact=False, cgs2=False, history=False, blocks=1, local_sweeps=1):
     """Restarted flexible GMRES(m).  prec in {"none", "gs2", "jr", "sor"}.
 
     Returns (x, info dict).  info: iterations, restarts, relres, converged,
@@ -209,7 +210,7 @@ def gmres(A, b, x0=None, restart=30, rtol=1e-8, maxit=10000, prec="none", varian
     (relative residual estimates) when requested.
     """
     kind = _PREC[prec]
-    P = _Prec(kind, variant, sweeps, inner, omega, gamma, precision, 1 if compact else 0)
+    P = _Prec(kind, variant, sweeps, inner, omega, gamma, precision, 1 if compact else 0, blocks, local_sweeps)
     info = _Info()
     x = np.zeros(A.n) if x0 is None else _vec(x0).copy()
     hist = np.full(maxit + 2, np.nan) if history else None
@@ -225,10 +226,10 @@ def gmres(A, b, x0=None, restart=30, rtol=1e-8, maxit=10000, prec="none", varian
 
 
 def pcg(A, b, x0=None, rtol=1e-8, maxit=10000, prec="none", variant=SYMMETRIC, sweeps=1, inner=1, omega=1.0,
-        gamma=1.0, precision=FP64, compact=False):
+        gamma=1.0, precision=FP64, compact=False, blocks=1, local_sweeps=1):
     """Preconditioned conjugate gradients.  Returns (x, info dict)."""
     kind = _PREC[prec]
-    P = _Prec(kind, variant, sweeps, inner, omega, gamma, precision, 1 if compact else 0)
+    P = _Prec(kind, variant, sweeps, inner, omega, gamma, precision, 1 if compact else 0, blocks, local_sweeps)
     info = _Info()
     x = np.zeros(A.n) if x0 is None else _vec(x0).copy()
     t0 = time.perf_counter()

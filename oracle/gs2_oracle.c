@@ -54,6 +54,8 @@ typedef struct {
 
 int or_mtgs_sweep(int n, const int32_t *rp, const int32_t *ci, const double *va, int variant, int sweeps, double w,
                   const double *b, double *x);
+int or_gs2_block_sweep(int n, const int32_t *rp, const int32_t *ci, const double *va, int blocks, int variant,
+                       int sweeps, int local_sweeps, int inner, double w, double gamma, const double *b, double *x);
 
 /* ------------------------------------------------------------------ basics */
 
@@ -500,6 +502,8 @@ typedef struct {
     double gamma;
     int precision; /* OR_FP64 / OR_FP32 / OR_FP16S (GS2 and JR only) */
     int compact;   /* GS2 compact form (FP64 only) */
+    int blocks;    /* hybrid relaxation: row blocks (<= 1: global), FP64 GS2 / JR */
+    int local_sweeps;
 } or_prec;
 
 typedef struct {
@@ -533,6 +537,9 @@ static int prec_apply(prec_ctx *C, const double *v, double *z)
         int variant = P->kind == OR_PREC_JR ? OR_FORWARD : P->variant;
         if (C->have_scaled) return scaled_apply(&C->S, variant, P->sweeps, inner, v, z, C->work);
         memset(z, 0, sizeof(double) * (size_t)n);
+        if (P->blocks > 1)
+            return or_gs2_block_sweep(n, A->rp, A->ci, A->va, P->blocks, variant, P->sweeps,
+                                      P->local_sweeps > 1 ? P->local_sweeps : 1, inner, P->omega, P->gamma, v, z);
         if (P->kind == OR_PREC_JR) return or_jr_sweep(n, A->rp, A->ci, A->va, P->sweeps, P->omega, v, z);
         if (P->compact) return or_gs2c_sweep(n, A->rp, A->ci, A->va, variant, P->sweeps, inner, P->omega, P->gamma, v, z);
         return or_gs2_sweep(n, A->rp, A->ci, A->va, variant, P->sweeps, inner, P->omega, P->gamma, v, z);

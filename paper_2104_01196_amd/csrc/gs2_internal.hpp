@@ -130,6 +130,12 @@ struct Handle {
     int orth = 0;        // GMRES orthogonalisation (0 delayed CGS2, 1 CGS2)
     int block_waves = 4; // wavefronts per workgroup in the sweep kernels
     Sell L, U;
+    // hybrid relaxation: `blocks` contiguous row blocks; L and U then hold the
+    // block-local triangles and E the couplings between blocks, applied to
+    // values frozen once per global sweep (`local_sweeps` local sweeps each)
+    int blocks = 1, local_sweeps = 1;
+    Sell E;
+    void *yh = nullptr; // frozen copy of the iterate
     double *sl = nullptr, *sr = nullptr; // scaling vectors (float64)
     // persistent temporaries (Section 6: allocated once, live with the handle)
     void *xh = nullptr, *xh2 = nullptr, *rh = nullptr, *ga = nullptr, *gb = nullptr;

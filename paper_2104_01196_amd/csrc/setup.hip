@@ -128,13 +128,57 @@ __device__ __forceinline__ _Float16 convert_scaled<_Float16>(double v, int *ovf)
     return h;
 }
 
+// Which entries of a row a stored part holds, as up to two ranges of the
+// row's sorted CSR entries.  Parts: 0 = strictly lower inside the row's
+// block, 1 = strictly upper inside the block, 2 = outside the block (the
+// couplings of the hybrid relaxation).  Blocks are contiguous ranges of bs
+// rows; with one block (bs >= n) part 2 is empty.  Sorted columns put the
+// off-block lower entries first and the off-block upper entries last.
+enum : int { PART_L = 0, PART_U = 1, PART_E = 2 };
+
+struct Ranges {
+    int32_t *off1 = nullptr, *cnt1 = nullptr, *off2 = nullptr, *cnt2 = nullptr, *tot = nullptr;
+};
+
+__global__ void k_ranges(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                         const int32_t *__restrict__ lcnt, const int32_t *__restrict__ ucnt, int64_t bs, int part,
+                         Ranges R)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t b0 = (i / bs) * bs, b1 = b0 + bs < n ? b0 + bs : n;
+    const int lc = lcnt[i], uc = ucnt[i];
+    const int64_t r = rp[i];
+    int lo = 0, hi = 0;
+    while (lo < lc && ci[r + lo] < b0) ++lo;
+    while (hi < uc && ci[r + lc + uc - hi] >= b1) ++hi;
+    int o1 = 0, c1 = 0, o2 = 0, c2 = 0;
+    if (part == PART_L) {
+        o1 = lo;
+        c1 = lc - lo;
+    } else if (part == PART_U) {
+        o1 = lc + 1;
+        c1 = uc - hi;
+    } else {
+        o1 = 0;
+        c1 = lo;
+        o2 = lc + 1 + uc - hi;
+        c2 = hi;
+    }
+    R.off1[i] = o1;
+    R.cnt1[i] = c1;
+    R.off2[i] = o2;
+    R.cnt2[i] = c2;
+    R.tot[i] = c1 + c2;
+}
+
 // One thread per (slice, lane): writes the lane's entries of its row, the
 // value (s_l[i] * a_ij) * s_r[j] rounded once to VT, padding with
 // (own column, 0).
 template <typename VT>
-__global__ void k_fill(int64_t n, int64_t nslices, int K, int lower, const int32_t *__restrict__ rp,
-                       const int32_t *__restrict__ ci, const double *__restrict__ va, const int32_t *__restrict__ lcnt,
-                       const int32_t *__restrict__ cnt, const double *__restrict__ sl, const double *__restrict__ sr,
+__global__ void k_fill(int64_t n, int64_t nslices, int K, const int32_t *__restrict__ rp,
+                       const int32_t *__restrict__ ci, const double *__restrict__ va, Ranges R,
+                       const double *__restrict__ sl, const double *__restrict__ sr,
                        const int64_t *__restrict__ sp, int32_t *__restrict__ col, VT *__restrict__ val,
                        int *__restrict__ err)
 {
@@ -147,8 +191,10 @@ __global__ void k_fill(int64_t n, int64_t nslices, int K, int lower, const int32
     const int64_t row = s * C + r;
     const int64_t beg = sp[s];
     const int steps = (int)((sp[s + 1] - beg) / WAVE);
-    const int c_row = row < n ? cnt[row] : 0;
-    const int64_t base = row < n ? (int64_t)rp[row] + (lower ? 0 : lcnt[row] + 1) : 0;
+    const int c_row = row < n ? R.tot[row] : 0;
+    const int c1 = row < n ? R.cnt1[row] : 0;
+    const int64_t base = row < n ? (int64_t)rp[row] : 0;
+    const int o1 = row < n ? R.off1[row] : 0, o2 = row < n ? R.off2[row] : 0;
     const int32_t pad_col = (int32_t)(row < n ? row : n - 1);
     const double srow = row < n ? sl[row] : 0.0;
     int ovf = 0;
@@ -156,8 +202,9 @@ __global__ void k_fill(int64_t n, int64_t nslices, int K, int lower, const int32
         const int e = t * K + q;
         const int64_t pos = beg + (int64_t)t * WAVE + l;
         if (e < c_row) {
-            const int32_t c = ci[base + e];
-            const double sc = (srow * va[base + e]) * sr[c];
+            const int64_t idx = base + (e < c1 ? o1 + e : o2 + (e - c1));
+            const int32_t c = ci[idx];
+            const double sc = (srow * va[idx]) * sr[c];
             col[pos] = c;
             val[pos] = convert_scaled<VT>(sc, &ovf);
         } else {
@@ -188,9 +235,10 @@ int choose_lanes(double avg_len, int max_len)
     return 16;
 }
 
-static int build_one(Sell &S, int64_t n, int K, int lower, int precision, const gs2_csr &A, const int32_t *lcnt,
-                     const int32_t *cnt, const double *sl, const double *sr, int *err, hipStream_t s)
+static int build_one(Sell &S, int64_t n, int K, int precision, const gs2_csr &A, const Ranges &R,
+                     const double *sl, const double *sr, int *err, hipStream_t s)
 {
+    const int32_t *cnt = R.tot;
     free_sell(S);
     S.n = n;
     S.K = K;
@@ -218,14 +266,14 @@ static int build_one(Sell &S, int64_t n, int K, int lower, int precision, const 
     const unsigned grid = (unsigned)((threads + tb - 1) / tb);
     if (S.nslices > 0) {
         if (precision == GS2_FP64)
-            k_fill<double><<<grid, tb, 0, s>>>(n, S.nslices, K, lower, A.rowptr, A.colind, A.val, lcnt, cnt, sl, sr,
-                                               S.slice_ptr, S.col, (double *)S.val, err);
+            k_fill<double><<<grid, tb, 0, s>>>(n, S.nslices, K, A.rowptr, A.colind, A.val, R, sl, sr, S.slice_ptr,
+                                               S.col, (double *)S.val, err);
         else if (precision == GS2_FP32)
-            k_fill<float><<<grid, tb, 0, s>>>(n, S.nslices, K, lower, A.rowptr, A.colind, A.val, lcnt, cnt, sl, sr,
-                                              S.slice_ptr, S.col, (float *)S.val, err);
+            k_fill<float><<<grid, tb, 0, s>>>(n, S.nslices, K, A.rowptr, A.colind, A.val, R, sl, sr, S.slice_ptr,
+                                              S.col, (float *)S.val, err);
         else
-            k_fill<_Float16><<<grid, tb, 0, s>>>(n, S.nslices, K, lower, A.rowptr, A.colind, A.val, lcnt, cnt, sl,
-                                                 sr, S.slice_ptr, S.col, (_Float16 *)S.val, err);
+            k_fill<_Float16><<<grid, tb, 0, s>>>(n, S.nslices, K, A.rowptr, A.colind, A.val, R, sl, sr, S.slice_ptr,
+                                                 S.col, (_Float16 *)S.val, err);
         GS2_TRY_HIP(hipGetLastError());
     }
     return GS2_OK;
@@ -251,14 +299,34 @@ struct SetupScratch {
     int32_t *lcnt = nullptr, *ucnt = nullptr;
     double *d = nullptr;
     int *err = nullptr;
+    Ranges R;
     ~SetupScratch()
     {
-        if (lcnt) (void)hipFree(lcnt);
-        if (ucnt) (void)hipFree(ucnt);
-        if (d) (void)hipFree(d);
-        if (err) (void)hipFree(err);
+        for (void *p : {(void *)lcnt, (void *)ucnt, (void *)d, (void *)err, (void *)R.off1, (void *)R.cnt1,
+                        (void *)R.off2, (void *)R.cnt2, (void *)R.tot})
+            if (p) (void)hipFree(p);
     }
 };
+
+// Ranges of part `part` for every row, then the part itself in sliced-ELL.
+static int build_part(Handle &h, Sell &S, int part, int K, const gs2_csr &A, SetupScratch &sc, hipStream_t s)
+{
+    const int64_t bs = h.blocks > 1 ? (h.n + h.blocks - 1) / h.blocks : std::max<int64_t>(h.n, 1);
+    k_ranges<<<(unsigned)((h.n + 255) / 256), 256, 0, s>>>(h.n, A.rowptr, A.colind, sc.lcnt, sc.ucnt, bs, part, sc.R);
+    GS2_TRY_HIP(hipGetLastError());
+    return build_one(S, h.n, K, h.precision, A, sc.R, h.sl, h.sr, sc.err, s);
+}
+
+static int64_t count_total(const int32_t *tot, int64_t n, hipStream_t s, int *st)
+{
+    std::vector<int32_t> t(n);
+    *st = GS2_OK;
+    if (n && hipMemcpyAsync(t.data(), tot, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess) *st = GS2_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) *st = GS2_ERR_HIP;
+    int64_t c = 0;
+    for (int32_t v : t) c += v;
+    return c;
+}
 
 static int read_err(int *err, hipStream_t s)
 {
@@ -374,6 +442,8 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
     GS2_TRY_HIP(hipMalloc(&sc.ucnt, sizeof(int32_t) * nb));
     GS2_TRY_HIP(hipMalloc(&sc.d, sizeof(double) * nb));
     GS2_TRY_HIP(hipMalloc(&sc.err, sizeof(int)));
+    for (int32_t **p : {&sc.R.off1, &sc.R.cnt1, &sc.R.off2, &sc.R.cnt2, &sc.R.tot})
+        GS2_TRY_HIP(hipMalloc(p, sizeof(int32_t) * nb));
     GS2_TRY_HIP(hipMalloc(&h.sl, sizeof(double) * nb));
     GS2_TRY_HIP(hipMalloc(&h.sr, sizeof(double) * nb));
     GS2_TRY_HIP(hipMemsetAsync(sc.err, 0, sizeof(int), s));
@@ -415,7 +485,7 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
                 int bestK = K;
                 for (int cand = 1; cand <= 16; cand *= 2) {
                     if (cand > 1 && cand > 2 * std::max(1.0, avg)) break;
-                    GS2_TRY(build_one(h.L, n, cand, 1, h.precision, A, sc.lcnt, sc.lcnt, h.sl, h.sr, sc.err, s));
+                    GS2_TRY(build_part(h, h.L, PART_L, cand, A, sc, s));
                     float ms = 0.f;
                     GS2_TRY(time_inner_pass(h, s, &ms));
                     if (ms < best) { best = ms; bestK = cand; }
@@ -426,20 +496,20 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
             }
         }
     }
-    GS2_TRY(build_one(h.L, n, K, 1, h.precision, A, sc.lcnt, sc.lcnt, h.sl, h.sr, sc.err, s));
-    GS2_TRY(build_one(h.U, n, K, 0, h.precision, A, sc.lcnt, sc.ucnt, h.sl, h.sr, sc.err, s));
-    GS2_TRY(read_err(sc.err, s));
-    // real entry counts
-    h.L.nnz = h.U.nnz = 0;
-    {
-        std::vector<int32_t> lc(n), uc(n);
-        if (n) {
-            GS2_TRY_HIP(hipMemcpyAsync(lc.data(), sc.lcnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-            GS2_TRY_HIP(hipMemcpyAsync(uc.data(), sc.ucnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-            GS2_TRY_HIP(hipStreamSynchronize(s));
-        }
-        for (int64_t i = 0; i < n; ++i) { h.L.nnz += lc[i]; h.U.nnz += uc[i]; }
+    int cst = GS2_OK;
+    GS2_TRY(build_part(h, h.L, PART_L, K, A, sc, s));
+    h.L.nnz = count_total(sc.R.tot, n, s, &cst);
+    GS2_TRY(cst);
+    GS2_TRY(build_part(h, h.U, PART_U, K, A, sc, s));
+    h.U.nnz = count_total(sc.R.tot, n, s, &cst);
+    GS2_TRY(cst);
+    if (h.blocks > 1) {
+        GS2_TRY(build_part(h, h.E, PART_E, K, A, sc, s));
+        h.E.nnz = count_total(sc.R.tot, n, s, &cst);
+        GS2_TRY(cst);
+        if (alloc_vecs) GS2_TRY_HIP(hipMalloc(&h.yh, prec_bytes(h.precision) * nb));
     }
+    GS2_TRY(read_err(sc.err, s));
     if (o.build_levels) GS2_TRY(build_levels(h, A, s));
     GS2_TRY_HIP(hipStreamSynchronize(s));
     return GS2_OK;
@@ -453,7 +523,8 @@ Handle::~Handle()
 {
     free_sell(L);
     free_sell(U);
-    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, (void *)lev_rows_l, (void *)lev_rows_u,
+    free_sell(E);
+    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, yh, (void *)lev_rows_l, (void *)lev_rows_u,
                     (void *)color_rows})
         if (p) (void)hipFree(p);
     if (gw) free_gmres_work(gw);
@@ -473,6 +544,8 @@ void gs2_default_options(gs2_options *opt)
     opt->lanes_per_row = 0;
     opt->rhs_per_item = 0;
     opt->orthogonalization = 0;
+    opt->blocks = 1;
+    opt->local_sweeps = 1;
 }
 
 int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
@@ -490,6 +563,9 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     if (opt) o = *opt;
     if (o.precision < GS2_FP64 || o.precision > GS2_FP16_SCALED) return GS2_ERR_ARG;
     if (o.orthogonalization < 0 || o.orthogonalization > 1) return GS2_ERR_ARG;
+    if (o.blocks < 0 || o.local_sweeps < 0 || (o.blocks > 1 && (o.compact || o.build_levels)) ||
+        (int64_t)o.blocks > std::max<int64_t>(A->n, 1))
+        return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;
     if (!H) return GS2_ERR_NOMEM;
@@ -502,6 +578,8 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     h.gamma = o.inner_damping;
     h.compact = o.compact ? 1 : 0;
     h.orth = o.orthogonalization;
+    h.blocks = std::max(1, o.blocks);
+    h.local_sweeps = std::max(1, o.local_sweeps);
     h.precision = o.precision;
     hipStream_t s = (hipStream_t)stream;
     int st = GS2_ERR_HIP;

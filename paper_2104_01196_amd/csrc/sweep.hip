@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int
                                                const AT *__restrict__ xh, const double *__restrict__ v,
                                                const double *__restrict__ sl, AT cdiag, AT w, int dst,
                                                AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
-                                               const double *__restrict__ sr)
+                                               const double *__restrict__ sr, SellView Ev, const AT *__restrict__ ye)
 {
     if (stop && *stop) return;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -113,6 +113,12 @@ __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int
 #pragma unroll 4
         for (int64_t p = beg + lane; p < end; p += WAVE) acc += (AT)val[p] * xh[col[p]];
     }
+    if (ye) { // couplings to other blocks, on the values frozen at the last exchange
+        const VT *__restrict__ val = (const VT *)Ev.val;
+        const int32_t *__restrict__ col = Ev.col;
+        const int64_t beg = Ev.sp[s], end = Ev.sp[s + 1];
+        for (int64_t p = beg + lane; p < end; p += WAVE) acc += (AT)val[p] * ye[col[p]];
+    }
     if (K > 1) acc = group_sum<K>(acc);
     if ((K > 1 && (lane & (K - 1))) || row >= n) return;
     const AT r = ((AT)(v[row] * sl[row]) - cdiag * xh[row]) - acc;
@@ -131,6 +137,14 @@ __global__ void k_first_jr(const int *__restrict__ stop, int64_t n, const double
     const AT r = (AT)(v[i] * sl[i]);
     if (final_) z[i] = sr[i] * (double)(w * r);
     else xh[i] = w * r;
+}
+
+template <typename AT>
+__global__ void k_copy_at(const int *__restrict__ stop, int64_t n, const AT *__restrict__ a, AT *__restrict__ b)
+{
+    if (stop && *stop) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
 }
 
 template <typename AT>
@@ -266,25 +280,28 @@ struct Launch {
     }
     template <int K>
     static void resid_k(const Handle &h, const Sell &P, const Sell *Q, const AT *xh, const double *v, AT cdiag, AT w,
-                        int dst, AT *rh, AT *xout, double *z, hipStream_t s)
+                        int dst, AT *rh, AT *xout, double *z, hipStream_t s, const AT *ye)
     {
         k_resid<VT, AT, K><<<grid_for(P.nslices), TB, 0, s>>>(h.stop, h.n, P.nslices, view(P), Q ? view(*Q) : view(P),
-                                                              Q ? 1 : 0, xh, v, h.sl, cdiag, w, dst, rh, xout, z, h.sr);
+                                                              Q ? 1 : 0, xh, v, h.sl, cdiag, w, dst, rh, xout, z, h.sr,
+                                                              ye ? view(h.E) : view(P), ye);
     }
+    // ye: values the off-block part E multiplies (NULL: no E term)
     static void resid(const Handle &h, const Sell &P, const Sell *Q, const AT *xh, const double *v, AT cdiag, AT w,
-                      int dst, AT *rh, AT *xout, double *z, hipStream_t s)
+                      int dst, AT *rh, AT *xout, double *z, hipStream_t s, const AT *ye = nullptr)
     {
         const double out = (dst == DST_ZADD || dst == DST_ZSET) ? 16.0 : (double)sizeof(AT);
         Prof pr(s, PK_RESID,
-                tri_bytes(P) + (Q ? tri_bytes(*Q) : 0.0) + (double)h.n * (16.0 + sizeof(AT) + out));
+                tri_bytes(P) + (Q ? tri_bytes(*Q) : 0.0) + (ye ? tri_bytes(h.E) + (double)h.n * sizeof(AT) : 0.0) +
+                    (double)h.n * (16.0 + sizeof(AT) + out));
         switch (P.K) {
-        case 1: resid_k<1>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 2: resid_k<2>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 4: resid_k<4>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 8: resid_k<8>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 16: resid_k<16>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 32: resid_k<32>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        default: resid_k<64>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
+        case 1: resid_k<1>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
+        case 2: resid_k<2>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
+        case 4: resid_k<4>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
+        case 8: resid_k<8>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
+        case 16: resid_k<16>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
+        case 32: resid_k<32>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
+        default: resid_k<64>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s, ye); break;
         }
     }
 
@@ -293,57 +310,87 @@ struct Launch {
     static int gs2(Handle &h, const double *v, double *z, hipStream_t s)
     {
         AT *xc = (AT *)h.xh, *xo = (AT *)h.xh2, *rh = (AT *)h.rh, *ga = (AT *)h.ga, *gb = (AT *)h.gb;
+        AT *y = (AT *)h.yh;
         const int per = h.variant == GS2_SYMMETRIC ? 2 : 1;
-        const int H = h.sweeps * per;
+        const bool hyb = h.blocks > 1;
+        const int nk = hyb ? h.local_sweeps : 1;
+        const int H = h.sweeps * nk * per;
         const AT w = (AT)h.omega;
         const AT cdiag = h.compact ? (AT)(1.0 - 1.0 / h.omega) : AT(1);
-        bool xzero = true;
-        for (int t = 0; t < H; ++t) {
-            const bool lower = h.variant == GS2_FORWARD || (h.variant == GS2_SYMMETRIC && (t % 2) == 0);
-            const Sell &T = lower ? h.L : h.U;
-            const Sell &O = lower ? h.U : h.L;
-            const bool fin = t == H - 1;
-            const bool set = xzero || h.compact; // x <- w g replaces x
-            if (h.inner == 0) {
-                if (xzero) {
-                    { Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (fin ? 16.0 : sizeof(AT)))); k_first_jr<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0, xc, z); }
-                } else {
-                    const int dst = fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
-                    if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, dst, nullptr, xo, z, s);
-                    else resid(h, T, &O, xc, v, cdiag, w, dst, nullptr, xo, z, s);
-                    std::swap(xc, xo);
-                }
-            } else {
-                int rv = 1;
-                if (!xzero) {
-                    if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s);
-                    else resid(h, T, &O, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s);
-                    rv = 0;
-                }
-                const AT *gin = rh;
-                for (int j = 1; j <= h.inner; ++j) {
-                    const bool last = j == h.inner;
-                    const int gv = (j == 1 && xzero) ? 1 : 0;
-                    AT *gout = (j & 1) ? ga : gb;
-                    const int dst = !last ? DST_G : fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
-                    inner(h, T, rh, gin, v, rv, gv, dst, gout, xc, z, s);
-                    gin = gout;
-                }
+        bool xzero = true, yzero = true;
+        int t = 0;
+        for (int ts = 0; ts < h.sweeps; ++ts) {
+            if (hyb && nk > 1) { // exchange: freeze the off-block values for the local sweeps
+                yzero = xzero;
+                if (!xzero) k_copy_at<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, xc, y);
             }
-            xzero = false;
+            for (int k = 0; k < nk; ++k)
+                for (int hf = 0; hf < per; ++hf, ++t) {
+                    const bool lower = h.variant == GS2_FORWARD || (h.variant == GS2_SYMMETRIC && hf == 0);
+                    const Sell &T = lower ? h.L : h.U;
+                    const Sell &O = lower ? h.U : h.L;
+                    const bool fin = t == H - 1;
+                    const bool set = xzero || h.compact; // x <- w g replaces x
+                    // off-block term: current iterate (one local sweep: global residual) or frozen copy
+                    const AT *ye = !hyb ? nullptr : nk > 1 ? (yzero ? nullptr : y) : xc;
+                    if (h.inner == 0) {
+                        if (xzero) {
+                            Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (fin ? 16.0 : sizeof(AT))));
+                            k_first_jr<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0,
+                                                                         xc, z);
+                        } else {
+                            const int dst = fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
+                            if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, dst, nullptr, xo, z, s);
+                            else resid(h, T, &O, xc, v, cdiag, w, dst, nullptr, xo, z, s, ye);
+                            std::swap(xc, xo);
+                        }
+                    } else {
+                        int rv = 1;
+                        if (!xzero) {
+                            if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s);
+                            else resid(h, T, &O, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s, ye);
+                            rv = 0;
+                        }
+                        const AT *gin = rh;
+                        for (int j = 1; j <= h.inner; ++j) {
+                            const bool last = j == h.inner;
+                            const int gv = (j == 1 && xzero) ? 1 : 0;
+                            AT *gout = (j & 1) ? ga : gb;
+                            const int dst =
+                                !last ? DST_G : fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
+                            inner(h, T, rh, gin, v, rv, gv, dst, gout, xc, z, s);
+                            gin = gout;
+                        }
+                    }
+                    xzero = false;
+                }
         }
         // keep the handle's notion of the current iterate buffer stable
         if (xc != (AT *)h.xh) std::swap(h.xh, h.xh2);
         return GS2_OK;
     }
 
+    // JR(n_t, n_k): `sweeps` global sweeps of n_k local sweeps each (one local
+    // sweep without blocks)
     static int jr(Handle &h, int sweeps, double omega, const double *v, double *z, hipStream_t s)
     {
-        AT *xc = (AT *)h.xh, *xo = (AT *)h.xh2;
+        AT *xc = (AT *)h.xh, *xo = (AT *)h.xh2, *y = (AT *)h.yh;
         const AT w = (AT)omega;
-        { Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (sweeps == 1 ? 16.0 : sizeof(AT)))); k_first_jr<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w, sweeps == 1 ? 1 : 0, xc, z); }
-        for (int t = 2; t <= sweeps; ++t) {
-            resid(h, h.L, &h.U, xc, v, AT(1), w, t == sweeps ? DST_ZADD : DST_XADD, nullptr, xo, z, s);
+        const bool hyb = h.blocks > 1;
+        const int nk = hyb ? h.local_sweeps : 1;
+        const int total = sweeps * nk;
+        {
+            Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (total == 1 ? 16.0 : sizeof(AT))));
+            k_first_jr<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w, total == 1 ? 1 : 0, xc, z);
+        }
+        bool yzero = true;
+        for (int step = 1; step < total; ++step) {
+            if (hyb && nk > 1 && step % nk == 0) {
+                k_copy_at<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, xc, y);
+                yzero = false;
+            }
+            const AT *ye = !hyb ? nullptr : nk > 1 ? (yzero ? nullptr : y) : xc;
+            resid(h, h.L, &h.U, xc, v, AT(1), w, step == total - 1 ? DST_ZADD : DST_XADD, nullptr, xo, z, s, ye);
             std::swap(xc, xo);
         }
         if (xc != (AT *)h.xh) std::swap(h.xh, h.xh2);

@@ -37,7 +37,8 @@ class CsrDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("inner_damping", C.c_double), ("compact", C.c_int),
                 ("build_levels", C.c_int), ("autotune", C.c_int), ("lanes_per_row", C.c_int),
-                ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int)]
+                ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int), ("blocks", C.c_int),
+                ("local_sweeps", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -166,10 +167,10 @@ class Handle:
 
 
 def gs2_setup(A: DeviceCSR, sweeps=1, inner=1, damping=1.0, variant=FORWARD, precision=FP64, inner_damping=1.0,
-              compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0,
-              stream=None) -> Handle:
+              compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0, blocks=1,
+              local_sweeps=1, stream=None) -> Handle:
     opt = Options(precision, inner_damping, int(compact), int(build_levels), int(autotune), lanes_per_row, 0,
-                  orthogonalization)
+                  orthogonalization, blocks, local_sweeps)
     out = C.c_void_p()
     d = A.desc()
     st = lib().gs2_setup(C.byref(d), sweeps, inner, damping, variant, C.byref(opt), _stream(stream), C.byref(out))
@@ -297,7 +298,7 @@ def gs2_setup_batched(mats, sweeps=2, inner=2, damping=1.0, variant=FORWARD, pre
                       stream=None) -> BatchHandle:
     """mats: list of DeviceCSR."""
     descs = (CsrDesc * len(mats))(*[m.desc() for m in mats])
-    opt = Options(precision, inner_damping, int(compact), 0, int(autotune), lanes_per_row, rhs_per_item)
+    opt = Options(precision, inner_damping, int(compact), 0, int(autotune), lanes_per_row, rhs_per_item, 0, 1, 1)
     out = C.c_void_p()
     st = lib().gs2_setup_batched(descs, len(mats), sweeps, inner, damping, variant, C.byref(opt), restart, nrhs,
                                  _stream(stream), C.byref(out))
