@@ -692,8 +692,10 @@ done:
  * A_loc x = b - E y, each a GS2 half (or a forward and a backward half)
  * whose inner JR sweeps use only the block's own triangle.  Coupling to
  * other blocks enters only through the frozen y (the multiple local sweeps
- * with a frozen halo of Section 3).  P = 1 is plain GS2; n_k = 1 uses the
- * global residual b - A x.
+ * with a frozen halo of Section 3).  The interface is exchanged once per
+ * global sweep (Fig. code:two-stage), so the backward half of a symmetric
+ * sweep also sees the frozen values.  P = 1 is plain GS2; a global sweep of a
+ * single forward or backward half uses the global residual b - A x.
  */
 static void block_half(const or_csr *A, const double *d, int bs, int lower, int inner, double w, double gamma,
                        const double *b, const double *y, double *x, double *r, double *g, double *gn)

@@ -318,9 +318,12 @@ struct Launch {
         const AT w = (AT)h.omega;
         const AT cdiag = h.compact ? (AT)(1.0 - 1.0 / h.omega) : AT(1);
         bool xzero = true, yzero = true;
+        // the interface is exchanged once per global sweep (Fig. code:two-stage), so every
+        // half of it sees the same off-block values; with a single half that is the live iterate
+        const bool freeze = hyb && nk * per > 1;
         int t = 0;
         for (int ts = 0; ts < h.sweeps; ++ts) {
-            if (hyb && nk > 1) { // exchange: freeze the off-block values for the local sweeps
+            if (freeze) { // exchange: freeze the off-block values for this global sweep
                 yzero = xzero;
                 if (!xzero) k_copy_at<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, xc, y);
             }
@@ -331,8 +334,8 @@ struct Launch {
                     const Sell &O = lower ? h.U : h.L;
                     const bool fin = t == H - 1;
                     const bool set = xzero || h.compact; // x <- w g replaces x
-                    // off-block term: current iterate (one local sweep: global residual) or frozen copy
-                    const AT *ye = !hyb ? nullptr : nk > 1 ? (yzero ? nullptr : y) : xc;
+                    // off-block term: frozen copy, or the live iterate when the global sweep has one half
+                    const AT *ye = !hyb ? nullptr : freeze ? (yzero ? nullptr : y) : xc;
                     if (h.inner == 0) {
                         if (xzero) {
                             Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (fin ? 16.0 : sizeof(AT))));
