@@ -161,19 +161,30 @@ int mtgs_apply(gs2_handle *h, int variant, double damping, const double *v, doub
 /*
  * Restarted flexible GMRES(restart), right-preconditioned, all Krylov
  * arithmetic in float64 (Arnoldi by classical Gram-Schmidt with one
- * reorthogonalisation, Givens rotations on the device, true residual at the
- * end of every cycle).  x: in = x0, out = solution (device).  b: device.
- * prec_kind GS2_PREC_* uses `prec` (GS2: gs2_apply; JR: the handle's sweeps
- * and damping; GS_TRISOLVE: gs_trisolve_apply with the handle's variant and
- * damping); prec may be NULL only for GS2_PREC_NONE.  Work vectors are cached
- * in `prec` (allocated once per restart length); with prec == NULL they are
- * allocated per call.  Converged when ||b - A x||/||b|| <= rtol; b = 0 gives
- * x = 0.  Synchronises `stream` once per restart cycle and before returning.
- * Returns GS2_OK, GS2_NOT_CONVERGED (maxit reached), GS2_BREAKDOWN, or an
- * error; `info` (host, may be NULL) is filled in every case.
+ * reorthogonalisation -- delayed, two passes over the basis per step, or
+ * plain CGS2 when the handle's orthogonalization is 1 --, Givens rotations on
+ * the device, true residual at the end of every cycle).  x: in = x0, out =
+ * solution (device).  b: device.  prec_kind GS2_PREC_* uses `prec` (GS2:
+ * gs2_apply; JR: the handle's sweeps and damping; GS_TRISOLVE and MTGS: the
+ * handle's variant and damping); prec may be NULL only for GS2_PREC_NONE.
+ * Work vectors are cached in `prec` (allocated once per restart length);
+ * with prec == NULL they are allocated per call.  Converged when
+ * ||b - A x||/||b|| <= rtol; b = 0 gives x = 0.  Synchronises `stream` once
+ * per restart cycle and before returning.  With a handle, a restart cycle is
+ * captured once into a HIP graph (keyed by A, b, x, handle, kind, restart,
+ * step count, rtol) and replayed (see gs2_graphs).  Returns GS2_OK,
+ * GS2_NOT_CONVERGED (maxit reached), GS2_BREAKDOWN, or an error; `info`
+ * (host, may be NULL) is filled in every case.
  */
 int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit, int prec_kind,
                 gs2_handle *prec, gs2_solve_info *info, void *stream);
+
+/*
+ * Process-wide switch for the graph replay of GMRES restart cycles: enable
+ * != 0 (the default) captures and replays, 0 launches every kernel one by
+ * one.  Both give bitwise identical results.  Returns the previous setting.
+ */
+int gs2_graphs(int enable);
 
 /*
  * Preconditioned conjugate gradients in float64 for symmetric positive
@@ -238,8 +249,9 @@ void gs2_destroy_batched(gs2_batch *bh);
  * stream, and tagged with the algorithmic bytes it must move (each stored
  * matrix entry and each vector element read or written once; sliced-ELL
  * padding not counted).  Launches of Arnoldi steps that the device skipped
- * after convergence are discarded.  Adds a few microseconds of host work
- * per launch; off by default.
+ * after convergence are discarded.  Inside a captured GMRES cycle the events
+ * become event-record nodes of the graph and are read after every replay.
+ * Adds a few microseconds of host work per launch; off by default.
  */
 
 /* enable != 0: clear previous records and start; 0: stop (records kept). */

@@ -4,7 +4,7 @@ The compute path is the HIP library libgs2.so (C ABI in include/gs2.h); this
 package only builds it and binds it through ctypes.
 """
 from .native import (  # noqa: F401
-    gs2_profile, gs2_profile_read,
+    gs2_profile, gs2_profile_read, gs2_graphs,
     BACKWARD, FORWARD, SYMMETRIC, FP16_SCALED, FP32, FP64,
     PREC_GS2, PREC_GS_TRISOLVE, PREC_JR, PREC_NONE, PREC_MTGS, mtgs_apply,
     DeviceCSR, Gs2Error, Handle, BatchHandle,

@@ -181,6 +181,11 @@ void prof_begin(hipStream_t s, int kid, double bytes);
 void prof_end(hipStream_t s);
 void prof_set_step(int cycle, int step);
 void prof_drop_from_step(int cycle, int kk);
+struct ProfSet; // event records captured into a graph
+void prof_capture_begin();
+ProfSet *prof_capture_end();
+void prof_accumulate(ProfSet *ps, int kk);
+void prof_free_set(ProfSet *ps);
 
 struct Prof {
     hipStream_t s;

@@ -1,15 +1,18 @@
 // Restarted flexible GMRES(m) in float64 (the Krylov solver the paper pairs
 // with GS2, Sections 1 and 8): right preconditioning with the preconditioned
 // vectors Z stored, Arnoldi by classical Gram-Schmidt with one full
-// reorthogonalisation (CGS2), Givens rotations applied on the device, and the
-// true residual ||b - A x|| at the end of every cycle.  The host synchronises
-// once per cycle; within a cycle every kernel reads a device-side stop flag
-// and returns at once after the residual estimate has met the tolerance.
+// reorthogonalisation (delayed: both passes folded into two sweeps over the
+// basis per step; or plain CGS2), Givens rotations applied on the device, and
+// the true residual ||b - A x|| at the end of every cycle.  The host
+// synchronises once per cycle; within a cycle every kernel reads a
+// device-side stop flag and returns at once after the residual estimate has
+// met the tolerance.  A cycle is captured once into a HIP graph and replayed.
 //
 // Reductions are deterministic: each workgroup writes one partial per
 // quantity (fixed row range, fixed butterfly), then one workgroup per
 // quantity sums the partials in a fixed order.  No floating-point atomics.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -21,6 +24,8 @@ namespace gs2 {
 constexpr int MAXM = 128;  // longest restart supported
 constexpr int RB = 1024;   // rows per workgroup in the vector kernels
 constexpr int KT = 256;    // threads per workgroup
+
+static std::atomic<int> g_graphs{1}; // replay restart cycles from HIP graphs
 
 struct GState {
     int j, done, kk, status;
@@ -40,6 +45,20 @@ struct GHeader {
     double bnorm, beta, rtol, inv;
 };
 
+// Everything a captured restart cycle bakes in.
+struct CycleKey {
+    const void *rp = nullptr, *ci = nullptr, *va = nullptr, *b = nullptr, *x = nullptr, *P = nullptr;
+    int kind = -1, m = 0, steps = 0;
+    double rtol = 0.0;
+    int orth = 0;
+    bool prof = false; // event-record nodes for per-kernel timing
+    bool operator==(const CycleKey &o) const
+    {
+        return rp == o.rp && ci == o.ci && va == o.va && b == o.b && x == o.x && P == o.P && kind == o.kind &&
+               m == o.m && steps == o.steps && rtol == o.rtol && orth == o.orth && prof == o.prof;
+    }
+};
+
 struct GmresWork {
     int64_t n = 0;
     int m = 0;
@@ -47,11 +66,47 @@ struct GmresWork {
     double *V = nullptr, *Z = nullptr, *w = nullptr, *w2 = nullptr, *part = nullptr;
     GState *st = nullptr;
     GHeader *hdr = nullptr; // pinned host copy
+    // HIP graph of one restart cycle (captured on its own stream, launched on the caller's)
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    CycleKey key;
+    ProfSet *pset = nullptr; // event records inside the graph (profiling on at capture)
 };
+
+template <typename F>
+static int capture_cycle(GmresWork *W, const CycleKey &key, F &&enqueue)
+{
+    if (W->exec) (void)hipGraphExecDestroy(W->exec);
+    if (W->graph) (void)hipGraphDestroy(W->graph);
+    prof_free_set(W->pset);
+    W->exec = nullptr;
+    W->graph = nullptr;
+    W->pset = nullptr;
+    if (!W->cap) GS2_TRY_HIP(hipStreamCreateWithFlags(&W->cap, hipStreamNonBlocking));
+    GS2_TRY_HIP(hipStreamBeginCapture(W->cap, hipStreamCaptureModeThreadLocal));
+    prof_capture_begin();
+    const int st = enqueue(W->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(W->cap, &g);
+    W->pset = prof_capture_end();
+    if (st != GS2_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != GS2_OK ? st : GS2_ERR_HIP;
+    }
+    W->graph = g;
+    GS2_TRY_HIP(hipGraphInstantiate(&W->exec, g, nullptr, nullptr, 0));
+    W->key = key;
+    return GS2_OK;
+}
 
 void free_gmres_work(GmresWork *g)
 {
     if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    prof_free_set(g->pset);
     for (void *p : {(void *)g->V, (void *)g->Z, (void *)g->w, (void *)g->w2, (void *)g->part, (void *)g->st})
         if (p) (void)hipFree(p);
     if (g->hdr) (void)hipHostFree(g->hdr);
@@ -284,18 +339,27 @@ __global__ __launch_bounds__(KT) void k_reduce(const double *__restrict__ part, 
 
 // Hessenberg column j = hA + hB, h_{j+1,j} = ||w||; apply the previous
 // rotations, form a new one, update the residual estimate g, and decide
-// whether the cycle stops (single thread; O(j) work).
-__global__ void k_givens(GState *__restrict__ st)
+// whether the cycle stops.  One wavefront stages the state in LDS, one lane
+// runs the O(j) serial recurrence on it.
+__global__ __launch_bounds__(WAVE) void k_givens(GState *__restrict__ st)
 {
-    if (threadIdx.x != 0 || st->done) return;
+    __shared__ double c[MAXM + 2], cs[MAXM], sn[MAXM];
+    if (st->done) return;
     const int j = st->j;
-    double *c = st->hA;
-    for (int k = 0; k <= j; ++k) c[k] += st->hB[k];
+    for (int k = threadIdx.x; k <= j; k += WAVE) {
+        c[k] = st->hA[k] + st->hB[k];
+        if (k < j) {
+            cs[k] = st->cs[k];
+            sn[k] = st->sn[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const double hn = sqrt(st->nrm[0]);
     const double wn0 = sqrt(st->hA[j + 1]); // ||A z_j|| (slot j+1 of the first pass)
     for (int k = 0; k < j; ++k) {
-        const double a = st->cs[k] * c[k] + st->sn[k] * c[k + 1];
-        c[k + 1] = -st->sn[k] * c[k] + st->cs[k] * c[k + 1];
+        const double a = cs[k] * c[k] + sn[k] * c[k + 1];
+        c[k + 1] = -sn[k] * c[k] + cs[k] * c[k + 1];
         c[k] = a;
     }
     const double rho = hypot(c[j], hn);
@@ -424,13 +488,29 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(int64_t n, const int32_t *__re
         part[(int64_t)k * nb + blockIdx.x] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
 }
 
-// Apply the committed rotations 0..jc-1 to col (jc+2 entries), form rotation
-// jc, store column jc of R and advance the residual recurrence g.
-__device__ bool commit_column(GState *st, double *col, int jc)
+// The small per-step scalar kernels are latency-bound: every value they need
+// is first copied from the device state into LDS by a whole wavefront, then
+// one lane runs the (inherently serial) rotation recurrence on LDS.
+struct RotLds {
+    double cs[MAXM], sn[MAXM], col[MAXM + 2];
+};
+
+__device__ void stage_rotations(const GState *st, RotLds &R, int cnt)
+{
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        R.cs[k] = st->cs[k];
+        R.sn[k] = st->sn[k];
+    }
+}
+
+// (one lane) Apply the committed rotations 0..jc-1 to col (jc+2 entries),
+// form rotation jc, store column jc of R and advance the residual
+// recurrence g.
+__device__ bool commit_column(GState *st, RotLds &R, double *col, int jc)
 {
     for (int k = 0; k < jc; ++k) {
-        const double a = st->cs[k] * col[k] + st->sn[k] * col[k + 1];
-        col[k + 1] = -st->sn[k] * col[k] + st->cs[k] * col[k + 1];
+        const double a = R.cs[k] * col[k] + R.sn[k] * col[k + 1];
+        col[k + 1] = -R.sn[k] * col[k] + R.cs[k] * col[k + 1];
         col[k] = a;
     }
     const double rho = hypot(col[jc], col[jc + 1]);
@@ -442,59 +522,81 @@ __device__ bool commit_column(GState *st, double *col, int jc)
         st->status = GS2_BREAKDOWN;
         return false;
     }
-    st->cs[jc] = col[jc] / rho;
-    st->sn[jc] = col[jc + 1] / rho;
+    const double c = col[jc] / rho, sn = col[jc + 1] / rho;
+    st->cs[jc] = c;
+    st->sn[jc] = sn;
+    R.cs[jc] = c;
+    R.sn[jc] = sn;
     col[jc] = rho;
     for (int k = 0; k <= jc; ++k) st->H[k * MAXM + jc] = col[k];
-    st->g[jc + 1] = -st->sn[jc] * st->g[jc];
-    st->g[jc] = st->cs[jc] * st->g[jc];
+    const double gj = st->g[jc];
+    st->g[jc + 1] = -sn * gj;
+    st->g[jc] = c * gj;
     return true;
 }
 
 // Between the passes: reorthogonalisation scalars of u, correction and
-// commit of column j-1, the new tentative column j (single thread).
-__global__ void k_dcgs_scalar(GState *__restrict__ st)
+// commit of column j-1, the new tentative column j (one wavefront).
+__global__ __launch_bounds__(WAVE) void k_dcgs_scalar(GState *__restrict__ st)
 {
-    if (threadIdx.x != 0 || st->done) return;
-    const int j = st->j;
-    double col[MAXM + 2];
+    __shared__ RotLds R;
+    __shared__ double ht[MAXM + 2], ha[MAXM + 2];
+    const int done = st->done, j = st->j;
+    if (done) return;
+    const int t = threadIdx.x;
     if (j == 0) {
-        st->inv_alpha = 1.0;
-        st->e = st->dd;
-        st->ht[0] = st->dd;
+        if (t == 0) {
+            st->inv_alpha = 1.0;
+            st->e = st->dd;
+            st->ht[0] = st->dd;
+        }
         return;
     }
+    stage_rotations(st, R, j);
     double aa = 0.0, ac = 0.0;
-    for (int k = 0; k < j; ++k) {
-        aa += st->hA[k] * st->hA[k];
-        ac += st->hA[k] * st->hB[k];
+    for (int k = t; k < j; k += WAVE) {
+        const double a = st->hA[k], c = st->hB[k];
+        ha[k] = a;
+        ht[k] = st->ht[k];
+        aa += a * a;
+        ac += a * c;
     }
+    aa = wave_sum(aa);
+    ac = wave_sum(ac);
+    __syncthreads(); // LDS copies complete (one wavefront: also orders the lanes)
     const double a2 = st->bb - aa;
+    const bool ok = isfinite(a2) && a2 > 0.0;
+    // new tentative column j: c (all lanes; lane 0 reads the old one from LDS only)
+    if (ok)
+        for (int k = t; k < j; k += WAVE) st->ht[k] = st->hB[k];
+    if (t != 0) return;
+    const double nu = st->nu;
+    double *col = R.col;
     if (!isfinite(a2)) {
         st->status = GS2_ERR_NONFINITE;
         st->done = 1;
         st->kk = j - 1;
         return;
     }
-    if (!(a2 > 0.0)) { // u fell into span(Q): end the cycle on the tentative column j-1
-        for (int k = 0; k < j; ++k) col[k] = st->ht[k];
-        col[j] = st->nu;
-        st->kk = commit_column(st, col, j - 1) ? j : j - 1;
+    if (!ok) { // u fell into span(Q): end the cycle on the tentative column j-1
+        for (int k = 0; k < j; ++k) col[k] = ht[k];
+        col[j] = nu;
+        st->kk = commit_column(st, R, col, j - 1) ? j : j - 1;
         st->done = 1;
         return;
     }
     const double alpha = sqrt(a2);
-    for (int k = 0; k < j; ++k) col[k] = st->ht[k] + st->nu * st->hA[k];
-    col[j] = st->nu * alpha;
-    if (!commit_column(st, col, j - 1)) {
+    for (int k = 0; k < j; ++k) col[k] = ht[k] + nu * ha[k];
+    col[j] = nu * alpha;
+    if (!commit_column(st, R, col, j - 1)) {
         st->kk = j - 1;
         st->done = 1;
         return;
     }
+    const double e = (st->dd - ac) / alpha;
     st->inv_alpha = 1.0 / alpha;
-    st->e = (st->dd - ac) / alpha;
-    for (int k = 0; k < j; ++k) st->ht[k] = st->hB[k];
-    st->ht[j] = st->e;
+    st->e = e;
+    st->ht[j] = e;
 }
 
 // Pass 2: q_j = (u - Q a)/alpha over u's slot, w' = w - Q c - e q_j into
@@ -516,18 +618,34 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
     double s = 0.0;
     double *__restrict__ u = V + (int64_t)j * ldv;
     double *__restrict__ wn = V + (int64_t)(j + 1) * ldv;
+    constexpr int NQ = RB / KT;
+    // rows past n are clamped to n-1 for loads and skipped for stores
+    int64_t rows[NQ];
+    double aq[NQ], aw[NQ];
 #pragma unroll
-    for (int q = 0; q < RB / KT; ++q) {
+    for (int q = 0; q < NQ; ++q) {
+        const int64_t row = r0 + threadIdx.x + q * KT;
+        rows[q] = row < n ? row : n - 1;
+        aq[q] = u[rows[q]];
+        aw[q] = w[rows[q]];
+    }
+#pragma unroll 2
+    for (int k = 0; k < j; ++k) {
+        const double *__restrict__ vk = V + (int64_t)k * ldv;
+        const double a = as[k], c = cs_[k];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double x = vk[rows[q]];
+            aq[q] -= a * x;
+            aw[q] -= c * x;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
         const int64_t row = r0 + threadIdx.x + q * KT;
         if (row >= n) continue;
-        double aq = u[row], aw = w[row];
-        for (int k = 0; k < j; ++k) {
-            const double vk = V[(int64_t)k * ldv + row];
-            aq -= as[k] * vk;
-            aw -= cs_[k] * vk;
-        }
-        const double qv = aq * ia;
-        const double wp = aw - e * qv;
+        const double qv = aq[q] * ia;
+        const double wp = aw[q] - e * qv;
         u[row] = qv;
         wn[row] = wp;
         s += wp * wp;
@@ -540,20 +658,24 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
     __shared__ double red[4];
+    __shared__ RotLds R;
+    __shared__ double ht[MAXM + 2];
     if (st->done) return;
+    const int j = st->j;
+    stage_rotations(st, R, j);
+    for (int k = threadIdx.x; k <= j; k += KT) ht[k] = st->ht[k];
     double s = 0.0;
     for (int b = threadIdx.x; b < nb; b += KT) s += part[b];
-    s = block_sum(s, red);
+    s = block_sum(s, red); // also orders the LDS staging
     if (threadIdx.x != 0) return;
-    const int j = st->j;
     const double nu = sqrt(s);
     st->nu = nu;
-    double col[MAXM + 2];
-    for (int k = 0; k <= j; ++k) col[k] = st->ht[k];
+    double *col = R.col;
+    for (int k = 0; k <= j; ++k) col[k] = ht[k];
     col[j + 1] = nu;
     for (int k = 0; k < j; ++k) {
-        const double a = st->cs[k] * col[k] + st->sn[k] * col[k + 1];
-        col[k + 1] = -st->sn[k] * col[k] + st->cs[k] * col[k + 1];
+        const double a = R.cs[k] * col[k] + R.sn[k] * col[k + 1];
+        col[k + 1] = -R.sn[k] * col[k] + R.cs[k] * col[k + 1];
         col[k] = a;
     }
     const double rho = hypot(col[j], col[j + 1]);
@@ -567,9 +689,9 @@ __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ p
     const bool breakdown = nu <= 1e-14 * sqrt(st->wn2);
     st->kk = j + 1;
     if (est <= st->rtol * st->bnorm || breakdown || j + 1 >= st->maxsteps) {
-        for (int k = 0; k <= j; ++k) col[k] = st->ht[k];
+        for (int k = 0; k <= j; ++k) col[k] = ht[k];
         col[j + 1] = nu;
-        if (!commit_column(st, col, j)) st->kk = j;
+        if (!commit_column(st, R, col, j)) st->kk = j;
         st->done = 1;
     } else {
         st->inv = 1.0 / nu;
@@ -744,7 +866,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     // z_j is always a copy: the delayed variant rewrites v_j after z_j was formed
     double *Zb = W->Z;
     int total = 0, cycles = 0, status = GS2_OK;
-    bool have_prev = false;
+    bool have_prev = false, replayed = false;
     // algorithmic bytes: CSR SpMV with A, and one pass over nk Krylov vectors
     const double spmv_b = 12.0 * (double)A.nnz + 4.0 * (n + 1) + 16.0 * n;
     const double red_b = 8.0 * nb;
@@ -762,7 +884,8 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         GS2_TRY(read_hdr());
         if (have_prev) {
             total += hdr->kk;
-            prof_drop_from_step(cycles - 1, hdr->kk);
+            if (replayed) prof_accumulate(W->pset, hdr->kk);
+            else prof_drop_from_step(cycles - 1, hdr->kk);
             if (hdr->status != GS2_OK) { status = hdr->status; break; }
         }
         const double beta = hdr->beta;
@@ -773,87 +896,104 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         if (cycles > 0) info->restarts++;
         cycles++;
         const int steps = std::min(m, maxit - total);
-        k_cycle_init<<<1, 64, 0, s>>>(st, steps, rtol);
-        k_scale0<<<gE, 256, 0, s>>>(n, W->V, st);
-        for (int j = 0; j < steps; ++j) {
-            prof_set_step(cycles - 1, j);
-            const double *vj = W->V + (int64_t)j * n;
-            double *zj = Zb + (int64_t)j * n;
-            const double vb = 8.0 * n * (j + 1);
-            if (orth == 0) { // delayed CGS2
-                if (j > 0) {
-                    Prof pr(s, PK_SCALE, 16.0 * n);
-                    k_normalize<<<gE, 256, 0, s>>>(n, W->V, n, st);
+        // one restart cycle, enqueued on stream `cs`
+        auto enqueue_cycle = [&](hipStream_t cs) -> int {
+            k_cycle_init<<<1, 64, 0, cs>>>(st, steps, rtol);
+            k_scale0<<<gE, 256, 0, cs>>>(n, W->V, st);
+            for (int j = 0; j < steps; ++j) {
+                prof_set_step(cycles - 1, j);
+                const double *vj = W->V + (int64_t)j * n;
+                double *zj = Zb + (int64_t)j * n;
+                const double vb = 8.0 * n * (j + 1);
+                if (orth == 0) { // delayed CGS2
+                    if (j > 0) {
+                        Prof pr(cs, PK_SCALE, 16.0 * n);
+                        k_normalize<<<gE, 256, 0, cs>>>(n, W->V, n, st);
+                    }
+                    GS2_TRY(precondition(kind, P, vj, zj, n, st, cs));
+                    {
+                        Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
+                        hipStream_t s = cs;
+                        GS2_SPMV_DISPATCH(K, k_spmv_dot2, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st,
+                                          W->part, nb);
+                    }
+                    {
+                        Prof pr(cs, PK_REDUCE, red_b * (2 * j + 3));
+                        k_reduce<<<2 * j + 3, KT, 0, cs>>>(W->part, nb, st, 3, 0, 2 * j + 3);
+                    }
+                    {
+                        Prof pr(cs, PK_GIVENS, 0.0);
+                        k_dcgs_scalar<<<1, 64, 0, cs>>>(st);
+                    }
+                    {
+                        Prof pr(cs, PK_CGS, 8.0 * n * (j + 4));
+                        k_dcgs_update<<<gN, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
+                    }
+                    {
+                        Prof pr(cs, PK_GIVENS, red_b);
+                        k_dcgs_finish<<<1, KT, 0, cs>>>(W->part, nb, st);
+                    }
+                    GS2_TRY_HIP(hipGetLastError());
+                    continue;
                 }
-                GS2_TRY(precondition(kind, P, vj, zj, n, st, s));
-                {
-                    Prof pr(s, PK_SPMV_DOT, spmv_b + vb);
-                    GS2_SPMV_DISPATCH(K, k_spmv_dot2, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st,
-                                      W->part, nb);
+                GS2_TRY(precondition(kind, P, vj, zj, n, st, cs));
+                {   // w = A z_j, hA = V^T w, ||w||^2
+                    Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
+                    hipStream_t s = cs;
+                    GS2_SPMV_DISPATCH(K, k_spmv_dot, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st,
+                                      W->part, nb, 0);
                 }
                 {
-                    Prof pr(s, PK_REDUCE, red_b * (2 * j + 3));
-                    k_reduce<<<2 * j + 3, KT, 0, s>>>(W->part, nb, st, 3, 0, 2 * j + 3);
+                    Prof pr(cs, PK_REDUCE, red_b * (j + 2));
+                    k_reduce<<<j + 2, KT, 0, cs>>>(W->part, nb, st, 0, 1, 0);
+                }
+                {   // w2 = w - V hA ; hB = V^T w2
+                    Prof pr(cs, PK_CGS, vb + 16.0 * n);
+                    k_update_dot<<<gN, KT, 0, cs>>>(n, W->V, n, st, 0, W->w, W->w2, 1, 0, W->part, nb);
                 }
                 {
-                    Prof pr(s, PK_GIVENS, 0.0);
-                    k_dcgs_scalar<<<1, 64, 0, s>>>(st);
+                    Prof pr(cs, PK_REDUCE, red_b * (j + 1));
+                    k_reduce<<<j + 1, KT, 0, cs>>>(W->part, nb, st, 1, 0, 0);
+                }
+                {   // v_{j+1} = w2 - V hB ; ||v_{j+1}||^2
+                    Prof pr(cs, PK_CGS, vb + 16.0 * n);
+                    k_update_dot<<<gN, KT, 0, cs>>>(n, W->V, n, st, 1, W->w2, W->V + (int64_t)(j + 1) * n, 0, 1,
+                                                    W->part, nb);
                 }
                 {
-                    Prof pr(s, PK_CGS, 8.0 * n * (j + 4));
-                    k_dcgs_update<<<gN, KT, 0, s>>>(n, W->V, n, st, W->w, W->part);
+                    Prof pr(cs, PK_REDUCE, red_b);
+                    k_reduce<<<1, KT, 0, cs>>>(W->part, nb, st, 2, 0, 1);
                 }
                 {
-                    Prof pr(s, PK_GIVENS, red_b);
-                    k_dcgs_finish<<<1, KT, 0, s>>>(W->part, nb, st);
+                    Prof pr(cs, PK_GIVENS, 0.0);
+                    k_givens<<<1, 64, 0, cs>>>(st);
+                }
+                {
+                    Prof pr(cs, PK_SCALE, 16.0 * n);
+                    k_scale_next<<<gE, 256, 0, cs>>>(n, W->V, n, st);
                 }
                 GS2_TRY_HIP(hipGetLastError());
-                continue;
             }
-            GS2_TRY(precondition(kind, P, vj, zj, n, st, s));
-            {   // w = A z_j, hA = V^T w, ||w||^2
-                Prof pr(s, PK_SPMV_DOT, spmv_b + vb);
-                GS2_SPMV_DISPATCH(K, k_spmv_dot, gN, n, A.rowptr, A.colind, A.val, zj, W->w, W->V, n, st, W->part,
-                                  nb, 0);
-            }
+            prof_set_step(cycles - 1, -1);
+            k_backsolve<<<1, 64, 0, cs>>>(st);
             {
-                Prof pr(s, PK_REDUCE, red_b * (j + 2));
-                k_reduce<<<j + 2, KT, 0, s>>>(W->part, nb, st, 0, 1, 0);
-            }
-            {   // w2 = w - V hA ; hB = V^T w2
-                Prof pr(s, PK_CGS, vb + 16.0 * n);
-                k_update_dot<<<gN, KT, 0, s>>>(n, W->V, n, st, 0, W->w, W->w2, 1, 0, W->part, nb);
-            }
-            {
-                Prof pr(s, PK_REDUCE, red_b * (j + 1));
-                k_reduce<<<j + 1, KT, 0, s>>>(W->part, nb, st, 1, 0, 0);
-            }
-            {   // v_{j+1} = w2 - V hB ; ||v_{j+1}||^2
-                Prof pr(s, PK_CGS, vb + 16.0 * n);
-                k_update_dot<<<gN, KT, 0, s>>>(n, W->V, n, st, 1, W->w2, W->V + (int64_t)(j + 1) * n, 0, 1, W->part,
-                                               nb);
-            }
-            {
-                Prof pr(s, PK_REDUCE, red_b);
-                k_reduce<<<1, KT, 0, s>>>(W->part, nb, st, 2, 0, 1);
-            }
-            {
-                Prof pr(s, PK_GIVENS, 0.0);
-                k_givens<<<1, 64, 0, s>>>(st);
-            }
-            {
-                Prof pr(s, PK_SCALE, 16.0 * n);
-                k_scale_next<<<gE, 256, 0, s>>>(n, W->V, n, st);
+                Prof pr(cs, PK_UPDATE_X, 8.0 * n * steps + 16.0 * n);
+                k_update_x<<<gE, KT, 0, cs>>>(n, Zb, n, st, x);
             }
             GS2_TRY_HIP(hipGetLastError());
+            return GS2_OK;
+        };
+        // Replay the cycle from a HIP graph, captured once per set of pointers
+        // and parameters (with a handle: its work space outlives the call).
+        // Profiling events captured with the cycle are read after each replay.
+        replayed = P && g_graphs.load();
+        if (replayed) {
+            const CycleKey key{A.rowptr, A.colind, A.val, b, x, P, kind, m, steps, rtol, orth, prof_on()};
+            if (!(W->exec && W->key == key)) GS2_TRY(capture_cycle(W, key, enqueue_cycle));
+            GS2_TRY_HIP(hipGraphLaunch(W->exec, s));
+        } else {
+            GS2_TRY(enqueue_cycle(s));
         }
-        prof_set_step(cycles - 1, -1);
-        k_backsolve<<<1, 64, 0, s>>>(st);
-        {
-            Prof pr(s, PK_UPDATE_X, 8.0 * n * steps + 16.0 * n);
-            k_update_x<<<gE, KT, 0, s>>>(n, Zb, n, st, x);
-        }
-        GS2_TRY_HIP(hipGetLastError());
         have_prev = true;
     }
     prof_set_step(0, -1);
@@ -864,6 +1004,8 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
 } // namespace gs2
 
 using namespace gs2;
+
+extern "C" int gs2_graphs(int enable) { return g_graphs.exchange(enable != 0 ? 1 : 0); }
 
 extern "C" int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit,
                            int prec_kind, gs2_handle *prec, gs2_solve_info *info, void *stream)

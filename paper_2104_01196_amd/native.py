@@ -77,6 +77,7 @@ def lib():
         ip = C.POINTER(C.c_int)
         L.gs2_handle_query.argtypes = [vp, i64p, i64p, i64p, i64p, ip, ip, ip]
         L.gs2_profile.argtypes = [i]
+        L.gs2_graphs.argtypes = [i]
         L.gs2_profile_kernel_count.argtypes = []
         L.gs2_profile_read.argtypes = [i, C.POINTER(C.c_char_p), i64p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         if hasattr(L, "gs2_setup_batched"):
@@ -263,6 +264,11 @@ def gs2_handle_query(h: Handle) -> dict:
 
 def gs2_profile(enable: bool):
     lib().gs2_profile(1 if enable else 0)
+
+
+def gs2_graphs(enable: bool) -> bool:
+    """Switch the HIP-graph replay of GMRES restart cycles; returns the previous setting."""
+    return bool(lib().gs2_graphs(1 if enable else 0))
 
 
 def gs2_profile_read() -> dict:
