@@ -172,7 +172,8 @@ int mtgs_apply(gs2_handle *h, int variant, double damping, const double *v, doub
  * ||b - A x||/||b|| <= rtol; b = 0 gives x = 0.  Synchronises `stream` once
  * per restart cycle and before returning.  With a handle, a restart cycle is
  * captured once into a HIP graph (keyed by A, b, x, handle, kind, restart,
- * step count, rtol) and replayed (see gs2_graphs).  Returns GS2_OK,
+ * step count, rtol) and replayed (see gs2_graphs; not while gs2_profile is
+ * on).  Returns GS2_OK,
  * GS2_NOT_CONVERGED (maxit reached), GS2_BREAKDOWN, or an error; `info`
  * (host, may be NULL) is filled in every case.
  */
@@ -249,9 +250,10 @@ void gs2_destroy_batched(gs2_batch *bh);
  * stream, and tagged with the algorithmic bytes it must move (each stored
  * matrix entry and each vector element read or written once; sliced-ELL
  * padding not counted).  Launches of Arnoldi steps that the device skipped
- * after convergence are discarded.  Inside a captured GMRES cycle the events
- * become event-record nodes of the graph and are read after every replay.
- * Adds a few microseconds of host work per launch; off by default.
+ * after convergence are discarded.  While enabled, GMRES launches its
+ * kernels one by one instead of replaying its captured graph (events inside
+ * a replayed graph do not give usable intervals).  Adds a few microseconds of
+ * host work per launch; off by default.
  */
 
 /* enable != 0: clear previous records and start; 0: stop (records kept). */

@@ -68,20 +68,60 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks)
     return x * q + (x < r ? x : r) + k;
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_xor(T v, int m)
+// Cross-lane data movement within a DPP row (16 lanes) uses the DPP operand
+// modifiers of the VALU instead of LDS-routed permutes.  Controls (CDNA ISA,
+// DPP_CTRL): quad_perm [1,0,3,2] = lane ^ 1, quad_perm [2,3,0,1] = lane ^ 2,
+// row_half_mirror = 7 - lane within each half row, row_mirror = 15 - lane
+// within each row.  Lanes whose source is inactive read 0.
+enum : int { DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
 {
-    return __shfl_xor(v, m, WAVE);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+__device__ __forceinline__ float read_lane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // Sum over a group of K consecutive lanes (K a power of two <= 64); every
-// lane of the group receives the sum.  The butterfly order is fixed, so the
-// result is deterministic.
+// lane of the group receives the sum.  Up to 16 lanes: pairs, quads, half
+// rows and rows are combined with DPP moves (after each step every lane of
+// the group holds the same value: the two operands of each addition are the
+// same pair of partial sums).  Across rows the four row sums are read into
+// scalar registers and added in a fixed order.  All 64 lanes must be active.
 template <int K, typename T>
 __device__ __forceinline__ T group_sum(T v)
 {
-#pragma unroll
-    for (int o = K / 2; o > 0; o >>= 1) v += shfl_xor(v, o);
+    static_assert(K >= 1 && K <= WAVE && (K & (K - 1)) == 0, "K must be a power of two <= 64");
+    if constexpr (K >= 2) v += dpp_move<DPP_XOR1>(v);
+    if constexpr (K >= 4) v += dpp_move<DPP_XOR2>(v);
+    if constexpr (K >= 8) v += dpp_move<DPP_HALF_MIRROR>(v);
+    if constexpr (K >= 16) v += dpp_move<DPP_MIRROR>(v);
+    if constexpr (K == 32) {
+        const T a = read_lane(v, 0) + read_lane(v, 16), b = read_lane(v, 32) + read_lane(v, 48);
+        v = (threadIdx.x & 32) ? b : a;
+    }
+    if constexpr (K == 64) v = (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
     return v;
 }
 
@@ -181,11 +221,6 @@ void prof_begin(hipStream_t s, int kid, double bytes);
 void prof_end(hipStream_t s);
 void prof_set_step(int cycle, int step);
 void prof_drop_from_step(int cycle, int kk);
-struct ProfSet; // event records captured into a graph
-void prof_capture_begin();
-ProfSet *prof_capture_end();
-void prof_accumulate(ProfSet *ps, int kk);
-void prof_free_set(ProfSet *ps);
 
 struct Prof {
     hipStream_t s;

@@ -51,11 +51,10 @@ struct CycleKey {
     int kind = -1, m = 0, steps = 0;
     double rtol = 0.0;
     int orth = 0;
-    bool prof = false; // event-record nodes for per-kernel timing
     bool operator==(const CycleKey &o) const
     {
         return rp == o.rp && ci == o.ci && va == o.va && b == o.b && x == o.x && P == o.P && kind == o.kind &&
-               m == o.m && steps == o.steps && rtol == o.rtol && orth == o.orth && prof == o.prof;
+               m == o.m && steps == o.steps && rtol == o.rtol && orth == o.orth;
     }
 };
 
@@ -71,7 +70,6 @@ struct GmresWork {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     CycleKey key;
-    ProfSet *pset = nullptr; // event records inside the graph (profiling on at capture)
 };
 
 template <typename F>
@@ -79,17 +77,13 @@ static int capture_cycle(GmresWork *W, const CycleKey &key, F &&enqueue)
 {
     if (W->exec) (void)hipGraphExecDestroy(W->exec);
     if (W->graph) (void)hipGraphDestroy(W->graph);
-    prof_free_set(W->pset);
     W->exec = nullptr;
     W->graph = nullptr;
-    W->pset = nullptr;
     if (!W->cap) GS2_TRY_HIP(hipStreamCreateWithFlags(&W->cap, hipStreamNonBlocking));
     GS2_TRY_HIP(hipStreamBeginCapture(W->cap, hipStreamCaptureModeThreadLocal));
-    prof_capture_begin();
     const int st = enqueue(W->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(W->cap, &g);
-    W->pset = prof_capture_end();
     if (st != GS2_OK || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return st != GS2_OK ? st : GS2_ERR_HIP;
@@ -106,7 +100,6 @@ void free_gmres_work(GmresWork *g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->cap) (void)hipStreamDestroy(g->cap);
-    prof_free_set(g->pset);
     for (void *p : {(void *)g->V, (void *)g->Z, (void *)g->w, (void *)g->w2, (void *)g->part, (void *)g->st})
         if (p) (void)hipFree(p);
     if (g->hdr) (void)hipHostFree(g->hdr);
@@ -129,7 +122,7 @@ static int alloc_work(GmresWork **out, int64_t n, int m)
     A((void **)&g->Z, sizeof(double) * N * m);
     A((void **)&g->w, sizeof(double) * N);
     A((void **)&g->w2, sizeof(double) * N);
-    A((void **)&g->part, sizeof(double) * (size_t)g->nb * (MAXM + 2));
+    A((void **)&g->part, sizeof(double) * (size_t)g->nb * (2 * MAXM + 3)); // delayed CGS2: 2j+3 per block
     A((void **)&g->st, sizeof(GState));
     if (st == GS2_OK && hipHostMalloc((void **)&g->hdr, sizeof(GHeader), hipHostMallocDefault) != hipSuccess)
         st = GS2_ERR_NOMEM;
@@ -157,44 +150,72 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
-// partial dots of the rows [r0, r0 + RB) held in wl (LDS) against V[0..nk),
-// plus the squared norm of wl when with_norm; written k-major: part[k*nb + b].
-__device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const double *wl, const double *__restrict__ V,
-                                               int64_t ldv, int nk, int with_norm, double *__restrict__ part, int nb,
-                                               double *red /* [MAXM+2][4] */)
+// Partial dots of the block's rows [r0, r0 + RB) against the basis vectors
+// V[0..nk).  The block's values a (and b when TWO) sit in LDS, zero past n.
+// The basis is split over the wavefronts (wave w takes k = w, w+4, ...) and
+// each lane covers RL = RB/64 rows of a vector, so one cross-lane reduction
+// serves RL loaded values and a wavefront keeps RL independent loads in
+// flight.  Rows past n are clamped to the last row for loading (their factor
+// is zero).  Results go to LDS: ra[k] = V_k.a, rb[k] = V_k.b.  The wavefront
+// with the fewest vectors (the last) also forms a.a, a.b and b.b into
+// rn[0..2] when with_norms.
+constexpr int RL = RB / WAVE;
+
+template <bool TWO>
+__device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const double *al, const double *bl,
+                                               const double *__restrict__ V, int64_t ldv, int nk, bool with_norms,
+                                               double *ra, double *rb, double *rn)
 {
-    const int t = threadIdx.x, wv = t / WAVE, ln = t & (WAVE - 1);
-    double wr[RB / KT];
+    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
+    const int last = (int)(n - 1 - r0 < RB - 1 ? n - 1 - r0 : RB - 1);
+    double ar[RL], br[RL];
 #pragma unroll
-    for (int u = 0; u < RB / KT; ++u) {
-        const int64_t row = r0 + t + u * KT;
-        wr[u] = row < n ? wl[t + u * KT] : 0.0;
+    for (int s = 0; s < RL; ++s) {
+        ar[s] = al[ln + s * WAVE];
+        br[s] = TWO ? bl[ln + s * WAVE] : 0.0;
     }
-    for (int k = 0; k < nk; ++k) {
-        const double *__restrict__ vk = V + (int64_t)k * ldv;
-        double s = 0.0;
+    for (int k = wv; k < nk; k += KT / WAVE) {
+        const double *__restrict__ vk = V + (int64_t)k * ldv + r0;
+        double sa = 0.0, sb = 0.0;
 #pragma unroll
-        for (int u = 0; u < RB / KT; ++u) {
-            const int64_t row = r0 + t + u * KT;
-            if (row < n) s += vk[row] * wr[u];
+        for (int s = 0; s < RL; ++s) {
+            const int i = ln + s * WAVE;
+            const double x = vk[i < last ? i : last];
+            sa += x * ar[s];
+            if (TWO) sb += x * br[s];
         }
-        s = wave_sum(s);
-        if (ln == 0) red[k * 4 + wv] = s;
+        sa = wave_sum(sa);
+        if (TWO) sb = wave_sum(sb);
+        if (ln == 0) {
+            ra[k] = sa;
+            if (TWO) rb[k] = sb;
+        }
     }
-    if (with_norm) {
-        double s = 0.0;
+    if (with_norms && wv == KT / WAVE - 1) {
+        double aa = 0.0, ab = 0.0, bb = 0.0;
 #pragma unroll
-        for (int u = 0; u < RB / KT; ++u) s += wr[u] * wr[u];
-        s = wave_sum(s);
-        if (ln == 0) red[nk * 4 + wv] = s;
+        for (int s = 0; s < RL; ++s) {
+            aa += ar[s] * ar[s];
+            if (TWO) {
+                ab += ar[s] * br[s];
+                bb += br[s] * br[s];
+            }
+        }
+        aa = wave_sum(aa);
+        if (TWO) {
+            ab = wave_sum(ab);
+            bb = wave_sum(bb);
+        }
+        if (ln == 0) {
+            rn[0] = aa;
+            rn[1] = ab;
+            rn[2] = bb;
+        }
     }
-    __syncthreads();
-    const int tot = nk + (with_norm ? 1 : 0);
-    for (int k = t; k < tot; k += KT)
-        part[(int64_t)k * nb + blockIdx.x] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
 }
 
-// w = A z (CSR, K lanes per row) fused with h = V^T w and ||w||^2 partials.
+// w = A z (CSR, K lanes per row) fused with h = V^T w and ||w||^2 partials,
+// written k-major: part[k*nb + b], the norm at k = nk.
 template <int K>
 __global__ __launch_bounds__(KT) void k_spmv_dot(int64_t n, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci, const double *__restrict__ va,
@@ -203,7 +224,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot(int64_t n, const int32_t *__res
                                                  double *__restrict__ part, int nb, int fixed_nk)
 {
     __shared__ double wl[RB];
-    __shared__ double red[(MAXM + 2) * 4];
+    __shared__ double ra[MAXM + 2], rn[3];
     if (st && st->done) return;
     const int nk = st ? st->j + 1 : fixed_nk;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
@@ -224,7 +245,9 @@ __global__ __launch_bounds__(KT) void k_spmv_dot(int64_t n, const int32_t *__res
         }
     }
     __syncthreads();
-    block_multidot(n, r0, wl, V, ldv, nk, 1, part, nb, red);
+    block_multidot<false>(n, r0, wl, nullptr, V, ldv, nk, true, ra, nullptr, rn);
+    __syncthreads();
+    for (int k = t; k <= nk; k += KT) part[(int64_t)k * nb + blockIdx.x] = k < nk ? ra[k] : rn[0];
 }
 
 // r = b - A x written to out, with ||r||^2 partials.
@@ -235,7 +258,7 @@ __global__ __launch_bounds__(KT) void k_true_resid(int64_t n, const int32_t *__r
                                                    double *__restrict__ out, double *__restrict__ part, int nb)
 {
     __shared__ double wl[RB];
-    __shared__ double red[4 * 4];
+    __shared__ double red[KT / WAVE];
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x, q = t & (K - 1);
     constexpr int RPP = KT / K;
@@ -254,8 +277,12 @@ __global__ __launch_bounds__(KT) void k_true_resid(int64_t n, const int32_t *__r
             if (row < n) out[row] = r;
         }
     }
-    __syncthreads();
-    block_multidot(n, r0, wl, nullptr, 0, 0, 1, part, nb, red);
+    __syncthreads(); // wl rows were written by other threads
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < RB / KT; ++u) s += wl[t + u * KT] * wl[t + u * KT];
+    s = block_sum(s, red);
+    if (t == 0) part[blockIdx.x] = s;
 }
 
 // ||b||^2 partials
@@ -273,15 +300,15 @@ __global__ __launch_bounds__(KT) void k_norm_part(int64_t n, const double *__res
 }
 
 // CGS pass: wout = win - V h (h = first nk entries of hsrc), then partial
-// dots V^T wout (and ||wout||^2 if with_norm).  wout may be a column of V.
+// dots V^T wout (and ||wout||^2 if with_norm, at k = nk or 0).  wout may be a
+// column of V past the first nk.
 __global__ __launch_bounds__(KT) void k_update_dot(int64_t n, const double *__restrict__ V, int64_t ldv,
                                                    const GState *__restrict__ st, int which_h,
                                                    const double *__restrict__ win, double *__restrict__ wout,
                                                    int do_dot, int with_norm, double *__restrict__ part, int nb)
 {
     __shared__ double wl[RB];
-    __shared__ double red[(MAXM + 2) * 4];
-    __shared__ double hs[MAXM + 2];
+    __shared__ double ra[MAXM + 2], rn[3], hs[MAXM + 2];
     if (st->done) return;
     const int nk = st->j + 1;
     const double *hsrc = which_h == 0 ? st->hA : st->hB;
@@ -289,19 +316,37 @@ __global__ __launch_bounds__(KT) void k_update_dot(int64_t n, const double *__re
     __syncthreads();
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x;
+    const int last = (int)(n - 1 - r0 < RB - 1 ? n - 1 - r0 : RB - 1);
+    constexpr int NQ = RB / KT;
+    double acc[NQ];
 #pragma unroll
-    for (int u = 0; u < RB / KT; ++u) {
-        const int64_t row = r0 + t + u * KT;
-        double acc = 0.0;
-        if (row < n) {
-            acc = win[row];
-            for (int k = 0; k < nk; ++k) acc -= hs[k] * V[(int64_t)k * ldv + row];
-            wout[row] = acc;
+    for (int u = 0; u < NQ; ++u) {
+        const int i = t + u * KT;
+        acc[u] = win[r0 + (i < last ? i : last)];
+    }
+    for (int k = 0; k < nk; ++k) { // k outer: NQ independent loads per vector
+        const double h = hs[k];
+        const double *__restrict__ vk = V + (int64_t)k * ldv + r0;
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int i = t + u * KT;
+            acc[u] -= h * vk[i < last ? i : last];
         }
-        wl[t + u * KT] = acc;
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int i = t + u * KT;
+        const bool in = i <= last;
+        if (in) wout[r0 + i] = acc[u];
+        wl[i] = in ? acc[u] : 0.0;
     }
     __syncthreads();
-    if (do_dot || with_norm) block_multidot(n, r0, wl, V, ldv, do_dot ? nk : 0, with_norm, part, nb, red);
+    if (!do_dot && !with_norm) return;
+    const int cnt = do_dot ? nk : 0;
+    block_multidot<false>(n, r0, wl, nullptr, V, ldv, cnt, with_norm != 0, ra, nullptr, rn);
+    __syncthreads();
+    for (int k = t; k < cnt + (with_norm ? 1 : 0); k += KT)
+        part[(int64_t)k * nb + blockIdx.x] = k < cnt ? ra[k] : rn[0];
 }
 
 // out[k] = sum_b part[k*nb + b] for k < cnt (one workgroup per k).  dst
@@ -418,8 +463,8 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(int64_t n, const int32_t *__re
                                                   const double *__restrict__ V, int64_t ldv,
                                                   const GState *__restrict__ st, double *__restrict__ part, int nb)
 {
-    __shared__ double wl[RB];
-    __shared__ double red[(2 * MAXM + 3) * 4];
+    __shared__ double wl[RB], ul[RB];
+    __shared__ double ra[MAXM + 2], rc[MAXM + 2], rn[3];
     if (st->done) return;
     const int j = st->j;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
@@ -439,53 +484,14 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(int64_t n, const int32_t *__re
             if (row < n) w[row] = acc;
         }
     }
-    __syncthreads();
-    const int wv = t / WAVE, ln = t & (WAVE - 1);
     const double *__restrict__ u = V + (int64_t)j * ldv;
-    double wr[RB / KT], ur[RB / KT];
-#pragma unroll
-    for (int s = 0; s < RB / KT; ++s) {
-        const int64_t row = r0 + t + s * KT;
-        wr[s] = row < n ? wl[t + s * KT] : 0.0;
-        ur[s] = row < n ? u[row] : 0.0;
-    }
-    for (int k = 0; k < j; ++k) {
-        const double *__restrict__ vk = V + (int64_t)k * ldv;
-        double sa = 0.0, sc = 0.0;
-#pragma unroll
-        for (int s = 0; s < RB / KT; ++s) {
-            const int64_t row = r0 + t + s * KT;
-            if (row < n) {
-                const double x = vk[row];
-                sa += x * ur[s];
-                sc += x * wr[s];
-            }
-        }
-        sa = wave_sum(sa);
-        sc = wave_sum(sc);
-        if (ln == 0) {
-            red[k * 4 + wv] = sa;
-            red[(j + k) * 4 + wv] = sc;
-        }
-    }
-    double sb = 0.0, sd = 0.0, sw = 0.0;
-#pragma unroll
-    for (int s = 0; s < RB / KT; ++s) {
-        sb += ur[s] * ur[s];
-        sd += ur[s] * wr[s];
-        sw += wr[s] * wr[s];
-    }
-    sb = wave_sum(sb);
-    sd = wave_sum(sd);
-    sw = wave_sum(sw);
-    if (ln == 0) {
-        red[(2 * j) * 4 + wv] = sb;
-        red[(2 * j + 1) * 4 + wv] = sd;
-        red[(2 * j + 2) * 4 + wv] = sw;
-    }
+    for (int i = t; i < RB; i += KT) ul[i] = r0 + i < n ? u[r0 + i] : 0.0;
+    __syncthreads();
+    // a = Q^T u, c = Q^T w (Q = V[0..j)), then u.u, u.w, w.w
+    block_multidot<true>(n, r0, ul, wl, V, ldv, j, true, ra, rc, rn);
     __syncthreads();
     for (int k = t; k < 2 * j + 3; k += KT)
-        part[(int64_t)k * nb + blockIdx.x] = ((red[k * 4 + 0] + red[k * 4 + 1]) + red[k * 4 + 2]) + red[k * 4 + 3];
+        part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
 }
 
 // The small per-step scalar kernels are latency-bound: every value they need
@@ -866,7 +872,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     // z_j is always a copy: the delayed variant rewrites v_j after z_j was formed
     double *Zb = W->Z;
     int total = 0, cycles = 0, status = GS2_OK;
-    bool have_prev = false, replayed = false;
+    bool have_prev = false;
     // algorithmic bytes: CSR SpMV with A, and one pass over nk Krylov vectors
     const double spmv_b = 12.0 * (double)A.nnz + 4.0 * (n + 1) + 16.0 * n;
     const double red_b = 8.0 * nb;
@@ -884,8 +890,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         GS2_TRY(read_hdr());
         if (have_prev) {
             total += hdr->kk;
-            if (replayed) prof_accumulate(W->pset, hdr->kk);
-            else prof_drop_from_step(cycles - 1, hdr->kk);
+            prof_drop_from_step(cycles - 1, hdr->kk);
             if (hdr->status != GS2_OK) { status = hdr->status; break; }
         }
         const double beta = hdr->beta;
@@ -985,10 +990,9 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         };
         // Replay the cycle from a HIP graph, captured once per set of pointers
         // and parameters (with a handle: its work space outlives the call).
-        // Profiling events captured with the cycle are read after each replay.
-        replayed = P && g_graphs.load();
-        if (replayed) {
-            const CycleKey key{A.rowptr, A.colind, A.val, b, x, P, kind, m, steps, rtol, orth, prof_on()};
+        // Per-kernel event profiling needs the launches one by one.
+        if (P && g_graphs.load() && !prof_on()) {
+            const CycleKey key{A.rowptr, A.colind, A.val, b, x, P, kind, m, steps, rtol, orth};
             if (!(W->exec && W->key == key)) GS2_TRY(capture_cycle(W, key, enqueue_cycle));
             GS2_TRY_HIP(hipGraphLaunch(W->exec, s));
         } else {

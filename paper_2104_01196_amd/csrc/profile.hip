@@ -4,7 +4,10 @@
 // when on, every library kernel launch is bracketed by a pair of events.
 // Launches of Arnoldi steps that the device skipped (after the residual
 // estimate met the tolerance) are dropped once the cycle's step count is
-// known, so averages cover executed launches only.
+// known, so averages cover executed launches only.  While profiling is on,
+// GMRES launches its kernels one by one instead of replaying a captured
+// graph: event-record nodes inside a replayed HIP graph do not give usable
+// pairwise timings (observed: negative intervals).
 #include <algorithm>
 #include <vector>
 
@@ -28,17 +31,6 @@ static int g_cycle = 0, g_step = -1;
 static std::vector<ProfRec> g_recs;
 static std::vector<hipEvent_t> g_pool;
 static std::mutex g_mu;
-// graph capture: records made while a stream is captured become event-record
-// nodes of the graph; their times are accumulated after every replay
-static bool g_capturing = false;
-static std::vector<ProfRec> g_cap;
-static double g_acc_ms[NKID], g_acc_bytes[NKID];
-static int64_t g_acc_n[NKID];
-
-struct ProfSet {
-    std::vector<ProfRec> recs;
-};
-
 static hipEvent_t get_event()
 {
     if (!g_pool.empty()) {
@@ -59,59 +51,14 @@ void prof_begin(hipStream_t s, int kid, double bytes)
     std::lock_guard<std::mutex> lk(g_mu);
     ProfRec r{kid, g_cycle, g_step, bytes, get_event(), get_event()};
     if (r.e0) (void)hipEventRecord(r.e0, s);
-    (g_capturing ? g_cap : g_recs).push_back(r);
+    g_recs.push_back(r);
 }
 
 void prof_end(hipStream_t s)
 {
     if (!g_on) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    std::vector<ProfRec> &v = g_capturing ? g_cap : g_recs;
-    if (!v.empty() && v.back().e1) (void)hipEventRecord(v.back().e1, s);
-}
-
-void prof_capture_begin()
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_capturing = true;
-    g_cap.clear();
-}
-
-ProfSet *prof_capture_end()
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_capturing = false;
-    if (g_cap.empty()) return nullptr;
-    ProfSet *ps = new (std::nothrow) ProfSet;
-    if (ps) ps->recs.swap(g_cap);
-    g_cap.clear();
-    return ps;
-}
-
-// after a replay has completed: add the executed steps (< kk) of the
-// captured records to the per-kernel totals
-void prof_accumulate(ProfSet *ps, int kk)
-{
-    if (!ps || !g_on) return;
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (const ProfRec &r : ps->recs) {
-        if (r.step >= kk || !r.e0 || !r.e1) continue;
-        float x = 0.f;
-        if (hipEventElapsedTime(&x, r.e0, r.e1) != hipSuccess) continue;
-        g_acc_ms[r.kid] += x;
-        g_acc_bytes[r.kid] += r.bytes;
-        g_acc_n[r.kid] += 1;
-    }
-}
-
-void prof_free_set(ProfSet *ps)
-{
-    if (!ps) return;
-    for (const ProfRec &r : ps->recs) {
-        if (r.e0) (void)hipEventDestroy(r.e0);
-        if (r.e1) (void)hipEventDestroy(r.e1);
-    }
-    delete ps;
+    if (!g_recs.empty() && g_recs.back().e1) (void)hipEventRecord(g_recs.back().e1, s);
 }
 
 void prof_set_step(int cycle, int step)
@@ -154,11 +101,6 @@ int gs2_profile(int enable)
         g_recs.clear();
         g_cycle = 0;
         g_step = -1;
-        for (int k = 0; k < NKID; ++k) {
-            g_acc_ms[k] = 0.0;
-            g_acc_bytes[k] = 0.0;
-            g_acc_n[k] = 0;
-        }
     }
     g_on = enable != 0;
     return GS2_OK;
@@ -169,8 +111,8 @@ int gs2_profile_read(int kid, const char **name, int64_t *launches, double *ms, 
     if (kid < 0 || kid >= NKID) return GS2_ERR_ARG;
     if (name) *name = KNAMES[kid];
     std::lock_guard<std::mutex> lk(g_mu);
-    int64_t cnt = g_acc_n[kid];
-    double t = g_acc_ms[kid], b = g_acc_bytes[kid];
+    int64_t cnt = 0;
+    double t = 0.0, b = 0.0;
     for (const ProfRec &r : g_recs) {
         if (r.kid != kid || !r.e0 || !r.e1) continue;
         if (hipEventSynchronize(r.e1) != hipSuccess) return GS2_ERR_HIP;

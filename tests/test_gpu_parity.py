@@ -297,6 +297,24 @@ def test_gmres_orthogonalization_variants(orth, cfg, size, m, kw):
     assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) <= 1e-5
 
 
+@pytest.mark.parametrize("orth", [0, 1])
+def test_gmres_long_restart(orth):
+    """A cycle of more than 64 Arnoldi steps (up to the longest supported
+    restart, 128): the delayed variant keeps 2j+3 partial sums per workgroup."""
+    p = config_problem(1, size=36)  # 118 steps in one cycle
+    A, b = p["A"], p["b"]
+    xo, io = oracle.gmres(A, b, restart=128, rtol=1e-10, prec="jr", sweeps=1)
+    assert io["iterations"] > 100 and io["restarts"] == 0
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 0, 1.0, g.FORWARD, orthogonalization=orth)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 128, 1e-10, 5000, g.PREC_JR, h)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    xh = host(x)
+    assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-10
+    assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) <= 1e-6
+
+
 def test_gmres_status_paths():
     p = config_problem(1, size=16)
     A, b = p["A"], p["b"]
