@@ -44,6 +44,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def stream_ceiling(torch, nbytes=1 << 31, reps=5):
+    """Measured HBM ceiling: device-to-device copy of nbytes (read + write
+    counted), best of reps, timed with events on torch's stream."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -136,13 +154,16 @@ def main():
         tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_laplace3d_{args.size}.json")
         if os.path.exists(tf):
             traffic = json.load(open(tf)).get("hbm_bytes_per_launch")
+        ceiling = stream_ceiling(torch)
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                "stream_copy_GBps": ceiling, "frac_of_stream_copy": ach / ceiling,
                 "algorithmic_bytes_per_launch": r["bytes"] / r["launches"],
                 "avg_launch_us": r["ms"] / r["launches"] * 1e3,
                 "measured": f"HIP events around every launch in {args.steps} profiled solves (kernel by kernel, "
                             f"{prof_solve_s * 1e3:.2f} ms/solve) after the timed graph-replayed solves"}
-        log(f"[bench] dominant kernel {dom}: {ach:.0f} GB/s ({100 * ach / HBM_PEAK_GBS:.1f}% of peak)")
+        log(f"[bench] dominant kernel {dom}: {ach:.0f} GB/s ({100 * ach / HBM_PEAK_GBS:.1f}% of peak, "
+            f"{100 * ach / ceiling:.1f}% of the measured {ceiling:.0f} GB/s copy)")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgs2.so")
-SOURCES = ["setup.hip", "sweep.hip", "krylov.hip", "cg.hip", "batched.hip", "profile.hip"]
+SOURCES = ["setup.hip", "sweep.hip", "sella.hip", "krylov.hip", "cg.hip", "batched.hip", "profile.hip"]
 ARCH = os.environ.get("GS2_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

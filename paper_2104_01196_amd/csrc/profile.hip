@@ -38,8 +38,9 @@ static hipEvent_t get_event()
         g_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (cache writeback) when recorded
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
