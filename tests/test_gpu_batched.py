@@ -151,4 +151,8 @@ def test_batched_full_size_sampled():
         for r in (0, 3):
             xo, io = oracle.gmres(mats[i], rhs[i][:, r], restart=20, rtol=1e-8, prec="gs2", sweeps=2, inner=2,
                                   precision=oracle.FP32)
-            assert abs(infos[i * 4 + r]["iterations"] - io["iterations"]) <= 1
+            # Long restarted runs (hundreds of steps in GMRES(20)) with a float32
+            # preconditioner: both sides round every apply to float32, in different
+            # summation orders, and the restarts amplify those differences into
+            # slightly different histories; the bar is 1% of the count (>= 1).
+            assert abs(infos[i * 4 + r]["iterations"] - io["iterations"]) <= max(1, io["iterations"] // 100)

@@ -315,6 +315,47 @@ def test_gmres_long_restart(orth):
     assert np.linalg.norm(xh - xo) / np.linalg.norm(xo) <= 1e-6
 
 
+@pytest.mark.parametrize("name", ["rand_long_rows", "convdiff_37", "rand_negdiag"])
+def test_gmres_general_matrices(name):
+    """GMRES's SpMV runs on a sliced-ELL copy of A: a few long rows (151
+    entries against a mean of 8) make it widen the lanes per row; nonsymmetric
+    and negative-diagonal matrices take the same path."""
+    A, dA = mat(name)
+    b = A.to_scipy() @ vec(A.n, 21)
+    xo, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", sweeps=1, inner=1)
+    assert io["converged"]
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 30, 1e-8, 20000, g.PREC_GS2, h)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    xh = host(x)
+    assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
+
+
+def test_gmres_matrix_values_changed_in_place():
+    """The sliced-ELL copy of A is keyed by its pattern arrays and its values
+    are copied again by every solve: scaling A's values in place (same
+    arrays) and b with them must give the original solution, and a second
+    copy of A (new arrays) must give bitwise the same result."""
+    p = config_problem(1, size=40)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD)
+    x1 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    i1 = g.gmres_solve(dA, dev(b), x1, 20, 1e-10, 5000, g.PREC_GS2, h)
+    dA.val.mul_(2.0)
+    x2 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    i2 = g.gmres_solve(dA, dev(2.0 * b), x2, 20, 1e-10, 5000, g.PREC_GS2, h)
+    assert i1["converged"] and i2["converged"] and i2["iterations"] == i1["iterations"]
+    xh = host(x2)
+    assert np.linalg.norm(2.0 * b - 2.0 * (A.to_scipy() @ xh)) / np.linalg.norm(2.0 * b) <= 1e-10
+    assert np.linalg.norm(xh - p["x_true"]) / np.linalg.norm(p["x_true"]) <= 1e-6
+    dB = g.DeviceCSR.from_host(A)  # original values, new arrays
+    x3 = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    g.gmres_solve(dB, dev(b), x3, 20, 1e-10, 5000, g.PREC_GS2, h)
+    assert torch.equal(x3, x1)
+
+
 def test_gmres_status_paths():
     p = config_problem(1, size=16)
     A, b = p["A"], p["b"]
