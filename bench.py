@@ -11,7 +11,15 @@ solution of the float64-preconditioner solve over the timed steps (median and
 spread reported with it); the float32 and scaled-float16 preconditioner
 solves are timed the same way and reported next to it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 128]
+Two further measurements print their own JSON line (not the default):
+--config 4 times the precision forms (FP64 / FP32 / scaled-FP16 SGS2(1,1)
+preconditioner, GMRES(50)) on the 192^3 variable-coefficient diffusion
+problem; --config 5 times the batched persistent solver (512 uneven
+convection-diffusion systems x 4 right-hand sides, GS2(2,2), GMRES(20),
+FP32 and FP64 preconditioner) against the plain FP64 path that solves the
+2048 systems one gmres_solve at a time.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--config 2|4|5]
 """
 from __future__ import annotations
 
@@ -32,7 +40,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--size", type=int, default=128, help="grid side of the 3D Laplacian")
+    ap.add_argument("--size", type=int, default=None, help="grid side (default: the configuration's)")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 4, 5],
+                    help="2: the benchmark workload (default); 4: precision forms on the 192^3 variable-coefficient "
+                         "problem; 5: batched form on 512 convection-diffusion systems x 4 right-hand sides")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16 preconditioner solves")
     ap.add_argument("--profile", choices=["on", "off"], default="on",
@@ -73,14 +84,27 @@ def main():
     import paper_2104_01196_amd as g
     from gen import config_problem
 
+    if args.config == 5:
+        return bench_batched(args, g, torch, np)
     dev = torch.device("cuda:0")
     t0 = time.time()
-    p = config_problem(2, size=args.size)
+    cfg = args.config
+    size = args.size or (128 if cfg == 2 else 192)
+    p = config_problem(cfg, size=size)
     A, b = p["A"], p["b"]
-    log(f"[bench] generated laplace3d {args.size}^3: n={A.n} nnz={A.nnz} ({time.time() - t0:.1f}s)")
+    log(f"[bench] generated config {cfg}, side {size}: n={A.n} nnz={A.nnz} ({time.time() - t0:.1f}s)")
+    # preconditioner: forward GS2(2 sweeps, 1 inner) for the benchmark workload;
+    # symmetric GS2(1, 1) for the precision forms (the paper's mixed-precision setting)
+    pv, psw, pin = (g.FORWARD, 2, 1) if cfg == 2 else (g.SYMMETRIC, 1, 1)
     dA = g.DeviceCSR.from_host(A, dev)
     db = torch.as_tensor(b, device=dev)
     restart, rtol, maxit = 50, 1e-8, 20000
+    if cfg == 2:
+        wname = f"laplace3d_{size}"
+        workload = f"laplace3d_7pt_{size}^3 GS2-forward(2 sweeps,1 inner) GMRES(50) rtol 1e-8"
+    else:
+        wname = f"vardiff3d_{size}"
+        workload = f"vardiff3d_7pt_{size}^3 kappa logU[1e-2,1e2] SGS2(1 sweep,1 inner) GMRES(50) rtol 1e-8"
 
     def solve(h, x):
         x.zero_()
@@ -94,7 +118,7 @@ def main():
     prof_solve_s = None
     for name, prec in forms:
         ts = time.time()
-        h = g.gs2_setup(dA, 2, 1, 1.0, g.FORWARD, precision=prec)
+        h = g.gs2_setup(dA, psw, pin, 1.0, pv, precision=prec)
         torch.cuda.synchronize()
         setup_s = time.time() - ts
         lanes = g.gs2_handle_query(h)["lanes_per_row"]
@@ -151,7 +175,7 @@ def main():
         r = prof[dom]
         ach = (r["bytes"] / r["launches"]) / ((r["ms"] / r["launches"]) * 1e-3) / 1e9
         traffic = None
-        tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_laplace3d_{args.size}.json")
+        tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{wname}.json")
         if os.path.exists(tf):
             traffic = json.load(open(tf)).get("hbm_bytes_per_launch")
         ceiling = stream_ceiling(torch)
@@ -166,13 +190,13 @@ def main():
             f"{100 * ach / ceiling:.1f}% of the measured {ceiling:.0f} GB/s copy)")
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and cfg == 2:
         import oracle
 
         nthreads = 1
         sample_steps = restart
         _, oi = oracle.gmres(A, b, restart=restart, rtol=rtol, maxit=sample_steps, prec="gs2",
-                             variant=oracle.FORWARD, sweeps=2, inner=1)
+                             variant=pv, sweeps=psw, inner=pin)
         per_step = oi["seconds"] / max(oi["iterations"], 1)
         cpu = {"value": per_step * head["iterations"], "unit": "s", "cores": nthreads, "kind": "oracle",
                "sample": f"first GMRES(50) cycle ({oi['iterations']} Arnoldi steps, {oi['seconds']:.1f}s) of the "
@@ -192,12 +216,108 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"laplace3d_7pt_{args.size}^3 GS2-forward(2 sweeps,1 inner) GMRES(50) rtol 1e-8",
-                   "n": A.n, "nnz": A.nnz, "restart": restart, "rtol": rtol},
+        "config": {"workload": workload, "n": A.n, "nnz": A.nnz, "restart": restart, "rtol": rtol},
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": results,
         "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args, g, torch, np):
+    """Batched form: every (system, right-hand side) pair of the 512-system
+    workload in one persistent launch, against the plain FP64 path (one
+    gs2_setup per system, one gmres_solve per pair)."""
+    from gen import config_problem
+
+    t0 = time.time()
+    p = config_problem(5, size=args.size)
+    mats, rhs = p["mats"], p["rhs"]
+    nrhs, restart, rtol, maxit = rhs[0].shape[1], 20, 1e-8, 20000
+    log(f"[bench] generated {len(mats)} systems, {sum(A.n for A in mats)} rows ({time.time() - t0:.1f}s)")
+    dm = [g.DeviceCSR.from_host(A) for A in mats]
+    B = torch.as_tensor(np.concatenate([r.ravel() for r in rhs]), device="cuda")
+    X = torch.zeros_like(B)
+    S = [A.to_scipy() for A in mats]
+
+    def check(Xh):
+        worst, off = 0.0, 0
+        for A, Sa, r in zip(mats, S, rhs):
+            x = Xh[off:off + A.n * nrhs].reshape(A.n, nrhs)
+            off += A.n * nrhs
+            worst = max(worst, float(np.max(np.linalg.norm(r - Sa @ x, axis=0) / np.linalg.norm(r, axis=0))))
+        return worst
+
+    res = {}
+    for name, prec in (("batched_fp32", g.FP32), ("batched_fp64", g.FP64)):
+        ts = time.time()
+        bh = g.gs2_setup_batched(dm, sweeps=2, inner=2, precision=prec, restart=restart, nrhs=nrhs)
+        torch.cuda.synchronize()
+        setup_s = time.time() - ts
+        for _ in range(args.warmup):
+            X.zero_()
+            g.gmres_solve_batched(bh, nrhs, B, X, rtol, maxit)
+        each = []
+        for _ in range(args.steps):
+            X.zero_()
+            torch.cuda.synchronize()
+            te = time.perf_counter()
+            st, infos = g.gmres_solve_batched(bh, nrhs, B, X, rtol, maxit)
+            torch.cuda.synchronize()
+            each.append(time.perf_counter() - te)
+        its = [f["iterations"] for f in infos]
+        res[name] = {"time_s": float(np.mean(each)), "median_s": float(np.median(each)), "min_s": min(each),
+                     "max_s": max(each), "setup_s": setup_s, "status": st, "iterations_max": max(its),
+                     "iterations_mean": float(np.mean(its)), "worst_relres_true": check(X.cpu().numpy())}
+        log(f"[bench] {name}: {res[name]['time_s'] * 1e3:.1f} ms for all {len(its)} pairs, its mean "
+            f"{res[name]['iterations_mean']:.0f} max {max(its)}, worst relres {res[name]['worst_relres_true']:.2e}")
+        del bh
+
+    # plain FP64 path: one handle per system, one solve per pair (per-system b/x
+    # buffers so each system's captured restart cycle is replayed for all its pairs)
+    ts = time.time()
+    hs = [g.gs2_setup(d, 2, 2, 1.0, g.FORWARD, precision=g.FP64) for d in dm]
+    bb = [torch.empty(A.n, dtype=torch.float64, device="cuda") for A in mats]
+    xb = [torch.empty(A.n, dtype=torch.float64, device="cuda") for A in mats]
+    torch.cuda.synchronize()
+    setup_s = time.time() - ts
+    Xs = torch.zeros_like(B)
+
+    def sequential():
+        its, off = [], 0
+        for i, A in enumerate(mats):
+            blk = B[off:off + A.n * nrhs].view(A.n, nrhs)
+            out = Xs[off:off + A.n * nrhs].view(A.n, nrhs)
+            for r in range(nrhs):
+                bb[i].copy_(blk[:, r])
+                xb[i].zero_()
+                its.append(g.gmres_solve(dm[i], bb[i], xb[i], restart, rtol, maxit, g.PREC_GS2, hs[i])["iterations"])
+                out[:, r].copy_(xb[i])
+            off += A.n * nrhs
+        return its
+
+    sequential()  # warmup: captures each system's cycle graph
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    its = sequential()
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - te
+    res["sequential_fp64"] = {"time_s": seq, "setup_s": setup_s, "iterations_max": max(its),
+                              "iterations_mean": float(np.mean(its)), "worst_relres_true": check(Xs.cpu().numpy())}
+    log(f"[bench] sequential_fp64: {seq * 1e3:.1f} ms, its mean {np.mean(its):.0f} max {max(its)}, worst relres "
+        f"{res['sequential_fp64']['worst_relres_true']:.2e}")
+    head = res["batched_fp32"]
+    out = {
+        "metric": "GS2-GMRES time-to-solution (s), batched form vs plain FP64 form",
+        "value": head["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["time_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 preconditioner / f64 Krylov", "data": "synthetic",
+        "config": {"workload": "512 convdiff2d upwind systems (sides U{16..256}, Pe U(0,50)) x 4 RHS, GS2(2,2) "
+                               "FP32 preconditioner, GMRES(20) FP64, rtol 1e-8, one persistent launch",
+                   "systems": len(mats), "rows": sum(A.n for A in mats), "nrhs": nrhs},
+        "forms": res,
+        "speedup_vs_sequential_fp64": seq / head["time_s"],
     }
     print(json.dumps(out), flush=True)
 
