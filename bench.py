@@ -55,6 +55,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_digest():
+    """sha256 of the HIP sources and the ABI header: counter-based traffic
+    figures are used only when they were taken on the kernels built now."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2104_01196_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_2104_01196_amd", "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "gs2.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def stream_ceiling(torch, nbytes=1 << 31, reps=5):
     """Measured HBM ceiling: device-to-device copy of nbytes (read + write
     counted), best of reps, timed with events on torch's stream."""
@@ -177,7 +193,11 @@ def main():
         traffic = None
         tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{wname}.json")
         if os.path.exists(tf):
-            traffic = json.load(open(tf)).get("hbm_bytes_per_launch")
+            rec = json.load(open(tf))
+            if rec.get("source_sha256") == source_digest():
+                traffic = rec.get("hbm_bytes_per_launch")
+            else:
+                log(f"[bench] {tf} was measured on other kernel sources: traffic reported as null")
         ceiling = stream_ceiling(torch)
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic,

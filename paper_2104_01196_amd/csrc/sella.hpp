@@ -42,7 +42,9 @@ void sella_free(SellA &S);
 // ybuf[i] = (A z)[r0 + i] for the RB rows of the workgroup starting at r0
 // (0 past n), into LDS.  The workgroup's NW wavefronts take consecutive
 // groups of RB / C / NW slices; each wavefront works on four slices at once
-// so that their loads are in flight together.  Ends with a barrier.
+// so that their loads are in flight together.  The matrix is streamed with
+// non-temporal loads, which leaves the caches to the gathered z.  Ends with
+// a barrier.
 template <int K, int RB, int NW>
 __device__ __forceinline__ void sella_rows(const SellAView A, int64_t n, int64_t r0, const double *__restrict__ z,
                                            double *ybuf)
@@ -73,7 +75,7 @@ __device__ __forceinline__ void sella_rows(const SellAView A, int64_t n, int64_t
             for (int u = 0; u < U; ++u) {
                 if (t < steps[u]) {
                     const int64_t p = beg[u] + (int64_t)t * WAVE + ln;
-                    acc[u] += A.val[p] * z[A.col[p]];
+                    acc[u] += __builtin_nontemporal_load(&A.val[p]) * z[__builtin_nontemporal_load(&A.col[p])];
                 }
             }
         }

@@ -85,7 +85,10 @@ __global__ __launch_bounds__(256) void k_inner(const int *__restrict__ stop, int
 // unit diagonal).  compact = 1: rh = S_l v - O xh - (1 - 1/w) xh with O the
 // triangle opposite to the inner one (eq. (two-stage-3) with damping).
 // The result goes to rh (DST_G) or is fused into a Jacobi-type update of xh
-// written to xout (double-buffered: xh is gathered here).
+// written to xout (double-buffered: xh is gathered here).  The triangles are
+// loaded non-temporally here (the gathered xh keeps the caches); the inner
+// pass keeps the default policy, since the following inner pass re-reads its
+// triangle (measured faster both ways).
 template <typename VT, typename AT, int K>
 __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView P, SellView Q, int two,
                                                const AT *__restrict__ xh, const double *__restrict__ v,
@@ -104,14 +107,16 @@ __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int
         const int32_t *__restrict__ col = P.col;
         const int64_t beg = P.sp[s], end = P.sp[s + 1];
 #pragma unroll 4
-        for (int64_t p = beg + lane; p < end; p += WAVE) acc += (AT)val[p] * xh[col[p]];
+        for (int64_t p = beg + lane; p < end; p += WAVE)
+            acc += (AT)__builtin_nontemporal_load(&val[p]) * xh[__builtin_nontemporal_load(&col[p])];
     }
     if (two) {
         const VT *__restrict__ val = (const VT *)Q.val;
         const int32_t *__restrict__ col = Q.col;
         const int64_t beg = Q.sp[s], end = Q.sp[s + 1];
 #pragma unroll 4
-        for (int64_t p = beg + lane; p < end; p += WAVE) acc += (AT)val[p] * xh[col[p]];
+        for (int64_t p = beg + lane; p < end; p += WAVE)
+            acc += (AT)__builtin_nontemporal_load(&val[p]) * xh[__builtin_nontemporal_load(&col[p])];
     }
     if (ye) { // couplings to other blocks, on the values frozen at the last exchange
         const VT *__restrict__ val = (const VT *)Ev.val;
