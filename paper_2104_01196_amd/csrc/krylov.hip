@@ -38,6 +38,9 @@ struct GState {
     // delayed CGS2: scalars of the current step and the tentative column
     double bb, dd, wn2, nu, inv_alpha, e;
     double ht[MAXM + 2];
+    // scale of the stored preconditioned vector of each step: step j works on
+    // the unnormalised tentative vector, z_j = zs[j] * (stored Z column j)
+    double zs[MAXM + 2];
 };
 
 struct GHeader {
@@ -428,9 +431,14 @@ __global__ void k_scale_next(int64_t n, double *__restrict__ V, int64_t ldv, con
 // ------------------------------------------------------------ delayed CGS2
 //
 // Two passes over V per Arnoldi step instead of four.  Step j starts from the
-// tentative vector u = V[j]: the previous step's projected vector, normalised
-// but not yet reorthogonalised.  Pass 1, fused with w = A z_j, forms
-// a = Q^T u, c = Q^T w, u.u, u.w and w.w (Q = V[0..j)) in one read of Q.
+// tentative vector u = V[j]: the previous step's projected vector, not yet
+// reorthogonalised, stored unnormalised with its scale zs[j] = 1/||u_raw||.
+// The preconditioner is linear (every apply starts from zero), so it is
+// applied to the raw vector and the scale is folded into the consumers: the
+// SpMV result and u are scaled when the first pass loads them, and the
+// solution update weighs column j of Z by zs[j].  Pass 1, fused with
+// w = A z_j, forms a = Q^T u, c = Q^T w, u.u, u.w and w.w (Q = V[0..j)) in
+// one read of Q.
 // Then q_j = (u - Q a)/alpha with alpha^2 = u.u - |a|^2, the coefficient of
 // w on q_j is e = (u.w - a.c)/alpha, and the previous step's tentative
 // Hessenberg column is corrected now that its vector's reorthogonalisation
@@ -452,11 +460,14 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, int64_t n, const 
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x;
     sella_rows<K, RB, KT / WAVE>(A, n, r0, z, wl);
+    const double zsc = st->zs[j];
     const double *__restrict__ u = V + (int64_t)j * ldv;
     for (int i = t; i < RB; i += KT) {
         const int64_t row = r0 + i;
-        if (row < n) w[row] = wl[i];
-        ul[i] = row < n ? u[row] : 0.0;
+        const double wv = zsc * wl[i];
+        wl[i] = wv;
+        if (row < n) w[row] = wv;
+        ul[i] = row < n ? zsc * u[row] : 0.0;
     }
     __syncthreads();
     // a = Q^T u, c = Q^T w (Q = V[0..j)), then u.u, u.w, w.w
@@ -513,85 +524,54 @@ __device__ bool commit_column(GState *st, RotLds &R, double *col, int jc)
     return true;
 }
 
-// Between the passes: reorthogonalisation scalars of u, correction and
-// commit of column j-1, the new tentative column j (one wavefront).
-__global__ __launch_bounds__(WAVE) void k_dcgs_scalar(GState *__restrict__ st)
+// Reorthogonalisation scalars of u from the reduced sums of pass 1:
+// alpha^2 = u.u - |a|^2 and e = (u.w - a.c)/alpha (alpha = 1, e = u.w at
+// j = 0).  as/cs_ hold a and c in LDS; the sums run in one wavefront in a
+// fixed order, so every workgroup that calls this gets the same bits.
+// Returns false when u has fallen into span(Q) (or alpha^2 is not finite).
+__device__ bool reorth_scalars(const GState *st, int j, const double *as, const double *cs_, double *sc,
+                               double *alpha, double *e, double *a2)
 {
-    __shared__ RotLds R;
-    __shared__ double ht[MAXM + 2], ha[MAXM + 2];
-    const int done = st->done, j = st->j;
-    if (done) return;
-    const int t = threadIdx.x;
-    if (j == 0) {
-        if (t == 0) {
-            st->inv_alpha = 1.0;
-            st->e = st->dd;
-            st->ht[0] = st->dd;
+    const int t = threadIdx.x, ln = t & (WAVE - 1);
+    if (t < WAVE) {
+        double aa = 0.0, ac = 0.0;
+        for (int k = ln; k < j; k += WAVE) {
+            aa += as[k] * as[k];
+            ac += as[k] * cs_[k];
         }
-        return;
+        aa = wave_sum(aa);
+        ac = wave_sum(ac);
+        if (ln == 0) {
+            sc[0] = aa;
+            sc[1] = ac;
+        }
     }
-    stage_rotations(st, R, j);
-    double aa = 0.0, ac = 0.0;
-    for (int k = t; k < j; k += WAVE) {
-        const double a = st->hA[k], c = st->hB[k];
-        ha[k] = a;
-        ht[k] = st->ht[k];
-        aa += a * a;
-        ac += a * c;
-    }
-    aa = wave_sum(aa);
-    ac = wave_sum(ac);
-    __syncthreads(); // LDS copies complete (one wavefront: also orders the lanes)
-    const double a2 = st->bb - aa;
-    const bool ok = isfinite(a2) && a2 > 0.0;
-    // new tentative column j: c (all lanes; lane 0 reads the old one from LDS only)
-    if (ok)
-        for (int k = t; k < j; k += WAVE) st->ht[k] = st->hB[k];
-    if (t != 0) return;
-    const double nu = st->nu;
-    double *col = R.col;
-    if (!isfinite(a2)) {
-        st->status = GS2_ERR_NONFINITE;
-        st->done = 1;
-        st->kk = j - 1;
-        return;
-    }
-    if (!ok) { // u fell into span(Q): end the cycle on the tentative column j-1
-        for (int k = 0; k < j; ++k) col[k] = ht[k];
-        col[j] = nu;
-        st->kk = commit_column(st, R, col, j - 1) ? j : j - 1;
-        st->done = 1;
-        return;
-    }
-    const double alpha = sqrt(a2);
-    for (int k = 0; k < j; ++k) col[k] = ht[k] + nu * ha[k];
-    col[j] = nu * alpha;
-    if (!commit_column(st, R, col, j - 1)) {
-        st->kk = j - 1;
-        st->done = 1;
-        return;
-    }
-    const double e = (st->dd - ac) / alpha;
-    st->inv_alpha = 1.0 / alpha;
-    st->e = e;
-    st->ht[j] = e;
+    __syncthreads();
+    *a2 = st->bb - sc[0];
+    const bool ok = j == 0 || (isfinite(*a2) && *a2 > 0.0);
+    *alpha = j == 0 ? 1.0 : sqrt(*a2);
+    *e = j == 0 ? st->dd : (st->dd - sc[1]) / *alpha;
+    return ok;
 }
 
-// Pass 2: q_j = (u - Q a)/alpha over u's slot, w' = w - Q c - e q_j into
-// V[j+1], partial ||w'||^2.
+// Pass 2 of step j: q_j = (u - Q a)/alpha over u's slot, w' = w - Q c - e q_j
+// into V[j+1], partial ||w'||^2.  Every workgroup derives alpha and e itself
+// (identical bits) and skips the pass when u has fallen into span(Q).
 __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restrict__ V, int64_t ldv,
                                                     const GState *__restrict__ st, const double *__restrict__ w,
                                                     double *__restrict__ part)
 {
-    __shared__ double as[MAXM + 2], cs_[MAXM + 2], red[4];
+    __shared__ double as[MAXM + 2], cs_[MAXM + 2], red[KT / WAVE], sc[2];
     if (st->done) return;
-    const int j = st->j;
-    for (int k = threadIdx.x; k < j; k += KT) {
+    const int j = st->j, t = threadIdx.x;
+    for (int k = t; k < j; k += KT) {
         as[k] = st->hA[k];
         cs_[k] = st->hB[k];
     }
     __syncthreads();
-    const double ia = st->inv_alpha, e = st->e;
+    double alpha, e, a2;
+    if (!reorth_scalars(st, j, as, cs_, sc, &alpha, &e, &a2)) return; // the same in every workgroup
+    const double ia = 1.0 / alpha, zsc = st->zs[j];
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     double s = 0.0;
     double *__restrict__ u = V + (int64_t)j * ldv;
@@ -602,9 +582,9 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
     double aq[NQ], aw[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int64_t row = r0 + threadIdx.x + q * KT;
+        const int64_t row = r0 + t + q * KT;
         rows[q] = row < n ? row : n - 1;
-        aq[q] = u[rows[q]];
+        aq[q] = zsc * u[rows[q]];
         aw[q] = w[rows[q]];
     }
 #pragma unroll 2
@@ -620,7 +600,7 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int64_t row = r0 + threadIdx.x + q * KT;
+        const int64_t row = r0 + t + q * KT;
         if (row >= n) continue;
         const double qv = aq[q] * ia;
         const double wp = aw[q] - e * qv;
@@ -629,26 +609,67 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
         s += wp * wp;
     }
     s = block_sum(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (t == 0) part[blockIdx.x] = s;
 }
 
-// ||w'||, tentative rotation of column j and the stopping decision.
+// The step's serial work (one workgroup): correct and commit column j-1
+// ([ht + nu a; nu alpha]) now that u's reorthogonalisation is known, store
+// the new tentative column [c, e], form ||w'|| from the partials, the
+// tentative rotation of column j and the residual estimate, and either stop
+// the cycle or advance j (the next tentative vector keeps its scale 1/||w'||
+// in zs[j+1]).  When u fell into span(Q) the cycle ends on the tentative
+// column j-1.
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
-    __shared__ double red[4];
+    __shared__ double as[MAXM + 2], cs_[MAXM + 2], ht[MAXM + 2], red[KT / WAVE], sc[2];
     __shared__ RotLds R;
-    __shared__ double ht[MAXM + 2];
     if (st->done) return;
-    const int j = st->j;
+    const int j = st->j, t = threadIdx.x;
     stage_rotations(st, R, j);
-    for (int k = threadIdx.x; k <= j; k += KT) ht[k] = st->ht[k];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += KT) s += part[b];
-    s = block_sum(s, red); // also orders the LDS staging
-    if (threadIdx.x != 0) return;
-    const double nu = sqrt(s);
-    st->nu = nu;
+    for (int k = t; k < j; k += KT) {
+        as[k] = st->hA[k];
+        cs_[k] = st->hB[k];
+        ht[k] = st->ht[k];
+    }
+    __syncthreads();
+    double alpha, e, a2;
+    const bool ok = reorth_scalars(st, j, as, cs_, sc, &alpha, &e, &a2);
+    double tot = 0.0;
+    if (ok)
+        for (int b = t; b < nb; b += KT) tot += part[b];
+    tot = block_sum(tot, red);
+    if (t != 0) return;
     double *col = R.col;
+    const double nu_prev = st->nu;
+    if (!ok) {
+        if (!isfinite(a2)) {
+            st->status = GS2_ERR_NONFINITE;
+            st->kk = j - 1;
+        } else {
+            for (int k = 0; k < j; ++k) col[k] = ht[k];
+            col[j] = nu_prev;
+            st->kk = commit_column(st, R, col, j - 1) ? j : j - 1;
+        }
+        st->done = 1;
+        return;
+    }
+    if (j > 0) {
+        for (int k = 0; k < j; ++k) col[k] = ht[k] + nu_prev * as[k];
+        col[j] = nu_prev * alpha;
+        if (!commit_column(st, R, col, j - 1)) {
+            st->kk = j - 1;
+            st->done = 1;
+            return;
+        }
+    }
+    st->inv_alpha = 1.0 / alpha;
+    st->e = e;
+    // tentative column j: [c, e; ||w'||]
+    for (int k = 0; k < j; ++k) ht[k] = cs_[k];
+    ht[j] = e;
+    for (int k = 0; k <= j; ++k) st->ht[k] = ht[k];
+    const double nu = sqrt(tot);
+    st->nu = nu;
     for (int k = 0; k <= j; ++k) col[k] = ht[k];
     col[j + 1] = nu;
     for (int k = 0; k < j; ++k) {
@@ -673,16 +694,9 @@ __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ p
         st->done = 1;
     } else {
         st->inv = 1.0 / nu;
+        st->zs[j + 1] = 1.0 / nu;
         st->j = j + 1;
     }
-}
-
-// V[j] *= 1/||w'|| of the previous step (the tentative vector's scale)
-__global__ void k_normalize(int64_t n, double *__restrict__ V, int64_t ldv, const GState *__restrict__ st)
-{
-    if (st->done) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) V[(int64_t)st->j * ldv + i] *= st->inv;
 }
 
 __global__ void k_cycle_init(GState *__restrict__ st, int maxsteps, double rtol)
@@ -697,6 +711,7 @@ __global__ void k_cycle_init(GState *__restrict__ st, int maxsteps, double rtol)
     st->inv = 1.0 / st->beta;
     for (int k = 0; k < MAXM + 2; ++k) st->g[k] = 0.0;
     st->g[0] = st->beta;
+    for (int k = 0; k < MAXM + 2; ++k) st->zs[k] = 1.0; // V[0] is normalised explicitly; CGS2 normalises all
 }
 
 __global__ void k_scale0(int64_t n, double *__restrict__ v, const GState *__restrict__ st)
@@ -717,13 +732,13 @@ __global__ void k_backsolve(GState *__restrict__ st)
     }
 }
 
-// x += Z y
+// x += Z y (column k of Z weighed by its scale zs[k])
 __global__ __launch_bounds__(KT) void k_update_x(int64_t n, const double *__restrict__ Z, int64_t ldz,
                                                  const GState *__restrict__ st, double *__restrict__ x)
 {
     __shared__ double ys[MAXM];
     const int kk = st->kk;
-    for (int k = threadIdx.x; k < kk; k += KT) ys[k] = st->y[k];
+    for (int k = threadIdx.x; k < kk; k += KT) ys[k] = st->y[k] * st->zs[k];
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -878,10 +893,6 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                 double *zj = Zb + (int64_t)j * n;
                 const double vb = 8.0 * n * (j + 1);
                 if (orth == 0) { // delayed CGS2
-                    if (j > 0) {
-                        Prof pr(cs, PK_SCALE, 16.0 * n);
-                        k_normalize<<<gE, 256, 0, cs>>>(n, W->V, n, st);
-                    }
                     GS2_TRY(precondition(kind, P, vj, zj, n, st, cs));
                     {
                         Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
@@ -891,10 +902,6 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                     {
                         Prof pr(cs, PK_REDUCE, red_b * (2 * j + 3));
                         k_reduce<<<2 * j + 3, KT, 0, cs>>>(W->part, nb, st, 3, 0, 2 * j + 3);
-                    }
-                    {
-                        Prof pr(cs, PK_GIVENS, 0.0);
-                        k_dcgs_scalar<<<1, 64, 0, cs>>>(st);
                     }
                     {
                         Prof pr(cs, PK_CGS, 8.0 * n * (j + 4));
