@@ -90,49 +90,100 @@ __device__ __forceinline__ void bfinish(int dst, int64_t row, const AT (&g)[R], 
     }
 }
 
+// A workgroup has only BNW wavefronts for a whole system, so each wavefront
+// works on BU slices at once: their (slice pointer -> column -> gathered
+// value) chains are in flight together instead of one after the other.
+template <typename AT, int R>
+constexpr int bu_of()
+{
+    return (sizeof(AT) == 8 ? 2 : 4) / R > 0 ? (sizeof(AT) == 8 ? 2 : 4) / R : 1;
+}
+
+// acc[u][r] += sum over the stored entries of slice s0 + u of val * src(col, r)
+template <typename VT, typename AT, int R, int BU, typename Src>
+__device__ __forceinline__ void bslice_dots(const int64_t *sp, const int32_t *col, const VT *val, int64_t s0,
+                                            int64_t nslices, int lane, Src src, AT (&acc)[BU][R])
+{
+    int64_t beg[BU];
+    int steps[BU];
+    int tmax = 0;
+#pragma unroll
+    for (int u = 0; u < BU; ++u) {
+        const int64_t s = s0 + u;
+        const bool ok = s < nslices;
+        beg[u] = ok ? sp[s] : 0;
+        steps[u] = ok ? (int)((sp[s + 1] - beg[u]) / WAVE) : 0;
+        tmax = steps[u] > tmax ? steps[u] : tmax;
+    }
+    // TS steps at a time: first every (column, value) load of the chunk, then
+    // the gathers they feed, so one chunk costs two memory latencies
+    constexpr int TS = 4;
+    for (int t0 = 0; t0 < tmax; t0 += TS) {
+        int cc[BU][TS];
+        AT av[BU][TS];
+#pragma unroll
+        for (int u = 0; u < BU; ++u)
+#pragma unroll
+            for (int q = 0; q < TS; ++q) {
+                const bool in = t0 + q < steps[u];
+                const int64_t p = beg[u] + (int64_t)(in ? t0 + q : 0) * WAVE + lane;
+                cc[u][q] = in ? col[p] : -1;
+                av[u][q] = in ? (AT)val[p] : AT(0);
+            }
+#pragma unroll
+        for (int u = 0; u < BU; ++u)
+#pragma unroll
+            for (int q = 0; q < TS; ++q)
+                if (cc[u][q] >= 0) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[u][r] += av[u][q] * src(cc[u][q], r);
+                }
+    }
+}
+
 // inner JR pass g = rh - w T g_old for R interleaved right-hand sides
 template <typename VT, typename AT, int R, int K>
 __device__ void bp_inner(const BSys &S, int lower, const AT *rh, const AT *gin, const double *v, int rv, int gv,
                          int damp, AT w, AT gamma, int dst, AT *gout, AT *xh, double *z)
 {
+    constexpr int BU = bu_of<AT, R>();
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int64_t *sp = lower ? S.Lsp : S.Usp;
     const int32_t *col = lower ? S.Lcol : S.Ucol;
     const VT *val = (const VT *)(lower ? S.Lval : S.Uval);
-    for (int64_t s = wv; s < S.nslices; s += BNW) {
-        const int64_t row = s * (WAVE / K) + lane / K;
-        AT acc[R];
+    for (int64_t s0 = (int64_t)wv * BU; s0 < S.nslices; s0 += (int64_t)BNW * BU) {
+        AT acc[BU][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = AT(0);
-        for (int64_t p = sp[s] + lane; p < sp[s + 1]; p += WAVE) {
-            const int c = col[p];
-            const AT a = (AT)val[p];
-            if (gv) {
-                const double sc = S.sl[c];
+        for (int u = 0; u < BU; ++u)
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += a * (AT)(v[(int64_t)c * R + r] * sc);
-            } else {
+            for (int r = 0; r < R; ++r) acc[u][r] = AT(0);
+        if (gv)
+            bslice_dots<VT, AT, R, BU>(sp, col, val, s0, S.nslices, lane,
+                                       [&](int c, int r) { return (AT)(v[(int64_t)c * R + r] * S.sl[c]); }, acc);
+        else
+            bslice_dots<VT, AT, R, BU>(sp, col, val, s0, S.nslices, lane,
+                                       [&](int c, int r) { return gin[(int64_t)c * R + r]; }, acc);
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += a * gin[(int64_t)c * R + r];
+        for (int u = 0; u < BU; ++u) {
+            if (K > 1) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[u][r] = group_sum<K>(acc[u][r]);
             }
-        }
-        if (K > 1) {
+            const int64_t row = (s0 + u) * (WAVE / K) + lane / K;
+            if ((K > 1 && (lane & (K - 1))) || row >= S.n) continue;
+            AT g[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = group_sum<K>(acc[r]);
-        }
-        if ((K > 1 && (lane & (K - 1))) || row >= S.n) continue;
-        AT g[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t i = row * R + r;
-            const AT rr = rv ? (AT)(v[i] * S.sl[row]) : rh[i];
-            g[r] = rr - w * acc[r];
-            if (damp) {
-                const AT go = gv ? (AT)(v[i] * S.sl[row]) : gin[i];
-                g[r] = (AT(1) - gamma) * go + gamma * g[r];
+            for (int r = 0; r < R; ++r) {
+                const int64_t i = row * R + r;
+                const AT rr = rv ? (AT)(v[i] * S.sl[row]) : rh[i];
+                g[r] = rr - w * acc[u][r];
+                if (damp) {
+                    const AT go = gv ? (AT)(v[i] * S.sl[row]) : gin[i];
+                    g[r] = (AT(1) - gamma) * go + gamma * g[r];
+                }
             }
+            bfinish<AT, R>(dst, row, g, w, gout, xh, xh, z, S.sr);
         }
-        bfinish<AT, R>(dst, row, g, w, gout, xh, xh, z, S.sr);
     }
 }
 
@@ -141,37 +192,35 @@ template <typename VT, typename AT, int R, int K>
 __device__ void bp_resid(const BSys &S, int lower, int compact, const AT *xh, const double *v, AT cdiag, AT w, int dst,
                          AT *rh, AT *xout, double *z)
 {
+    constexpr int BU = bu_of<AT, R>();
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-    for (int64_t s = wv; s < S.nslices; s += BNW) {
-        const int64_t row = s * (WAVE / K) + lane / K;
-        AT acc[R];
+    auto gx = [&](int c, int r) { return xh[(int64_t)c * R + r]; };
+    for (int64_t s0 = (int64_t)wv * BU; s0 < S.nslices; s0 += (int64_t)BNW * BU) {
+        AT acc[BU][R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = AT(0);
-        for (int part = 0; part < 2; ++part) {
-            const bool useL = part == 0;
-            if (compact && (useL == (bool)lower)) continue; // compact: only the opposite triangle
-            const int64_t *sp = useL ? S.Lsp : S.Usp;
-            const int32_t *col = useL ? S.Lcol : S.Ucol;
-            const VT *val = (const VT *)(useL ? S.Lval : S.Uval);
-            for (int64_t p = sp[s] + lane; p < sp[s + 1]; p += WAVE) {
-                const int c = col[p];
-                const AT a = (AT)val[p];
+        for (int u = 0; u < BU; ++u)
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += a * xh[(int64_t)c * R + r];
+            for (int r = 0; r < R; ++r) acc[u][r] = AT(0);
+        if (!(compact && lower)) // compact: only the triangle opposite to the inner one
+            bslice_dots<VT, AT, R, BU>(S.Lsp, S.Lcol, (const VT *)S.Lval, s0, S.nslices, lane, gx, acc);
+        if (!(compact && !lower))
+            bslice_dots<VT, AT, R, BU>(S.Usp, S.Ucol, (const VT *)S.Uval, s0, S.nslices, lane, gx, acc);
+#pragma unroll
+        for (int u = 0; u < BU; ++u) {
+            if (K > 1) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[u][r] = group_sum<K>(acc[u][r]);
             }
-        }
-        if (K > 1) {
+            const int64_t row = (s0 + u) * (WAVE / K) + lane / K;
+            if ((K > 1 && (lane & (K - 1))) || row >= S.n) continue;
+            AT g[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = group_sum<K>(acc[r]);
+            for (int r = 0; r < R; ++r) {
+                const int64_t i = row * R + r;
+                g[r] = ((AT)(v[i] * S.sl[row]) - cdiag * xh[i]) - acc[u][r];
+            }
+            bfinish<AT, R>(dst, row, g, w, rh, const_cast<AT *>(xh), xout, z, S.sr);
         }
-        if ((K > 1 && (lane & (K - 1))) || row >= S.n) continue;
-        AT g[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t i = row * R + r;
-            g[r] = ((AT)(v[i] * S.sl[row]) - cdiag * xh[i]) - acc[r];
-        }
-        bfinish<AT, R>(dst, row, g, w, rh, const_cast<AT *>(xh), xout, z, S.sr);
     }
 }
 
@@ -240,22 +289,57 @@ __device__ void b_precond(const BConst &c, const BSys &S, const double *v, doubl
 
 // ------------------------------------------------- block-level Krylov pieces
 
-// w = A z (or w = b - A z with bstride > 0) for R interleaved vectors; thread per row.
+// w = A z (or w = b - A z with bstride > 0) for R interleaved vectors; a
+// thread works on RU rows (RU*BT apart) at once so that their CSR chains
+// (row pointer -> column -> z) are in flight together.
 template <int R>
 __device__ void b_spmv(const BSys &S, const double *z, double *w, const double *b, int64_t bstride)
 {
-    for (int64_t row = threadIdx.x; row < S.n; row += BT) {
-        double acc[R];
+    constexpr int RU = 4 / R;
+    for (int64_t r0 = threadIdx.x; r0 < S.n; r0 += (int64_t)BT * RU) {
+        int pb[RU], pe[RU];
+        int len = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0.0;
-        for (int p = S.rp[row]; p < S.rp[row + 1]; ++p) {
-            const double a = S.va[p];
-            const int64_t cc = (int64_t)S.ci[p] * R;
+        for (int u = 0; u < RU; ++u) {
+            const int64_t row = r0 + (int64_t)u * BT;
+            pb[u] = row < S.n ? S.rp[row] : 0;
+            pe[u] = row < S.n ? S.rp[row + 1] : 0;
+            len = pe[u] - pb[u] > len ? pe[u] - pb[u] : len;
+        }
+        double acc[RU][R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += a * z[cc + r];
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[u][r] = 0.0;
+        constexpr int TS = 4; // entries per row and chunk: loads first, then the gathers
+        for (int t0 = 0; t0 < len; t0 += TS) {
+            int cc[RU][TS];
+            double av[RU][TS];
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int q = 0; q < TS; ++q) {
+                    const int p = pb[u] + t0 + q;
+                    const bool in = p < pe[u];
+                    cc[u][q] = in ? S.ci[p] : -1;
+                    av[u][q] = in ? S.va[p] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int q = 0; q < TS; ++q)
+                    if (cc[u][q] >= 0) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[u][r] += av[u][q] * z[(int64_t)cc[u][q] * R + r];
+                    }
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) w[row * R + r] = b ? b[row * bstride + r] - acc[r] : acc[r];
+        for (int u = 0; u < RU; ++u) {
+            const int64_t row = r0 + (int64_t)u * BT;
+            if (row >= S.n) continue;
+#pragma unroll
+            for (int r = 0; r < R; ++r) w[row * R + r] = b ? b[row * bstride + r] - acc[u][r] : acc[u][r];
+        }
     }
 }
 
@@ -279,21 +363,36 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
             for (int r = 0; r < R; ++r) acc[kk][r] = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) nacc[r] = 0.0;
-        for (int64_t row = threadIdx.x; row < n; row += BT) {
-            double wr[R];
+        // RU rows per thread at once: all their loads are issued before use, since
+        // a workgroup's few wavefronts cannot hide one memory latency per row
+        constexpr int RU = 2;
+        for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
+            double wr[RU][R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) wr[r] = w[row * R + r];
+            for (int u = 0; u < RU; ++u) {
+                const int64_t row = r0 + (int64_t)u * BT;
+                const int64_t rr = row < n ? row : n - 1; // clamped; its factor is zero
+#pragma unroll
+                for (int r = 0; r < R; ++r) wr[u][r] = row < n ? w[rr * R + r] : 0.0;
+            }
 #pragma unroll
             for (int kk = 0; kk < KC; ++kk) {
                 if (kk < kc) {
-                    const double *vk = V + (int64_t)(k0 + kk) * ldv + row * R;
+                    const double *vk = V + (int64_t)(k0 + kk) * ldv;
 #pragma unroll
-                    for (int r = 0; r < R; ++r) acc[kk][r] += vk[r] * wr[r];
+                    for (int u = 0; u < RU; ++u) {
+                        const int64_t row = r0 + (int64_t)u * BT;
+                        const int64_t rr = row < n ? row : n - 1;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[kk][r] += vk[rr * R + r] * wr[u][r];
+                    }
                 }
             }
             if (nrm) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) nacc[r] += wr[r] * wr[r];
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) nacc[r] += wr[u][r] * wr[u][r];
             }
         }
 #pragma unroll
@@ -327,22 +426,39 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
     }
 }
 
-// wout = win - sum_k h[k*R + r] V_k   (h in LDS)
+// wout = win - sum_k h[k*R + r] V_k   (h in LDS).  Vectors outer, RU rows per
+// thread inner: RU*R independent loads per vector instead of one load, wait
+// and use per vector and row.
 template <int R>
 __device__ void b_update(int64_t n, const double *V, int64_t ldv, int nk, const double *h, const double *win,
                          double *wout)
 {
-    for (int64_t row = threadIdx.x; row < n; row += BT) {
-        double acc[R];
+    constexpr int RU = 8 / R;
+    for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
+        double acc[RU][R];
+        int64_t rr[RU];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = win[row * R + r];
+        for (int u = 0; u < RU; ++u) {
+            const int64_t row = r0 + (int64_t)u * BT;
+            rr[u] = row < n ? row : n - 1; // clamped for loads, skipped for stores
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[u][r] = win[rr[u] * R + r];
+        }
+#pragma unroll 2
         for (int k = 0; k < nk; ++k) {
-            const double *vk = V + (int64_t)k * ldv + row * R;
+            const double *vk = V + (int64_t)k * ldv;
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] -= h[k * R + r] * vk[r];
+            for (int u = 0; u < RU; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[u][r] -= h[k * R + r] * vk[rr[u] * R + r];
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) wout[row * R + r] = acc[r];
+        for (int u = 0; u < RU; ++u) {
+            const int64_t row = r0 + (int64_t)u * BT;
+            if (row >= n) continue;
+#pragma unroll
+            for (int r = 0; r < R; ++r) wout[row * R + r] = acc[u][r];
+        }
     }
 }
 
@@ -804,18 +920,25 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
         hipEvent_t e0, e1;
         GS2_TRY_HIP(hipEventCreate(&e0));
         GS2_TRY_HIP(hipEventCreate(&e1));
+        // One restart cycle per item, every right-hand side doing the same
+        // work, measures throughput only.  In a real solve the right-hand
+        // sides of an item converge at different steps and the item runs until
+        // its slowest one has (and the largest items form the critical path), so
+        // the smallest R within 25% of the best tuning time is taken.
+        std::vector<float> ms_of(cands.size(), 0.f);
         float best = 1e30f;
-        for (int R : cands) {
-            GS2_TRY(configure(b, R));
+        for (size_t c = 0; c < cands.size(); ++c) {
+            GS2_TRY(configure(b, cands[c]));
             GS2_TRY_HIP(hipMemsetAsync(Xt, 0, sizeof(double) * tot, s));
             GS2_TRY_HIP(hipEventRecord(e0, s));
-            GS2_TRY(run(b, Bt, Xt, 0.0, restart, s)); // one restart cycle per item
+            GS2_TRY(run(b, Bt, Xt, 0.0, restart, s));
             GS2_TRY_HIP(hipEventRecord(e1, s));
             GS2_TRY_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            GS2_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) { best = ms; bestR = R; }
+            GS2_TRY_HIP(hipEventElapsedTime(&ms_of[c], e0, e1));
+            best = std::min(best, ms_of[c]);
         }
+        for (size_t c = 0; c < cands.size(); ++c) // cands is in decreasing R
+            if (ms_of[c] <= 1.25f * best) bestR = cands[c];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(Bt);
