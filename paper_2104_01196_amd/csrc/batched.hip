@@ -12,7 +12,9 @@
 // loaded once per group and applied to R vectors (an SpMM-like access).
 // Each right-hand side keeps its own Hessenberg matrix, rotations and
 // convergence flag; a right-hand side that has converged stops contributing
-// while the others continue.  The launch is captured in a HIP graph at setup
+// while the others continue.  The Arnoldi process is classical Gram-Schmidt
+// with delayed reorthogonalisation (two passes over the basis per step, as in
+// the single-system solver).  The launch is captured in a HIP graph at setup
 // and replayed by every solve; its arguments live in device memory.
 #include <algorithm>
 #include <chrono>
@@ -289,11 +291,13 @@ __device__ void b_precond(const BConst &c, const BSys &S, const double *v, doubl
 
 // ------------------------------------------------- block-level Krylov pieces
 
-// w = A z (or w = b - A z with bstride > 0) for R interleaved vectors; a
+// w = A z (w = b - A z with bstride > 0, w = scl[r] (A z) with scl) for R
+// interleaved vectors; a
 // thread works on RU rows (RU*BT apart) at once so that their CSR chains
 // (row pointer -> column -> z) are in flight together.
 template <int R>
-__device__ void b_spmv(const BSys &S, const double *z, double *w, const double *b, int64_t bstride)
+__device__ void b_spmv(const BSys &S, const double *z, double *w, const double *b, int64_t bstride,
+                       const double *scl = nullptr)
 {
     constexpr int RU = 4 / R;
     for (int64_t r0 = threadIdx.x; r0 < S.n; r0 += (int64_t)BT * RU) {
@@ -338,7 +342,8 @@ __device__ void b_spmv(const BSys &S, const double *z, double *w, const double *
             const int64_t row = r0 + (int64_t)u * BT;
             if (row >= S.n) continue;
 #pragma unroll
-            for (int r = 0; r < R; ++r) w[row * R + r] = b ? b[row * bstride + r] - acc[u][r] : acc[u][r];
+            for (int r = 0; r < R; ++r)
+                w[row * R + r] = b ? b[row * bstride + r] - acc[u][r] : scl ? scl[r] * acc[u][r] : acc[u][r];
         }
     }
 }
@@ -426,51 +431,194 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
     }
 }
 
-// wout = win - sum_k h[k*R + r] V_k   (h in LDS).  Vectors outer, RU rows per
-// thread inner: RU*R independent loads per vector instead of one load, wait
-// and use per vector and row.
+// Pass 1 of the delayed reorthogonalisation for R interleaved right-hand
+// sides: outA[k*R + r] = <V_k, u>, outC[k*R + r] = <V_k, w> for k < nk, with
+// u = us[r] * uraw (the unnormalised tentative vector and its scale), and
+// outN[r], outN[R + r], outN[2R + r] = u.u, u.w, w.w.  Chunks of KC2 vectors
+// (2*KC2*R + 3R <= RED_STRIDE reduction slots); fixed-order reductions.
 template <int R>
-__device__ void b_update(int64_t n, const double *V, int64_t ldv, int nk, const double *h, const double *win,
-                         double *wout)
+__device__ void b_multidot2(int64_t n, const double *V, int64_t ldv, int nk, const double *uraw, const double *us,
+                            const double *w, double *outA, double *outC, double *outN, double *red)
 {
-    constexpr int RU = 8 / R;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    constexpr int KC2 = 4 / R;
+    constexpr int RU = 2;
+    for (int k0 = 0; k0 < nk || k0 == 0; k0 += KC2) {
+        const int kc = min(KC2, nk - k0);
+        const bool nrm = k0 == 0;
+        double aa[KC2][R], cc[KC2][R], nn[3][R];
+#pragma unroll
+        for (int kk = 0; kk < KC2; ++kk)
+#pragma unroll
+            for (int r = 0; r < R; ++r) aa[kk][r] = cc[kk][r] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) nn[q][r] = 0.0;
+        for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
+            double ur[RU][R], wr[RU][R];
+            int64_t rr[RU];
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                const int64_t row = r0 + (int64_t)u * BT;
+                rr[u] = row < n ? row : n - 1; // clamped; its factors are zero
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    ur[u][r] = row < n ? us[r] * uraw[rr[u] * R + r] : 0.0;
+                    wr[u][r] = row < n ? w[rr[u] * R + r] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int kk = 0; kk < KC2; ++kk) {
+                if (kk < kc) {
+                    const double *vk = V + (int64_t)(k0 + kk) * ldv;
+#pragma unroll
+                    for (int u = 0; u < RU; ++u)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const double x = vk[rr[u] * R + r];
+                            aa[kk][r] += x * ur[u][r];
+                            cc[kk][r] += x * wr[u][r];
+                        }
+                }
+            }
+            if (nrm) {
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        nn[0][r] += ur[u][r] * ur[u][r];
+                        nn[1][r] += ur[u][r] * wr[u][r];
+                        nn[2][r] += wr[u][r] * wr[u][r];
+                    }
+            }
+        }
+        // slots: [a: KC2*R][c: KC2*R][norms: 3R]
+#pragma unroll
+        for (int kk = 0; kk < KC2; ++kk) {
+            if (kk < kc) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double sa = wave_sum(aa[kk][r]);
+                    const double sc = wave_sum(cc[kk][r]);
+                    if (lane == 0) {
+                        red[wv * RED_STRIDE + kk * R + r] = sa;
+                        red[wv * RED_STRIDE + (KC2 + kk) * R + r] = sc;
+                    }
+                }
+            }
+        }
+        if (nrm) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double sn = wave_sum(nn[q][r]);
+                    if (lane == 0) red[wv * RED_STRIDE + 2 * KC2 * R + q * R + r] = sn;
+                }
+        }
+        __syncthreads();
+        const int cnt = max(kc, 0) * R;
+        for (int t = threadIdx.x; t < 2 * cnt + (nrm ? 3 * R : 0); t += BT) {
+            int slot;
+            double *dst;
+            if (t < cnt) {
+                slot = t;
+                dst = outA + k0 * R + t;
+            } else if (t < 2 * cnt) {
+                slot = KC2 * R + (t - cnt);
+                dst = outC + k0 * R + (t - cnt);
+            } else {
+                slot = 2 * KC2 * R + (t - 2 * cnt);
+                dst = outN + (t - 2 * cnt);
+            }
+            double sum = 0.0;
+            for (int q = 0; q < BNW; ++q) sum += red[q * RED_STRIDE + slot];
+            *dst = sum;
+        }
+        __syncthreads();
+        if (nk <= 0) break;
+    }
+}
+
+// Pass 2 for R interleaved right-hand sides: q = (us[r] uraw - sum_k a_k V_k)
+// * ia[r] over uraw's slot, w' = w - sum_k c_k V_k - e[r] q into wn, and
+// nrm[r] = ||w'||^2.  Vectors outer, RU rows per thread inner.
+template <int R>
+__device__ void b_update2(int64_t n, const double *V, int64_t ldv, int nk, const double *a, const double *cvec,
+                          double *uraw, const double *us, const double *ia, const double *e, const double *w,
+                          double *wn, double *nrm, double *red)
+{
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    constexpr int RU = 4 / R;
+    double nacc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) nacc[r] = 0.0;
     for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
-        double acc[RU][R];
+        double aq[RU][R], aw[RU][R];
         int64_t rr[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t row = r0 + (int64_t)u * BT;
             rr[u] = row < n ? row : n - 1; // clamped for loads, skipped for stores
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[u][r] = win[rr[u] * R + r];
+            for (int r = 0; r < R; ++r) {
+                aq[u][r] = us[r] * uraw[rr[u] * R + r];
+                aw[u][r] = w[rr[u] * R + r];
+            }
         }
-#pragma unroll 2
         for (int k = 0; k < nk; ++k) {
             const double *vk = V + (int64_t)k * ldv;
 #pragma unroll
             for (int u = 0; u < RU; ++u)
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[u][r] -= h[k * R + r] * vk[rr[u] * R + r];
+                for (int r = 0; r < R; ++r) {
+                    const double x = vk[rr[u] * R + r];
+                    aq[u][r] -= a[k * R + r] * x;
+                    aw[u][r] -= cvec[k * R + r] * x;
+                }
         }
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t row = r0 + (int64_t)u * BT;
             if (row >= n) continue;
 #pragma unroll
-            for (int r = 0; r < R; ++r) wout[row * R + r] = acc[u][r];
+            for (int r = 0; r < R; ++r) {
+                const double qv = aq[u][r] * ia[r];
+                const double wp = aw[u][r] - e[r] * qv;
+                uraw[row * R + r] = qv;
+                wn[row * R + r] = wp;
+                nacc[r] += wp * wp;
+            }
         }
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double sn = wave_sum(nacc[r]);
+        if (lane == 0) red[wv * RED_STRIDE + r] = sn;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < R; t += BT) {
+        double sum = 0.0;
+        for (int q = 0; q < BNW; ++q) sum += red[q * RED_STRIDE + t];
+        nrm[t] = sum;
+    }
+    __syncthreads();
 }
 
 struct BLds {
     double *red, *hA, *hB, *H, *cs, *sn, *g, *y, *bnorm, *beta, *inv, *wn2, *nrm, *col;
+    // delayed reorthogonalisation: tentative column, scale of each stored Z
+    // column, ||w'|| of the last step, pass-1 norms (u.u, u.w, w.w), the scale
+    // of the current tentative vector, 1/alpha and e of the current step
+    double *ht, *zs, *nu, *nrm3, *us, *ia, *ev;
     int *done, *kk, *iters, *restarts, *status, *conv, *flag;
 };
 
 __host__ __device__ inline size_t blds_bytes(int m, int R)
 {
-    const size_t d = (size_t)BNW * RED_STRIDE + 3 * (size_t)(m + 2) * R + (size_t)(m + 1) * m * R +
-                     3 * (size_t)m * R + (size_t)(m + 2) * R + 5 * (size_t)R;
+    const size_t d = (size_t)BNW * RED_STRIDE + 5 * (size_t)(m + 2) * R + (size_t)(m + 1) * m * R +
+                     3 * (size_t)m * R + (size_t)(m + 2) * R + 12 * (size_t)R;
     return d * sizeof(double) + (6 * (size_t)R + 2) * sizeof(int) + 64;
 }
 
@@ -492,6 +640,13 @@ __device__ inline BLds blds_carve(double *base, int m, int R)
     L.inv = p; p += R;
     L.wn2 = p; p += R;
     L.nrm = p; p += R;
+    L.ht = p; p += (m + 2) * R;
+    L.zs = p; p += (m + 2) * R;
+    L.nu = p; p += R;
+    L.nrm3 = p; p += 3 * R;
+    L.us = p; p += R;
+    L.ia = p; p += R;
+    L.ev = p; p += R;
     int *q = (int *)p;
     L.done = q; q += R;
     L.kk = q; q += R;
@@ -501,6 +656,37 @@ __device__ inline BLds blds_carve(double *base, int m, int R)
     L.conv = q; q += R;
     L.flag = q;
     return L;
+}
+
+// (one thread per right-hand side) apply the committed rotations 0..jc-1 of
+// right-hand side r to col (jc+2 entries), form rotation jc, store column jc
+// of R and advance the residual recurrence g.  False on a zero or
+// non-finite rotation radius (status set).
+__device__ bool bcommit(BLds &L, int R, int m, int r, double *col, int jc)
+{
+    for (int k = 0; k < jc; ++k) {
+        const double a = L.cs[k * R + r] * col[k] + L.sn[k * R + r] * col[k + 1];
+        col[k + 1] = -L.sn[k * R + r] * col[k] + L.cs[k * R + r] * col[k + 1];
+        col[k] = a;
+    }
+    const double rho = hypot(col[jc], col[jc + 1]);
+    if (!isfinite(rho)) {
+        L.status[r] = GS2_ERR_NONFINITE;
+        return false;
+    }
+    if (rho == 0.0) {
+        L.status[r] = GS2_BREAKDOWN;
+        return false;
+    }
+    const double cs = col[jc] / rho, sn = col[jc + 1] / rho;
+    L.cs[jc * R + r] = cs;
+    L.sn[jc * R + r] = sn;
+    col[jc] = rho;
+    for (int k = 0; k <= jc; ++k) L.H[(k * m + jc) * R + r] = col[k];
+    const double gj = L.g[jc * R + r];
+    L.g[(jc + 1) * R + r] = -sn * gj;
+    L.g[jc * R + r] = cs * gj;
+    return true;
 }
 
 template <typename VT, typename AT, int R, int K>
@@ -577,67 +763,108 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
         ++cycle;
         for (int64_t i = t; i < nR; i += BT) V[i] = L.inv[i % R] == 0.0 ? 0.0 : V[i] * L.inv[i % R];
         __syncthreads();
+        if (t < R) L.zs[t] = 1.0; // V_0 is normalised explicitly
+        __syncthreads();
+        // Arnoldi steps with delayed reorthogonalisation (two passes over the
+        // basis per step; the tentative vector V_j stays unnormalised, its
+        // scale in zs, and is reorthogonalised one step late)
         for (int j = 0; j < m; ++j) {
             double *vj = V + (int64_t)j * nR;
             double *zj = Z + (int64_t)j * nR;
-            b_precond<VT, AT, R, K>(c, S, vj, zj, P);
-            // w = A z_j ; hA = V^T w ; ||w||^2
-            b_spmv<R>(S, zj, w, nullptr, 0);
+            b_precond<VT, AT, R, K>(c, S, vj, zj, P); // on the raw vector: the apply is linear
+            if (t < R) L.us[t] = L.done[t] ? 0.0 : L.zs[j * R + t];
             __syncthreads();
-            b_multidot<R>(n, V, nR, j + 1, w, 1, L.hA, L.red);
-            if (t < R) L.wn2[t] = L.hA[(j + 1) * R + t];
+            b_spmv<R>(S, zj, w, nullptr, 0, L.us); // w = A z_j, z_j = us * stored column
             __syncthreads();
-            b_update<R>(n, V, nR, j + 1, L.hA, w, w);
+            // pass 1: a = Q^T u, c = Q^T w, u.u, u.w, w.w (Q = V_0..V_{j-1})
+            b_multidot2<R>(n, V, nR, j, vj, L.us, w, L.hA, L.hB, L.nrm3, L.red);
+            if (t < R) {
+                const int r = t;
+                L.ia[r] = 0.0;
+                L.ev[r] = 0.0;
+                if (!L.done[r]) {
+                    double *col = L.col + r * (m + 2);
+                    double aa = 0.0, ac = 0.0;
+                    for (int k = 0; k < j; ++k) {
+                        aa += L.hA[k * R + r] * L.hA[k * R + r];
+                        ac += L.hA[k * R + r] * L.hB[k * R + r];
+                    }
+                    const double a2 = L.nrm3[r] - aa;
+                    const bool ok = j == 0 || (isfinite(a2) && a2 > 0.0);
+                    const double alpha = j == 0 ? 1.0 : sqrt(ok ? a2 : 1.0);
+                    if (j > 0 && !isfinite(a2)) {
+                        L.status[r] = GS2_ERR_NONFINITE;
+                        L.done[r] = 1;
+                    } else if (!ok) { // u fell into span(Q): end on the tentative column j-1
+                        for (int k = 0; k < j; ++k) col[k] = L.ht[k * R + r];
+                        col[j] = L.nu[r];
+                        if (bcommit(L, R, m, r, col, j - 1)) L.kk[r] = j;
+                        L.done[r] = 1;
+                    } else {
+                        bool good = true;
+                        if (j > 0) { // column j-1 corrected: [ht + nu a; nu alpha]
+                            for (int k = 0; k < j; ++k) col[k] = L.ht[k * R + r] + L.nu[r] * L.hA[k * R + r];
+                            col[j] = L.nu[r] * alpha;
+                            good = bcommit(L, R, m, r, col, j - 1);
+                            if (good) L.kk[r] = j;
+                        }
+                        if (!good) {
+                            L.done[r] = 1;
+                        } else {
+                            const double e = j == 0 ? L.nrm3[R + r] : (L.nrm3[R + r] - ac) / alpha;
+                            for (int k = 0; k < j; ++k) L.ht[k * R + r] = L.hB[k * R + r];
+                            L.ht[j * R + r] = e;
+                            L.wn2[r] = L.nrm3[2 * R + r];
+                            L.ia[r] = 1.0 / alpha;
+                            L.ev[r] = e;
+                        }
+                    }
+                    if (L.done[r]) {
+                        L.us[r] = 0.0;
+                        L.ia[r] = 0.0;
+                    }
+                }
+            }
             __syncthreads();
-            b_multidot<R>(n, V, nR, j + 1, w, 0, L.hB, L.red);
+            // pass 2: q_j over V_j, w' = w - Q c - e q_j into V_{j+1}, ||w'||^2
             double *vn = V + (int64_t)(j + 1) * nR;
-            b_update<R>(n, V, nR, j + 1, L.hB, w, vn);
-            __syncthreads();
-            b_multidot<R>(n, nullptr, 0, 0, vn, 1, L.nrm, L.red);
+            b_update2<R>(n, V, nR, j, L.hA, L.hB, vj, L.us, L.ia, L.ev, w, vn, L.nrm, L.red);
             if (t == 0) L.flag[0] = 0;
             __syncthreads();
-            if (t < R && !L.done[t]) {
+            if (t < R && !L.done[t]) { // tentative rotation of column j, residual estimate, stop test
                 const int r = t;
                 double *col = L.col + r * (m + 2);
-                for (int k = 0; k <= j; ++k) col[k] = L.hA[k * R + r] + L.hB[k * R + r];
-                const double hn = sqrt(L.nrm[r]);
-                const double wn0 = sqrt(L.wn2[r]);
+                const double nu = sqrt(L.nrm[r]);
+                L.nu[r] = nu;
+                for (int k = 0; k <= j; ++k) col[k] = L.ht[k * R + r];
+                col[j + 1] = nu;
                 for (int k = 0; k < j; ++k) {
                     const double a = L.cs[k * R + r] * col[k] + L.sn[k * R + r] * col[k + 1];
                     col[k + 1] = -L.sn[k * R + r] * col[k] + L.cs[k * R + r] * col[k + 1];
                     col[k] = a;
                 }
-                const double rho = hypot(col[j], hn);
-                L.iters[r]++;
-                if (!isfinite(rho) || !isfinite(hn)) {
+                const double rho = hypot(col[j], col[j + 1]);
+                if (!isfinite(rho) || !isfinite(nu)) {
                     L.status[r] = GS2_ERR_NONFINITE;
                     L.done[r] = 1;
-                    L.iters[r]--;
-                } else if (rho == 0.0) {
-                    L.status[r] = GS2_BREAKDOWN;
-                    L.done[r] = 1;
-                    L.iters[r]--;
                 } else {
-                    L.cs[j * R + r] = col[j] / rho;
-                    L.sn[j * R + r] = hn / rho;
-                    col[j] = rho;
-                    for (int k = 0; k <= j; ++k) L.H[(k * m + j) * R + r] = col[k];
-                    L.g[(j + 1) * R + r] = -L.sn[j * R + r] * L.g[j * R + r];
-                    L.g[j * R + r] = L.cs[j * R + r] * L.g[j * R + r];
-                    L.kk[r] = j + 1;
-                    const bool bd = hn <= 1e-14 * wn0;
-                    L.inv[r] = bd ? 0.0 : 1.0 / hn;
-                    if (fabs(L.g[(j + 1) * R + r]) <= rtol * L.bnorm[r] || bd || j + 1 >= m || L.iters[r] >= maxit)
+                    L.iters[r]++;
+                    const double est = rho > 0.0 ? fabs(col[j + 1] / rho * L.g[j * R + r]) : 0.0;
+                    const bool bd = nu <= 1e-14 * sqrt(L.wn2[r]);
+                    if (est <= rtol * L.bnorm[r] || bd || j + 1 >= m || L.iters[r] >= maxit) {
+                        for (int k = 0; k <= j; ++k) col[k] = L.ht[k * R + r];
+                        col[j + 1] = nu;
+                        if (bcommit(L, R, m, r, col, j)) L.kk[r] = j + 1;
+                        else L.iters[r]--;
                         L.done[r] = 1;
+                    } else {
+                        L.zs[(j + 1) * R + r] = 1.0 / nu;
+                        atomicOr(L.flag, 1);
+                    }
                 }
-                if (L.done[r]) L.inv[r] = 0.0;
-                else atomicOr(L.flag, 1);
             }
             __syncthreads();
-            const int more = L.flag[0];
-            for (int64_t i = t; i < nR; i += BT) vn[i] = L.inv[i % R] == 0.0 ? 0.0 : vn[i] * L.inv[i % R];
-            __syncthreads();
-            if (!more) break;
+            if (!L.flag[0]) break;
         }
         // y = R^{-1} g, x += Z y  (per right-hand side)
         if (t < R) {
@@ -652,7 +879,7 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
         for (int64_t i = t; i < nR; i += BT) {
             const int r = (int)(i % R);
             double acc = w2[i];
-            for (int k = 0; k < L.kk[r]; ++k) acc += L.y[k * R + r] * Z[(int64_t)k * nR + i];
+            for (int k = 0; k < L.kk[r]; ++k) acc += L.y[k * R + r] * L.zs[k * R + r] * Z[(int64_t)k * nR + i];
             w2[i] = acc;
         }
         __syncthreads();
