@@ -79,7 +79,8 @@ typedef struct gs2_options {
     int autotune;         /* 1: time candidate schedules at setup (default)  */
     int lanes_per_row;    /* 0 = automatic; else 1,2,4,...,64 (forced)       */
     int rhs_per_item;     /* batched: right-hand sides per work item, 0 =    */
-                          /* autotuned over {4,2,1} dividing nrhs            */
+                          /* tuned over {4,2,1} dividing nrhs (the smallest  */
+                          /* within 25% of the best one-cycle time)          */
     int orthogonalization; /* gmres_solve with this handle: 0 = CGS2 with    */
                            /* delayed reorthogonalisation (two passes over   */
                            /* the basis per step, default), 1 = CGS2 (four)  */
@@ -224,8 +225,12 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
 
 /*
  * As gs2_setup for nsys matrices As[0..nsys) (host array of descriptors of
- * device CSR arrays).  Allocates the workspace for GMRES(restart) with up to
- * nrhs right-hand sides per system.  opt->precision applies to every system.
+ * device CSR arrays).  Allocates the workspace for GMRES(restart), restart
+ * <= 32, with nrhs right-hand sides per system.  opt->precision applies to
+ * every system.  One workgroup solves one (system, group of right-hand
+ * sides) item start to finish: flexible GMRES in float64 with delayed
+ * reorthogonalisation, the preconditioner in the chosen precision.
+ * Synchronises `stream`; allocates.  Errors as gs2_setup.
  */
 int gs2_setup_batched(const gs2_csr *As, int nsys, int sweeps, int inner, double damping, int variant,
                       const gs2_options *opt, int restart, int nrhs, void *stream, gs2_batch **out);
