@@ -204,6 +204,23 @@ def test_ragged_and_tiny_sizes():
             assert rel_inf(host(z), oracle.sor_sweep(A, v, np.zeros(n), variant, sw, 1.0)) <= 1e-11
 
 
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 1023, 1025, 2049])
+@pytest.mark.parametrize("orth", [0, 1])
+def test_gmres_ragged_sizes(n, orth):
+    """GMRES at sizes around the 64-row slices and the 1024-row workgroups of
+    the Krylov kernels (partial last slice, partial last workgroup)."""
+    A = random_sparse(n, seed=60 + n, avg_offdiag=min(4, n - 1) if n > 1 else 0)
+    b = A.to_scipy() @ vec(n, 61)
+    xo, io = oracle.gmres(A, b, restart=20, rtol=1e-10, prec="gs2")
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD, orthogonalization=orth)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 20, 1e-10, 5000, g.PREC_GS2, h)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    xh = host(x)
+    assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-10
+
+
 def test_setup_errors():
     A = poisson2d(6)
     # zero diagonal
