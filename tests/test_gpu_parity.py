@@ -488,6 +488,56 @@ def test_full_size_laplace3d_apply_and_solve():
         assert np.linalg.norm(xh - p["x_true"]) / np.linalg.norm(p["x_true"]) <= 1e-4
 
 
+@pytest.mark.slow
+def test_full_size_vardiff_precision_forms():
+    """192^3 variable-coefficient diffusion (the precision-form workload):
+    one SGS2(1,1) apply per form compared element by element with the
+    oracle, and each form's GMRES(50) solve checked on the host (true
+    residual, error against the float64-preconditioner solution)."""
+    p = config_problem(4)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    S = A.to_scipy()
+    v = vec(A.n, 12)
+    xs = {}
+    for prec, tol in [(g.FP64, 2e-12), (g.FP32, 2e-5), (g.FP16_SCALED, 1e-4)]:
+        h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, precision=prec)
+        z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+        g.gs2_apply(h, dev(v), z)
+        ref = oracle.gs2_apply(A, v, g.SYMMETRIC, 1, 1, 1.0) if prec == g.FP64 else \
+            oracle.gs2_apply_lp(A, v, prec, g.SYMMETRIC, 1, 1, 1.0)
+        assert rel_inf(host(z), ref) <= tol
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        info = g.gmres_solve(dA, dev(b), x, 50, 1e-8, 5000, g.PREC_GS2, h)
+        assert info["converged"]
+        xs[prec] = host(x)
+        assert np.linalg.norm(b - S @ xs[prec]) / np.linalg.norm(b) <= 1e-8
+    for prec in (g.FP32, g.FP16_SCALED):  # equal final accuracy
+        assert np.linalg.norm(xs[prec] - xs[g.FP64]) / np.linalg.norm(xs[g.FP64]) <= 1e-6
+
+
+@pytest.mark.slow
+def test_full_size_elasticity_apply_and_jacobi_solve():
+    """64^3-node elasticity (786,432 rows, 61.7 M stored entries): damped
+    SGS2(1,3) and JR(3) applies element by element against the oracle, and
+    a Jacobi-preconditioned (JR(1)) GMRES(50) solve checked on the host."""
+    p = config_problem(3)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    v = vec(A.n, 13)
+    h = g.gs2_setup(dA, 1, 3, 0.7, g.SYMMETRIC)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), oracle.gs2_apply(A, v, g.SYMMETRIC, 1, 3, 0.7)) <= 4e-12
+    g.jr_apply(h, 3, 0.7, dev(v), z)
+    assert rel_inf(host(z), oracle.jr_sweep(A, v, np.zeros(A.n), 3, 0.7)) <= 3e-12
+    h1 = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 50, 1e-8, 6000, g.PREC_JR, h1)
+    assert info["converged"]
+    assert np.linalg.norm(b - A.to_scipy() @ host(x)) / np.linalg.norm(b) <= 1e-8
+
+
 # -------------------------------------------------------------------- PCG
 
 @pytest.mark.parametrize("prec,kind,kw", [
