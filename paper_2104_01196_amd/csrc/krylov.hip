@@ -720,16 +720,39 @@ __global__ void k_scale0(int64_t n, double *__restrict__ v, const GState *__rest
     if (i < n) v[i] *= st->inv;
 }
 
-// y = R^{-1} g over the kk columns of this cycle (single thread).
-__global__ void k_backsolve(GState *__restrict__ st)
+// y = R^{-1} g over the kk columns of this cycle (one wavefront).  Row k of
+// the triangular solve is a dot product over l > k, split over the lanes; the
+// lanes load row k-1 of R while row k is being reduced, so each row costs a
+// reduction rather than a memory latency.
+__global__ __launch_bounds__(WAVE) void k_backsolve(GState *__restrict__ st)
 {
-    if (threadIdx.x != 0) return;
-    const int kk = st->kk;
+    __shared__ double ys[MAXM];
+    const int kk = st->kk, ln = threadIdx.x;
+    constexpr int PER = (MAXM + WAVE - 1) / WAVE; // row entries per lane
+    double h[PER], hn[PER];
+    auto load_row = [&](int k, double (&dst)[PER]) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int l = k + 1 + ln + q * WAVE;
+            dst[q] = (k >= 0 && l < kk) ? st->H[k * MAXM + l] : 0.0;
+        }
+    };
+    load_row(kk - 1, h);
     for (int k = kk - 1; k >= 0; --k) {
-        double s = st->g[k];
-        for (int l = k + 1; l < kk; ++l) s -= st->H[k * MAXM + l] * st->y[l];
-        st->y[k] = s / st->H[k * MAXM + k];
+        load_row(k - 1, hn); // in flight while row k is reduced
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int l = k + 1 + ln + q * WAVE;
+            if (l < kk) p += h[q] * ys[l];
+        }
+        p = wave_sum(p);
+        if (ln == 0) ys[k] = (st->g[k] - p) / st->H[k * MAXM + k];
+        __syncthreads(); // one wavefront: orders the LDS write before the next row's reads
+#pragma unroll
+        for (int q = 0; q < PER; ++q) h[q] = hn[q];
     }
+    for (int k = ln; k < kk; k += WAVE) st->y[k] = ys[k];
 }
 
 // x += Z y (column k of Z weighed by its scale zs[k])
@@ -952,7 +975,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                 GS2_TRY_HIP(hipGetLastError());
             }
             prof_set_step(cycles - 1, -1);
-            k_backsolve<<<1, 64, 0, cs>>>(st);
+            k_backsolve<<<1, WAVE, 0, cs>>>(st);
             {
                 Prof pr(cs, PK_UPDATE_X, 8.0 * n * steps + 16.0 * n);
                 k_update_x<<<gE, KT, 0, cs>>>(n, Zb, n, st, x);

@@ -488,7 +488,8 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
                     GS2_TRY(build_part(h, h.L, PART_L, cand, A, sc, s));
                     float ms = 0.f;
                     GS2_TRY(time_inner_pass(h, s, &ms));
-                    if (ms < best) { best = ms; bestK = cand; }
+                    // a wider candidate must win by more than the timing noise
+                    if (ms < 0.97f * best) { best = ms; bestK = cand; }
                 }
                 K = bestK;
                 std::lock_guard<std::mutex> lk(g_tune_mu);
