@@ -41,93 +41,121 @@ __device__ __forceinline__ void finish(int dst, int64_t row, AT g, AT w, AT *gou
     }
 }
 
-// Inner JR pass: g_new = rh - w T g_old (optionally damped with gamma), one
-// wavefront per slice of T.  rv: rh_i = AT(v_i s_l[i]) (first half of an
-// apply); gv: g_old_j = AT(v_j s_l[j]) (its first inner pass).
-template <typename VT, typename AT, int K>
-__global__ __launch_bounds__(256) void k_inner(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView T, const AT *__restrict__ rh,
-                                               const AT *__restrict__ gin, const double *__restrict__ v,
-                                               const double *__restrict__ sl, int rv, int gv, int damp, AT w, AT gamma,
-                                               int dst, AT *__restrict__ gout, AT *__restrict__ xh,
-                                               double *__restrict__ z, const double *__restrict__ sr)
+// Slices per wavefront in the sweep kernels.  A slice of a 32-bit form
+// carries half the bytes of a float64 one, so its wavefront spends
+// proportionally more time on the fixed per-slice chain (slice pointer ->
+// columns -> gathered values); two slices per wavefront keep their loads in
+// flight together.  Measured on the 128^3 solve: float32 / scaled-float16
+// 38.2 / 37.9 -> 36.9 / 36.4 ms; for float64 one slice per wavefront stays
+// best (two or four were measured slower).
+template <typename AT>
+constexpr int su_of()
 {
-    if (stop && *stop) return;
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t s = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (s >= nslices) return;
-    const int64_t row = s * (WAVE / K) + lane / K;
-    const int64_t beg = T.sp[s], end = T.sp[s + 1];
+    return sizeof(AT) == 8 ? 1 : 2;
+}
+
+// acc[u] += sum over the stored entries of slice s0 + u of val * src(col)
+template <typename VT, typename AT, int SUN, typename Src>
+__device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t nslices, int lane, Src src,
+                                           AT (&acc)[SUN])
+{
+    int64_t beg[SUN];
+    int steps[SUN];
+    int tmax = 0;
+#pragma unroll
+    for (int u = 0; u < SUN; ++u) {
+        const int64_t s = s0 + u;
+        const bool ok = s < nslices;
+        beg[u] = ok ? T.sp[s] : 0;
+        steps[u] = ok ? (int)((T.sp[s + 1] - beg[u]) / WAVE) : 0;
+        tmax = steps[u] > tmax ? steps[u] : tmax;
+    }
     const VT *__restrict__ val = (const VT *)T.val;
     const int32_t *__restrict__ col = T.col;
-    AT acc = AT(0);
-    if (gv) {
 #pragma unroll 4
-        for (int64_t p = beg + lane; p < end; p += WAVE) {
-            const int c = col[p];
-            acc += (AT)val[p] * (AT)(v[c] * sl[c]);
+    for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+        for (int u = 0; u < SUN; ++u) {
+            if (t < steps[u]) {
+                const int64_t p = beg[u] + (int64_t)t * WAVE + lane;
+                acc[u] += (AT)val[p] * src(col[p]);
+            }
         }
-    } else {
-#pragma unroll 4
-        for (int64_t p = beg + lane; p < end; p += WAVE) acc += (AT)val[p] * gin[col[p]];
     }
-    if (K > 1) acc = group_sum<K>(acc);
-    if ((K > 1 && (lane & (K - 1))) || row >= n) return;
-    const AT r = rv ? (AT)(v[row] * sl[row]) : rh[row];
-    AT g = r - w * acc;
-    if (damp) {
-        const AT go = gv ? (AT)(v[row] * sl[row]) : gin[row];
-        g = (AT(1) - gamma) * go + gamma * g;
+}
+
+// Inner JR pass: g_new = rh - w T g_old (optionally damped with gamma), one
+// or two slices of T per wavefront.  rv: rh_i = AT(v_i s_l[i]) (first half
+// of an apply); gv: g_old_j = AT(v_j s_l[j]) (its first inner pass).
+template <typename VT, typename AT, int K>
+__global__ __launch_bounds__(256) void k_inner(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView T,
+                                               const AT *__restrict__ rh, const AT *__restrict__ gin,
+                                               const double *__restrict__ v, const double *__restrict__ sl, int rv,
+                                               int gv, int damp, AT w, AT gamma, int dst, AT *__restrict__ gout,
+                                               AT *__restrict__ xh, double *__restrict__ z,
+                                               const double *__restrict__ sr)
+{
+    constexpr int SUN = su_of<AT>();
+    if (stop && *stop) return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t s0 = (xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE) * SUN;
+    if (s0 >= nslices) return;
+    AT acc[SUN];
+#pragma unroll
+    for (int u = 0; u < SUN; ++u) acc[u] = AT(0);
+    if (gv) slice_dots<VT, AT, SUN>(T, s0, nslices, lane, [&](int c) { return (AT)(v[c] * sl[c]); }, acc);
+    else slice_dots<VT, AT, SUN>(T, s0, nslices, lane, [&](int c) { return gin[c]; }, acc);
+#pragma unroll
+    for (int u = 0; u < SUN; ++u) {
+        const AT a = K > 1 ? group_sum<K>(acc[u]) : acc[u];
+        const int64_t row = (s0 + u) * (WAVE / K) + lane / K;
+        if ((K > 1 && (lane & (K - 1))) || row >= n) continue;
+        const AT r = rv ? (AT)(v[row] * sl[row]) : rh[row];
+        AT g = r - w * a;
+        if (damp) {
+            const AT go = gv ? (AT)(v[row] * sl[row]) : gin[row];
+            g = (AT(1) - gamma) * go + gamma * g;
+        }
+        finish<AT>(dst, row, g, w, gout, xh, xh, z, sr);
     }
-    finish<AT>(dst, row, g, w, gout, xh, xh, z, sr);
 }
 
 // Outer residual pass.  compact = 0: rh = S_l v - xh - A xh (both triangles,
 // unit diagonal).  compact = 1: rh = S_l v - O xh - (1 - 1/w) xh with O the
 // triangle opposite to the inner one (eq. (two-stage-3) with damping).
 // The result goes to rh (DST_G) or is fused into a Jacobi-type update of xh
-// written to xout (double-buffered: xh is gathered here).  The triangles are
-// loaded non-temporally here (the gathered xh keeps the caches); the inner
-// pass keeps the default policy, since the following inner pass re-reads its
-// triangle (measured faster both ways).
+// written to xout (double-buffered: xh is gathered here).  The couplings to
+// other blocks (hybrid relaxation) multiply the values frozen at the last
+// exchange.  (Loading the triangles here with the non-temporal policy was
+// measured: no gain in float64, 3 % slower solves in the 32-bit forms.)
 template <typename VT, typename AT, int K>
-__global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView P, SellView Q, int two,
-                                               const AT *__restrict__ xh, const double *__restrict__ v,
-                                               const double *__restrict__ sl, AT cdiag, AT w, int dst,
-                                               AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
-                                               const double *__restrict__ sr, SellView Ev, const AT *__restrict__ ye)
+__global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView P,
+                                               SellView Q, int two, const AT *__restrict__ xh,
+                                               const double *__restrict__ v, const double *__restrict__ sl, AT cdiag,
+                                               AT w, int dst, AT *__restrict__ rh, AT *__restrict__ xout,
+                                               double *__restrict__ z, const double *__restrict__ sr, SellView Ev,
+                                               const AT *__restrict__ ye)
 {
+    constexpr int SUN = su_of<AT>();
     if (stop && *stop) return;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t s = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    if (s >= nslices) return;
-    const int64_t row = s * (WAVE / K) + lane / K;
-    AT acc = AT(0);
-    {
-        const VT *__restrict__ val = (const VT *)P.val;
-        const int32_t *__restrict__ col = P.col;
-        const int64_t beg = P.sp[s], end = P.sp[s + 1];
-#pragma unroll 4
-        for (int64_t p = beg + lane; p < end; p += WAVE)
-            acc += (AT)__builtin_nontemporal_load(&val[p]) * xh[__builtin_nontemporal_load(&col[p])];
+    const int64_t s0 = (xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE) * SUN;
+    if (s0 >= nslices) return;
+    AT acc[SUN];
+#pragma unroll
+    for (int u = 0; u < SUN; ++u) acc[u] = AT(0);
+    auto gx = [&](int c) { return xh[c]; };
+    slice_dots<VT, AT, SUN>(P, s0, nslices, lane, gx, acc);
+    if (two) slice_dots<VT, AT, SUN>(Q, s0, nslices, lane, gx, acc);
+    if (ye) slice_dots<VT, AT, SUN>(Ev, s0, nslices, lane, [&](int c) { return ye[c]; }, acc);
+#pragma unroll
+    for (int u = 0; u < SUN; ++u) {
+        const AT a = K > 1 ? group_sum<K>(acc[u]) : acc[u];
+        const int64_t row = (s0 + u) * (WAVE / K) + lane / K;
+        if ((K > 1 && (lane & (K - 1))) || row >= n) continue;
+        const AT r = ((AT)(v[row] * sl[row]) - cdiag * xh[row]) - a;
+        finish<AT>(dst, row, r, w, rh, const_cast<AT *>(xh), xout, z, sr);
     }
-    if (two) {
-        const VT *__restrict__ val = (const VT *)Q.val;
-        const int32_t *__restrict__ col = Q.col;
-        const int64_t beg = Q.sp[s], end = Q.sp[s + 1];
-#pragma unroll 4
-        for (int64_t p = beg + lane; p < end; p += WAVE)
-            acc += (AT)__builtin_nontemporal_load(&val[p]) * xh[__builtin_nontemporal_load(&col[p])];
-    }
-    if (ye) { // couplings to other blocks, on the values frozen at the last exchange
-        const VT *__restrict__ val = (const VT *)Ev.val;
-        const int32_t *__restrict__ col = Ev.col;
-        const int64_t beg = Ev.sp[s], end = Ev.sp[s + 1];
-        for (int64_t p = beg + lane; p < end; p += WAVE) acc += (AT)val[p] * ye[col[p]];
-    }
-    if (K > 1) acc = group_sum<K>(acc);
-    if ((K > 1 && (lane & (K - 1))) || row >= n) return;
-    const AT r = ((AT)(v[row] * sl[row]) - cdiag * xh[row]) - acc;
-    finish<AT>(dst, row, r, w, rh, const_cast<AT *>(xh), xout, z, sr);
 }
 
 // First half of JR from xh = 0: xh = w S_l v, or z = S_r w S_l v if final.
@@ -240,7 +268,11 @@ __global__ void k_color(const int *__restrict__ stop, const int32_t *__restrict_
 
 constexpr int TB = 256; // 4 wavefronts per workgroup, one slice each
 
-static inline unsigned grid_for(int64_t nslices) { return (unsigned)std::max<int64_t>(1, (nslices + 3) / 4); }
+static inline unsigned grid_for(int64_t nslices, int su)
+{
+    const int64_t per = 4 * su;
+    return (unsigned)std::max<int64_t>(1, (nslices + per - 1) / per);
+}
 static inline unsigned grid_rows(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + TB - 1) / TB); }
 
 template <typename VT, typename AT>
@@ -250,7 +282,7 @@ struct Launch {
                         int dst, AT *gout, AT *xh, double *z, hipStream_t s)
     {
         const int damp = h.gamma != 1.0;
-        k_inner<VT, AT, K><<<grid_for(T.nslices), TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv, gv, damp,
+        k_inner<VT, AT, K><<<grid_for(T.nslices, su_of<AT>()), TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv, gv, damp,
                                                               (AT)h.omega, (AT)h.gamma, dst, gout, xh, z, h.sr);
     }
     // algorithmic bytes of one pass: each stored entry (value + column) and
@@ -287,7 +319,7 @@ struct Launch {
     static void resid_k(const Handle &h, const Sell &P, const Sell *Q, const AT *xh, const double *v, AT cdiag, AT w,
                         int dst, AT *rh, AT *xout, double *z, hipStream_t s, const AT *ye)
     {
-        k_resid<VT, AT, K><<<grid_for(P.nslices), TB, 0, s>>>(h.stop, h.n, P.nslices, view(P), Q ? view(*Q) : view(P),
+        k_resid<VT, AT, K><<<grid_for(P.nslices, su_of<AT>()), TB, 0, s>>>(h.stop, h.n, P.nslices, view(P), Q ? view(*Q) : view(P),
                                                               Q ? 1 : 0, xh, v, h.sl, cdiag, w, dst, rh, xout, z, h.sr,
                                                               ye ? view(h.E) : view(P), ye);
     }
