@@ -9,7 +9,8 @@ One "step" is one complete solve (the whole preconditioned Krylov path:
 setup excluded, done once before timing).  `value` is the mean time to
 solution of the float64-preconditioner solve over the timed steps (median and
 spread reported with it); the float32 and scaled-float16 preconditioner
-solves are timed the same way and reported next to it.
+solves are timed the same way and reported next to it, each with the
+algorithmic bandwidth of its sweep kernels from a profiled pass.
 
 Two further measurements print their own JSON line (not the default):
 --config 4 times the precision forms (FP64 / FP32 / scaled-FP16 SGS2(1,1)
@@ -151,7 +152,8 @@ def main():
             each.append(time.perf_counter() - te)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / args.steps
-        if headline and args.profile == "on":
+        form_prof = None
+        if args.profile == "on":
             # the same solves again with every launch bracketed by HIP events on
             # its stream (kernel by kernel: events do not time graph replays)
             g.gs2_profile(True)
@@ -160,9 +162,11 @@ def main():
             for _ in range(args.steps):
                 solve(h, x)
             torch.cuda.synchronize()
-            prof_solve_s = (time.perf_counter() - tp) / args.steps
             g.gs2_profile(False)
-            prof = g.gs2_profile_read()
+            form_prof = g.gs2_profile_read()
+            if headline:
+                prof_solve_s = (time.perf_counter() - tp) / args.steps
+                prof = form_prof
         xs = x.cpu().numpy()
         if xref is None:
             xref = xs
@@ -173,6 +177,12 @@ def main():
                          "converged": info["converged"], "relres_true": rel, "setup_s": setup_s, "lanes_per_row": lanes,
                          "rel_err_vs_fp64_solution": float(np.linalg.norm(xs - xref) / np.linalg.norm(xref)),
                          "rel_err_vs_x_true": float(np.linalg.norm(xs - p["x_true"]) / np.linalg.norm(p["x_true"]))}
+        if form_prof:  # the sweep kernels' algorithmic bandwidth in this form
+            results[name]["sweep_GBps"] = {
+                k: (r["bytes"] / r["launches"]) / ((r["ms"] / r["launches"]) * 1e-3) / 1e9
+                for k, r in form_prof.items() if k in ("gs2_inner", "gs2_resid", "gs2_first_jr") and r["bytes"]}
+            log(f"[bench] {name} sweep kernels: " + ", ".join(
+                f"{k} {v:.0f} GB/s ({100 * v / HBM_PEAK_GBS:.1f}%)" for k, v in results[name]["sweep_GBps"].items()))
         log(f"[bench] {name}: {dt * 1e3:.2f} ms/solve (median {np.median(each) * 1e3:.2f}, spread "
             f"{min(each) * 1e3:.2f}-{max(each) * 1e3:.2f}), its={info['iterations']}, relres={rel:.2e}, "
             f"setup {setup_s:.2f}s, {lanes} lanes/row")
