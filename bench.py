@@ -20,7 +20,11 @@ convection-diffusion systems x 4 right-hand sides, GS2(2,2), GMRES(20),
 FP32 and FP64 preconditioner) against the plain FP64 path that solves the
 2048 systems one gmres_solve at a time.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--config 2|4|5]
+--compare times GMRES(50) on the default workload with each preconditioner
+of the paper's comparison (GS2, SGS2, JR, exact level-scheduled GS/SGS,
+multicolor GS, none).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--config 2|4|5] [--compare]
 """
 from __future__ import annotations
 
@@ -45,6 +49,9 @@ def parse():
     ap.add_argument("--config", type=int, default=2, choices=[2, 4, 5],
                     help="2: the benchmark workload (default); 4: precision forms on the 192^3 variable-coefficient "
                          "problem; 5: batched form on 512 convection-diffusion systems x 4 right-hand sides")
+    ap.add_argument("--compare", action="store_true",
+                    help="with --config 2: GMRES(50) with each preconditioner of the comparison (GS2, SGS2, JR, "
+                         "exact level-scheduled GS, multicolor GS) instead of the default measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16 preconditioner solves")
     ap.add_argument("--profile", choices=["on", "off"], default="on",
@@ -103,6 +110,8 @@ def main():
 
     if args.config == 5:
         return bench_batched(args, g, torch, np)
+    if args.compare:
+        return bench_compare(args, g, torch, np)
     dev = torch.device("cuda:0")
     t0 = time.time()
     cfg = args.config
@@ -252,6 +261,66 @@ def main():
         "forms": results,
         "kernels": kernels,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_compare(args, g, torch, np):
+    """GMRES(50) on the 128^3 Laplacian with each preconditioner of the
+    paper's comparison: time to solution (graph-replayed), iterations, and
+    the preconditioner's share from a profiled pass (events per launch)."""
+    from gen import config_problem
+
+    size = args.size or 128
+    p = config_problem(2, size=size)
+    A, b = p["A"], p["b"]
+    dA = g.DeviceCSR.from_host(A)
+    db = torch.as_tensor(b, device="cuda")
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    # name, kind, setup (sweeps, inner, damping, variant, build_levels)
+    cases = [("GS2-FWD(2,1)", g.PREC_GS2, (2, 1, 1.0, g.FORWARD, False)),
+             ("GS2-FWD(2,2)", g.PREC_GS2, (2, 2, 1.0, g.FORWARD, False)),
+             ("GS2-FWD(2,3)", g.PREC_GS2, (2, 3, 1.0, g.FORWARD, False)),
+             ("SGS2(1,1)", g.PREC_GS2, (1, 1, 1.0, g.SYMMETRIC, False)),
+             ("SGS2(2,1)", g.PREC_GS2, (2, 1, 1.0, g.SYMMETRIC, False)),
+             ("SGS2(2,2)", g.PREC_GS2, (2, 2, 1.0, g.SYMMETRIC, False)),
+             ("JR(3)", g.PREC_JR, (3, 1, 1.0, g.FORWARD, False)),
+             ("GS-FWD(2) exact, level-scheduled", g.PREC_GS_TRISOLVE, (2, 1, 1.0, g.FORWARD, True)),
+             ("SGS(1) exact, level-scheduled", g.PREC_GS_TRISOLVE, (1, 1, 1.0, g.SYMMETRIC, True)),
+             ("MT-GS-FWD(2) multicolor", g.PREC_MTGS, (2, 1, 1.0, g.FORWARD, True)),
+             ("none", g.PREC_NONE, None)]
+    pre_kinds = ("gs2_inner", "gs2_resid", "gs2_first_jr", "trisolve_level")
+    res = {}
+    for name, kind, cfg in cases:
+        h = None
+        if cfg:
+            sw, inner, w, var, lev = cfg
+            h = g.gs2_setup(dA, sw, inner, w, var, build_levels=lev)
+        solve = lambda: (x.zero_(), g.gmres_solve(dA, db, x, 50, 1e-8, 20000, kind, h))[1]
+        solve()
+        torch.cuda.synchronize()
+        each = []
+        for _ in range(args.steps):
+            te = time.perf_counter()
+            info = solve()
+            each.append(time.perf_counter() - te)
+        g.gs2_profile(True)
+        solve()
+        g.gs2_profile(False)
+        prof = g.gs2_profile_read()
+        pre_ms = sum(r["ms"] for k, r in prof.items() if k in pre_kinds)
+        rel = float(np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) / np.linalg.norm(b))
+        its = info["iterations"]
+        res[name] = {"time_s": float(np.median(each)), "iterations": its, "converged": info["converged"],
+                     "relres_true": rel, "precond_ms_per_apply": pre_ms / max(its, 1) if kind != g.PREC_NONE else 0.0}
+        log(f"[bench] {name:34s} {res[name]['time_s'] * 1e3:8.2f} ms  its {its:4d}  "
+            f"precond {res[name]['precond_ms_per_apply'] * 1e3:8.1f} us/apply  relres {rel:.2e}")
+        del h
+    out = {"metric": "GS2-GMRES time-to-solution (s) by preconditioner", "value": res["GS2-FWD(2,1)"]["time_s"],
+           "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f64",
+           "config": {"workload": f"laplace3d_7pt_{size}^3 GMRES(50) rtol 1e-8, preconditioner comparison",
+                      "n": A.n, "nnz": A.nnz},
+           "preconditioners": res}
     print(json.dumps(out), flush=True)
 
 
