@@ -79,8 +79,9 @@ typedef struct gs2_options {
     int autotune;         /* 1: time candidate schedules at setup (default)  */
     int lanes_per_row;    /* 0 = automatic; else 1,2,4,...,64 (forced)       */
     int rhs_per_item;     /* batched: right-hand sides per work item, 0 =    */
-                          /* tuned over {4,2,1} dividing nrhs (the smallest  */
-                          /* within 25% of the best one-cycle time)          */
+                          /* tuned over {4,2,1} dividing nrhs (the fastest   */
+                          /* one-cycle time; with team_rows < 0 the smallest */
+                          /* R within 25% of it)                             */
     int orthogonalization; /* gmres_solve with this handle: 0 = CGS2 with    */
                            /* delayed reorthogonalisation (two passes over   */
                            /* the basis per step, default), 1 = CGS2 (four)  */
@@ -88,6 +89,11 @@ typedef struct gs2_options {
                           /* contiguous row blocks (0 or 1 = global GS2)     */
     int local_sweeps;     /* n_k local sweeps per global sweep with frozen   */
                           /* off-block values (0 or 1 = one)                 */
+    int team_rows;        /* batched: rows x right-hand sides per workgroup  */
+                          /* of a team; an item of n rows and R right-hand   */
+                          /* sides is solved by round(n R / team_rows)       */
+                          /* workgroups (1..8).  0 = default (32768), < 0 =  */
+                          /* one workgroup per item                          */
 } gs2_options;
 
 typedef struct gs2_solve_info {
@@ -227,10 +233,13 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * As gs2_setup for nsys matrices As[0..nsys) (host array of descriptors of
  * device CSR arrays).  Allocates the workspace for GMRES(restart), restart
  * <= 32, with nrhs right-hand sides per system.  opt->precision applies to
- * every system.  One workgroup solves one (system, group of right-hand
+ * every system.  A team of workgroups (one for most items, up to 8 for the
+ * largest, see opt->team_rows) solves one (system, group of right-hand
  * sides) item start to finish: flexible GMRES in float64 with delayed
- * reorthogonalisation, the preconditioner in the chosen precision.
- * Synchronises `stream`; allocates.  Errors as gs2_setup.
+ * reorthogonalisation, the preconditioner in the chosen precision.  A
+ * team's members synchronise through a bounded wait; should one ever exceed
+ * 30 s, the item is abandoned and reported with GS2_ERR_HIP instead of the
+ * launch hanging.  Synchronises `stream`; allocates.  Errors as gs2_setup.
  */
 int gs2_setup_batched(const gs2_csr *As, int nsys, int sweeps, int inner, double damping, int variant,
                       const gs2_options *opt, int restart, int nrhs, void *stream, gs2_batch **out);

@@ -3,11 +3,17 @@
 // systems of Section 10 motivate it).
 //
 // One persistent kernel launch solves everything.  A work item is one system
-// together with a group of R right-hand sides; it is solved start to finish
-// by a single workgroup, so every reduction and every ordering point is a
-// workgroup barrier and no workgroup ever waits for another.  Workgroups pop
-// items from an atomic counter, largest systems first (longest processing
-// time first), and leave when the queue is empty.  The R right-hand sides of
+// together with a group of R right-hand sides, solved start to finish by a
+// team of G workgroups: G = 1 for most items, so that every reduction and
+// every ordering point is a workgroup barrier, and up to 8 for the largest,
+// whose single-workgroup time (rows x iterations, and the iteration count
+// grows with the system) would otherwise outlast everything else.  Workgroups
+// pop (item, member) slots from an atomic counter, largest systems first
+// (longest processing time first), and leave when the queue is empty.  A
+// team's rows are split among its members; its passes are separated by a
+// barrier on a per-item arrival counter (agent-scope release / acquire), and
+// its reductions sum the members' partials in member order, so every member
+// holds bit-identical scalars and repeats the small serial work itself.  The R right-hand sides of
 // an item are stored interleaved (row-major n x R), so each matrix entry is
 // loaded once per group and applied to R vectors (an SpMM-like access).
 // Each right-hand side keeps its own Hessenberg matrix, rotations and
@@ -51,6 +57,13 @@ struct BSys {
 struct BItem {
     int sys, r0;
     int64_t base; // scalar offset (row x rhs units) of this item's vectors
+    int G;        // workgroups in the item's team
+    int pad;
+    int64_t xoff; // offset of the team's exchange area (2 x G x XS doubles)
+};
+
+struct BSlot {
+    int item, member;
 };
 
 struct BParams {
@@ -71,7 +84,115 @@ struct BConst {
     unsigned *queue;
     gs2_solve_info *info;
     const BParams *prm;
+    const BSlot *slots;
+    int nslots, pad;
+    unsigned *tbar;   // per item: team barrier arrivals
+    double *xch;      // team reduction exchange areas
+    int *abort;       // set when a team barrier times out
+    long long spin_ticks; // wall-clock ticks a team barrier may wait
 };
+
+// Exchange slots per member and buffer: the largest team reduction is pass 1
+// of the delayed reorthogonalisation, (2m + 3) R values.
+constexpr int XS = (2 * BMAXM + 3) * 4 + 4;
+
+// A team of G workgroups solving one item; member me.  ep (in LDS) counts
+// the team barriers passed (the same in every member), ab (in LDS) is set
+// once the team has aborted.  With G = 1 every team operation is a plain
+// workgroup barrier.
+struct BTeam {
+    int G, me;
+    unsigned *bar;
+    double *xch;
+    int *abort;
+    long long spin;
+    unsigned *ep;
+    int *ab;
+};
+
+// this workgroup's share of an item's rows: thread / wavefront index within
+// the team and the team's totals
+__device__ __forceinline__ int64_t tthread(const BTeam &T) { return (int64_t)T.me * BT + threadIdx.x; }
+__device__ __forceinline__ int64_t tthreads(const BTeam &T) { return (int64_t)T.G * BT; }
+__device__ __forceinline__ int64_t twave(const BTeam &T) { return (int64_t)T.me * BNW + threadIdx.x / WAVE; }
+__device__ __forceinline__ int64_t twaves(const BTeam &T) { return (int64_t)T.G * BNW; }
+
+// Team barrier: every member's global writes before it are visible to every
+// member after it.  Each wavefront first waits for its own stores to reach
+// the L2 (a workgroup barrier alone does not), then one thread per workgroup
+// arrives with a release at agent scope (the L2 is written back, which makes
+// the writes visible to workgroups on other XCDs) and waits for
+// G * (epoch + 1) arrivals; every thread then acquires at agent scope.  The
+// wait is bounded: past spin ticks of the wall clock the abort flag is
+// raised, every waiting member leaves, and the item ends with an error
+// instead of a hang.  Returns false once aborted.  Out of line, so that
+// single-workgroup items (G = 1, a plain workgroup barrier) do not carry its
+// registers.
+__device__ __noinline__ bool team_wait(const BTeam T)
+{
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(T.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned target = (unsigned)T.G * (*T.ep + 1);
+        const long long t0 = wall_clock64();
+        int ab = 0;
+        while (__hip_atomic_load(T.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ab = 1;
+                break;
+            }
+            if (wall_clock64() - t0 > T.spin) {
+                __hip_atomic_store(T.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (ab) *T.ab = 1;
+        *T.ep += 1;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *T.ab == 0;
+}
+
+__device__ __forceinline__ bool team_sync(const BTeam &T)
+{
+    __syncthreads();
+    if (T.G == 1) return true;
+    return team_wait(T);
+}
+
+// Sum the members' partials of up to three LDS arrays (lengths c0, c1, c2,
+// c0 + c1 + c2 <= XS) in member order; every member gets the same bits.
+// Buffers alternate with the barrier count, so a member that runs ahead into
+// the next reduction never overwrites partials still being read.
+__device__ __noinline__ void team_sum_wait(const BTeam T, double *a0, int c0, double *a1, int c1, double *a2, int c2)
+{
+    const int tot = c0 + c1 + c2;
+    double *buf = T.xch + (size_t)(*T.ep & 1u) * T.G * XS;
+    for (int i = threadIdx.x; i < tot; i += BT)
+        buf[(size_t)T.me * XS + i] = i < c0 ? a0[i] : i < c0 + c1 ? a1[i - c0] : a2[i - c0 - c1];
+    __syncthreads();
+    if (!team_wait(T)) return;
+    for (int i = threadIdx.x; i < tot; i += BT) {
+        double s = 0.0;
+        for (int q = 0; q < T.G; ++q) s += buf[(size_t)q * XS + i];
+        if (i < c0) a0[i] = s;
+        else if (i < c0 + c1) a1[i - c0] = s;
+        else a2[i - c0 - c1] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void team_sum(const BTeam &T, double *a0, int c0, double *a1 = nullptr, int c1 = 0,
+                                         double *a2 = nullptr, int c2 = 0)
+{
+    if (T.G == 1) return;
+    team_sum_wait(T, a0, c0, a1, c1, a2, c2);
+}
 
 enum : int { BD_G = 0, BD_XADD = 1, BD_XSET = 2, BD_ZADD = 3, BD_ZSET = 4 };
 
@@ -145,15 +266,15 @@ __device__ __forceinline__ void bslice_dots(const int64_t *sp, const int32_t *co
 
 // inner JR pass g = rh - w T g_old for R interleaved right-hand sides
 template <typename VT, typename AT, int R, int K>
-__device__ void bp_inner(const BSys &S, int lower, const AT *rh, const AT *gin, const double *v, int rv, int gv,
-                         int damp, AT w, AT gamma, int dst, AT *gout, AT *xh, double *z)
+__device__ void bp_inner(const BTeam T, const BSys &S, int lower, const AT *rh, const AT *gin, const double *v, int rv,
+                         int gv, int damp, AT w, AT gamma, int dst, AT *gout, AT *xh, double *z)
 {
     constexpr int BU = bu_of<AT, R>();
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
     const int64_t *sp = lower ? S.Lsp : S.Usp;
     const int32_t *col = lower ? S.Lcol : S.Ucol;
     const VT *val = (const VT *)(lower ? S.Lval : S.Uval);
-    for (int64_t s0 = (int64_t)wv * BU; s0 < S.nslices; s0 += (int64_t)BNW * BU) {
+    for (int64_t s0 = twave(T) * BU; s0 < S.nslices; s0 += twaves(T) * BU) {
         AT acc[BU][R];
 #pragma unroll
         for (int u = 0; u < BU; ++u)
@@ -191,13 +312,13 @@ __device__ void bp_inner(const BSys &S, int lower, const AT *rh, const AT *gin, 
 
 // outer residual (non-compact: both triangles; compact: the opposite one)
 template <typename VT, typename AT, int R, int K>
-__device__ void bp_resid(const BSys &S, int lower, int compact, const AT *xh, const double *v, AT cdiag, AT w, int dst,
-                         AT *rh, AT *xout, double *z)
+__device__ __forceinline__ void bp_resid(const BTeam T, const BSys &S, int lower, int compact, const AT *xh, const double *v, AT cdiag,
+                         AT w, int dst, AT *rh, AT *xout, double *z)
 {
     constexpr int BU = bu_of<AT, R>();
-    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
     auto gx = [&](int c, int r) { return xh[(int64_t)c * R + r]; };
-    for (int64_t s0 = (int64_t)wv * BU; s0 < S.nslices; s0 += (int64_t)BNW * BU) {
+    for (int64_t s0 = twave(T) * BU; s0 < S.nslices; s0 += twaves(T) * BU) {
         AT acc[BU][R];
 #pragma unroll
         for (int u = 0; u < BU; ++u)
@@ -227,9 +348,9 @@ __device__ void bp_resid(const BSys &S, int lower, int compact, const AT *xh, co
 }
 
 template <typename AT, int R>
-__device__ void bp_first_jr(const BSys &S, const double *v, AT w, int fin, AT *xh, double *z)
+__device__ void bp_first_jr(const BTeam T, const BSys &S, const double *v, AT w, int fin, AT *xh, double *z)
 {
-    for (int64_t i = threadIdx.x; i < S.n * R; i += BT) {
+    for (int64_t i = tthread(T); i < S.n * R; i += tthreads(T)) {
         const int64_t row = i / R;
         const AT r = (AT)(v[i] * S.sl[row]);
         if (fin) z[i] = S.sr[row] * (double)(w * r);
@@ -238,10 +359,9 @@ __device__ void bp_first_jr(const BSys &S, const double *v, AT w, int fin, AT *x
 }
 
 // z = Mhat^{-1} v for the R right-hand sides of one system (the same pass
-// sequence as the single-system apply, with a workgroup barrier between
-// passes).
+// sequence as the single-system apply, with a team barrier between passes).
 template <typename VT, typename AT, int R, int K>
-__device__ void b_precond(const BConst &c, const BSys &S, const double *v, double *z, AT *P)
+__device__ void b_precond(const BTeam &T, const BConst &c, const BSys &S, const double *v, double *z, AT *P)
 {
     const int64_t nR = S.n * R;
     AT *xa = P, *xb = P + nR, *rh = P + 2 * nR, *ga = P + 3 * nR, *gb = P + 4 * nR;
@@ -258,21 +378,21 @@ __device__ void b_precond(const BConst &c, const BSys &S, const double *v, doubl
         const bool set = xzero || c.compact;
         if (c.inner == 0) {
             if (xzero) {
-                bp_first_jr<AT, R>(S, v, w, fin ? 1 : 0, xc, z);
+                bp_first_jr<AT, R>(T, S, v, w, fin ? 1 : 0, xc, z);
             } else {
                 const int dst = fin ? (set ? BD_ZSET : BD_ZADD) : (set ? BD_XSET : BD_XADD);
-                bp_resid<VT, AT, R, K>(S, lower, c.compact, xc, v, cdiag, w, dst, nullptr, xo, z);
+                bp_resid<VT, AT, R, K>(T, S, lower, c.compact, xc, v, cdiag, w, dst, nullptr, xo, z);
                 AT *tmp = xc;
                 xc = xo;
                 xo = tmp;
             }
-            __syncthreads();
+            team_sync(T);
         } else {
             int rv = 1;
             if (!xzero) {
-                bp_resid<VT, AT, R, K>(S, lower, c.compact, xc, v, cdiag, w, BD_G, rh, nullptr, nullptr);
+                bp_resid<VT, AT, R, K>(T, S, lower, c.compact, xc, v, cdiag, w, BD_G, rh, nullptr, nullptr);
                 rv = 0;
-                __syncthreads();
+                team_sync(T);
             }
             const AT *gin = rh;
             for (int j = 1; j <= c.inner; ++j) {
@@ -280,9 +400,9 @@ __device__ void b_precond(const BConst &c, const BSys &S, const double *v, doubl
                 const int gv = (j == 1 && xzero) ? 1 : 0;
                 AT *gout = (j & 1) ? ga : gb;
                 const int dst = !last ? BD_G : fin ? (set ? BD_ZSET : BD_ZADD) : (set ? BD_XSET : BD_XADD);
-                bp_inner<VT, AT, R, K>(S, lower, rh, gin, v, rv, gv, damp, w, gamma, dst, gout, xc, z);
+                bp_inner<VT, AT, R, K>(T, S, lower, rh, gin, v, rv, gv, damp, w, gamma, dst, gout, xc, z);
                 gin = gout;
-                __syncthreads();
+                team_sync(T);
             }
         }
         xzero = false;
@@ -296,16 +416,17 @@ __device__ void b_precond(const BConst &c, const BSys &S, const double *v, doubl
 // thread works on RU rows (RU*BT apart) at once so that their CSR chains
 // (row pointer -> column -> z) are in flight together.
 template <int R>
-__device__ void b_spmv(const BSys &S, const double *z, double *w, const double *b, int64_t bstride,
+__device__ void b_spmv(const BTeam T, const BSys &S, const double *z, double *w, const double *b, int64_t bstride,
                        const double *scl = nullptr)
 {
     constexpr int RU = 4 / R;
-    for (int64_t r0 = threadIdx.x; r0 < S.n; r0 += (int64_t)BT * RU) {
+    const int64_t NT = tthreads(T);
+    for (int64_t r0 = tthread(T); r0 < S.n; r0 += NT * RU) {
         int pb[RU], pe[RU];
         int len = 0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            const int64_t row = r0 + (int64_t)u * BT;
+            const int64_t row = r0 + (int64_t)u * NT;
             pb[u] = row < S.n ? S.rp[row] : 0;
             pe[u] = row < S.n ? S.rp[row + 1] : 0;
             len = pe[u] - pb[u] > len ? pe[u] - pb[u] : len;
@@ -339,7 +460,7 @@ __device__ void b_spmv(const BSys &S, const double *z, double *w, const double *
         }
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            const int64_t row = r0 + (int64_t)u * BT;
+            const int64_t row = r0 + (int64_t)u * NT;
             if (row >= S.n) continue;
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -351,10 +472,11 @@ __device__ void b_spmv(const BSys &S, const double *z, double *w, const double *
 // out[k*R + r] = <V_k(:,r), w(:,r)> for k < nk, then (with_norm) out[nk*R + r]
 // = ||w(:,r)||^2.  Chunks of KC vectors; fixed-order reductions.
 template <int R>
-__device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, const double *w, int with_norm,
-                           double *out, double *red)
+__device__ __forceinline__ void b_multidot(const BTeam &T, int64_t n, const double *V, int64_t ldv, int nk, const double *w,
+                           int with_norm, double *out, double *red)
 {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int64_t NT = tthreads(T);
     constexpr int KC = kc_of<R>();
     const int stride_red = RED_STRIDE;
     for (int k0 = 0; k0 < nk || (k0 == 0 && with_norm); k0 += KC) {
@@ -371,11 +493,11 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
         // RU rows per thread at once: all their loads are issued before use, since
         // a workgroup's few wavefronts cannot hide one memory latency per row
         constexpr int RU = 2;
-        for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
+        for (int64_t r0 = tthread(T); r0 < n; r0 += NT * RU) {
             double wr[RU][R];
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
-                const int64_t row = r0 + (int64_t)u * BT;
+                const int64_t row = r0 + (int64_t)u * NT;
                 const int64_t rr = row < n ? row : n - 1; // clamped; its factor is zero
 #pragma unroll
                 for (int r = 0; r < R; ++r) wr[u][r] = row < n ? w[rr * R + r] : 0.0;
@@ -386,7 +508,7 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
                     const double *vk = V + (int64_t)(k0 + kk) * ldv;
 #pragma unroll
                     for (int u = 0; u < RU; ++u) {
-                        const int64_t row = r0 + (int64_t)u * BT;
+                        const int64_t row = r0 + (int64_t)u * NT;
                         const int64_t rr = row < n ? row : n - 1;
 #pragma unroll
                         for (int r = 0; r < R; ++r) acc[kk][r] += vk[rr * R + r] * wr[u][r];
@@ -429,6 +551,7 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
         __syncthreads();
         if (nk <= 0) break;
     }
+    team_sum(T, out, (nk > 0 ? nk : 0) * R + (with_norm ? R : 0));
 }
 
 // Pass 1 of the delayed reorthogonalisation for R interleaved right-hand
@@ -437,12 +560,13 @@ __device__ void b_multidot(int64_t n, const double *V, int64_t ldv, int nk, cons
 // outN[r], outN[R + r], outN[2R + r] = u.u, u.w, w.w.  Chunks of KC2 vectors
 // (2*KC2*R + 3R <= RED_STRIDE reduction slots); fixed-order reductions.
 template <int R>
-__device__ void b_multidot2(int64_t n, const double *V, int64_t ldv, int nk, const double *uraw, const double *us,
-                            const double *w, double *outA, double *outC, double *outN, double *red)
+__device__ __forceinline__ void b_multidot2(const BTeam &T, int64_t n, const double *V, int64_t ldv, int nk, const double *uraw,
+                            const double *us, const double *w, double *outA, double *outC, double *outN, double *red)
 {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     constexpr int KC2 = 4 / R;
     constexpr int RU = 2;
+    const int64_t NT = tthreads(T);
     for (int k0 = 0; k0 < nk || k0 == 0; k0 += KC2) {
         const int kc = min(KC2, nk - k0);
         const bool nrm = k0 == 0;
@@ -455,12 +579,12 @@ __device__ void b_multidot2(int64_t n, const double *V, int64_t ldv, int nk, con
         for (int q = 0; q < 3; ++q)
 #pragma unroll
             for (int r = 0; r < R; ++r) nn[q][r] = 0.0;
-        for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
+        for (int64_t r0 = tthread(T); r0 < n; r0 += NT * RU) {
             double ur[RU][R], wr[RU][R];
             int64_t rr[RU];
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
-                const int64_t row = r0 + (int64_t)u * BT;
+                const int64_t row = r0 + (int64_t)u * NT;
                 rr[u] = row < n ? row : n - 1; // clamped; its factors are zero
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -539,27 +663,30 @@ __device__ void b_multidot2(int64_t n, const double *V, int64_t ldv, int nk, con
         __syncthreads();
         if (nk <= 0) break;
     }
+    const int cnt = (nk > 0 ? nk : 0) * R;
+    team_sum(T, outA, cnt, outC, cnt, outN, 3 * R);
 }
 
 // Pass 2 for R interleaved right-hand sides: q = (us[r] uraw - sum_k a_k V_k)
 // * ia[r] over uraw's slot, w' = w - sum_k c_k V_k - e[r] q into wn, and
 // nrm[r] = ||w'||^2.  Vectors outer, RU rows per thread inner.
 template <int R>
-__device__ void b_update2(int64_t n, const double *V, int64_t ldv, int nk, const double *a, const double *cvec,
-                          double *uraw, const double *us, const double *ia, const double *e, const double *w,
-                          double *wn, double *nrm, double *red)
+__device__ __forceinline__ void b_update2(const BTeam &T, int64_t n, const double *V, int64_t ldv, int nk, const double *a,
+                          const double *cvec, double *uraw, const double *us, const double *ia, const double *e,
+                          const double *w, double *wn, double *nrm, double *red)
 {
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     constexpr int RU = 4 / R;
+    const int64_t NT = tthreads(T);
     double nacc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) nacc[r] = 0.0;
-    for (int64_t r0 = threadIdx.x; r0 < n; r0 += (int64_t)BT * RU) {
+    for (int64_t r0 = tthread(T); r0 < n; r0 += NT * RU) {
         double aq[RU][R], aw[RU][R];
         int64_t rr[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            const int64_t row = r0 + (int64_t)u * BT;
+            const int64_t row = r0 + (int64_t)u * NT;
             rr[u] = row < n ? row : n - 1; // clamped for loads, skipped for stores
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -580,7 +707,7 @@ __device__ void b_update2(int64_t n, const double *V, int64_t ldv, int nk, const
         }
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            const int64_t row = r0 + (int64_t)u * BT;
+            const int64_t row = r0 + (int64_t)u * NT;
             if (row >= n) continue;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -604,6 +731,7 @@ __device__ void b_update2(int64_t n, const double *V, int64_t ldv, int nk, const
         nrm[t] = sum;
     }
     __syncthreads();
+    team_sum(T, nrm, R); // also the barrier after the writes of q and w'
 }
 
 struct BLds {
@@ -612,14 +740,15 @@ struct BLds {
     // column, ||w'|| of the last step, pass-1 norms (u.u, u.w, w.w), the scale
     // of the current tentative vector, 1/alpha and e of the current step
     double *ht, *zs, *nu, *nrm3, *us, *ia, *ev;
-    int *done, *kk, *iters, *restarts, *status, *conv, *flag;
+    int *done, *kk, *iters, *restarts, *status, *conv, *flag, *abort;
+    unsigned *epoch;
 };
 
 __host__ __device__ inline size_t blds_bytes(int m, int R)
 {
     const size_t d = (size_t)BNW * RED_STRIDE + 5 * (size_t)(m + 2) * R + (size_t)(m + 1) * m * R +
                      3 * (size_t)m * R + (size_t)(m + 2) * R + 12 * (size_t)R;
-    return d * sizeof(double) + (6 * (size_t)R + 2) * sizeof(int) + 64;
+    return d * sizeof(double) + (6 * (size_t)R + 4) * sizeof(int) + 64;
 }
 
 __device__ inline BLds blds_carve(double *base, int m, int R)
@@ -655,6 +784,8 @@ __device__ inline BLds blds_carve(double *base, int m, int R)
     L.status = q; q += R;
     L.conv = q; q += R;
     L.flag = q;
+    L.abort = q + 1;
+    L.epoch = (unsigned *)(q + 2);
     return L;
 }
 
@@ -662,7 +793,7 @@ __device__ inline BLds blds_carve(double *base, int m, int R)
 // right-hand side r to col (jc+2 entries), form rotation jc, store column jc
 // of R and advance the residual recurrence g.  False on a zero or
 // non-finite rotation radius (status set).
-__device__ bool bcommit(BLds &L, int R, int m, int r, double *col, int jc)
+__device__ __forceinline__ bool bcommit(BLds &L, int R, int m, int r, double *col, int jc)
 {
     for (int k = 0; k < jc; ++k) {
         const double a = L.cs[k * R + r] * col[k] + L.sn[k * R + r] * col[k + 1];
@@ -690,7 +821,7 @@ __device__ bool bcommit(BLds &L, int R, int m, int r, double *col, int jc)
 }
 
 template <typename VT, typename AT, int R, int K>
-__device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
+__device__ __forceinline__ void b_solve_item(const BConst &c, const BItem &it, const BTeam &T, BLds &L)
 {
     const BSys S = c.sys[it.sys];
     const BParams prm = *c.prm;
@@ -703,13 +834,19 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
     double *w = c.W + it.base * 2, *w2 = w + nR;
     AT *P = (AT *)c.P + it.base * 5;
     const int t = threadIdx.x;
+    const int64_t tt = tthread(T), NT = tthreads(T);
+    int *ab = T.ab;
     const double rtol = prm.rtol;
     const int maxit = prm.maxit;
+    if (t == 0) {
+        *ab = 0;
+        *T.ep = 0u;
+    }
 
     // ||b|| per right-hand side: gather b into w (interleaved), then a norm pass
-    for (int64_t i = t; i < nR; i += BT) w[i] = Bb[(i / R) * nrhs + (i % R)];
-    __syncthreads();
-    b_multidot<R>(n, nullptr, 0, 0, w, 1, L.bnorm, L.red); // writes L.bnorm[0..R) = ||b||^2
+    for (int64_t i = tt; i < nR; i += NT) w[i] = Bb[(i / R) * nrhs + (i % R)];
+    team_sync(T);
+    b_multidot<R>(T, n, nullptr, 0, 0, w, 1, L.bnorm, L.red); // writes L.bnorm[0..R) = ||b||^2
     if (t < R) {
         L.bnorm[t] = sqrt(L.bnorm[t]);
         L.iters[t] = 0;
@@ -723,18 +860,18 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
     }
     __syncthreads();
     // b = 0 -> x = 0
-    for (int64_t i = t; i < nR; i += BT)
+    for (int64_t i = tt; i < nR; i += NT)
         if (L.conv[i % R]) Xb[(i / R) * nrhs + (i % R)] = 0.0;
     // working copy of x in w2 (interleaved)
-    for (int64_t i = t; i < nR; i += BT) w2[i] = Xb[(i / R) * nrhs + (i % R)];
-    __syncthreads();
+    for (int64_t i = tt; i < nR; i += NT) w2[i] = Xb[(i / R) * nrhs + (i % R)];
+    team_sync(T);
 
     int cycle = 0;
-    for (;;) {
+    while (!*ab) {
         // true residual r = b - A x into V_0, ||r||^2
-        b_spmv<R>(S, w2, V, Bb, nrhs);
-        __syncthreads();
-        b_multidot<R>(n, nullptr, 0, 0, V, 1, L.beta, L.red);
+        b_spmv<R>(T, S, w2, V, Bb, nrhs);
+        team_sync(T);
+        b_multidot<R>(T, n, nullptr, 0, 0, V, 1, L.beta, L.red);
         if (t == 0) L.flag[0] = 0;
         __syncthreads();
         if (t < R) {
@@ -759,25 +896,24 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
             }
         }
         __syncthreads();
-        if (!L.flag[0]) break;
+        if (!L.flag[0] || *ab) break;
         ++cycle;
-        for (int64_t i = t; i < nR; i += BT) V[i] = L.inv[i % R] == 0.0 ? 0.0 : V[i] * L.inv[i % R];
-        __syncthreads();
+        for (int64_t i = tt; i < nR; i += NT) V[i] = L.inv[i % R] == 0.0 ? 0.0 : V[i] * L.inv[i % R];
         if (t < R) L.zs[t] = 1.0; // V_0 is normalised explicitly
-        __syncthreads();
+        team_sync(T);
         // Arnoldi steps with delayed reorthogonalisation (two passes over the
         // basis per step; the tentative vector V_j stays unnormalised, its
         // scale in zs, and is reorthogonalised one step late)
         for (int j = 0; j < m; ++j) {
             double *vj = V + (int64_t)j * nR;
             double *zj = Z + (int64_t)j * nR;
-            b_precond<VT, AT, R, K>(c, S, vj, zj, P); // on the raw vector: the apply is linear
+            b_precond<VT, AT, R, K>(T, c, S, vj, zj, P); // on the raw vector: the apply is linear
             if (t < R) L.us[t] = L.done[t] ? 0.0 : L.zs[j * R + t];
             __syncthreads();
-            b_spmv<R>(S, zj, w, nullptr, 0, L.us); // w = A z_j, z_j = us * stored column
-            __syncthreads();
+            b_spmv<R>(T, S, zj, w, nullptr, 0, L.us); // w = A z_j, z_j = us * stored column
+            team_sync(T);
             // pass 1: a = Q^T u, c = Q^T w, u.u, u.w, w.w (Q = V_0..V_{j-1})
-            b_multidot2<R>(n, V, nR, j, vj, L.us, w, L.hA, L.hB, L.nrm3, L.red);
+            b_multidot2<R>(T, n, V, nR, j, vj, L.us, w, L.hA, L.hB, L.nrm3, L.red);
             if (t < R) {
                 const int r = t;
                 L.ia[r] = 0.0;
@@ -828,7 +964,7 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
             __syncthreads();
             // pass 2: q_j over V_j, w' = w - Q c - e q_j into V_{j+1}, ||w'||^2
             double *vn = V + (int64_t)(j + 1) * nR;
-            b_update2<R>(n, V, nR, j, L.hA, L.hB, vj, L.us, L.ia, L.ev, w, vn, L.nrm, L.red);
+            b_update2<R>(T, n, V, nR, j, L.hA, L.hB, vj, L.us, L.ia, L.ev, w, vn, L.nrm, L.red);
             if (t == 0) L.flag[0] = 0;
             __syncthreads();
             if (t < R && !L.done[t]) { // tentative rotation of column j, residual estimate, stop test
@@ -864,7 +1000,7 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
                 }
             }
             __syncthreads();
-            if (!L.flag[0]) break;
+            if (!L.flag[0] || *ab) break;
         }
         // y = R^{-1} g, x += Z y  (per right-hand side)
         if (t < R) {
@@ -876,23 +1012,24 @@ __device__ void b_solve_item(const BConst &c, const BItem &it, BLds &L)
             }
         }
         __syncthreads();
-        for (int64_t i = t; i < nR; i += BT) {
+        for (int64_t i = tt; i < nR; i += NT) {
             const int r = (int)(i % R);
             double acc = w2[i];
             for (int k = 0; k < L.kk[r]; ++k) acc += L.y[k * R + r] * L.zs[k * R + r] * Z[(int64_t)k * nR + i];
             w2[i] = acc;
         }
-        __syncthreads();
+        team_sync(T);
     }
-    // write back x and the per-right-hand-side records
-    for (int64_t i = t; i < nR; i += BT) Xb[(i / R) * nrhs + (i % R)] = w2[i];
-    if (t < R) {
+    // write back x and the per-right-hand-side records (member 0)
+    for (int64_t i = tt; i < nR; i += NT) Xb[(i / R) * nrhs + (i % R)] = w2[i];
+    if (t < R && T.me == 0) {
         gs2_solve_info f;
         f.iterations = L.iters[t];
         f.restarts = L.restarts[t];
         f.relres = L.bnorm[t] > 0.0 ? L.beta[t] / L.bnorm[t] : 0.0;
-        f.converged = L.conv[t];
-        f.status = L.conv[t] ? GS2_OK : (L.status[t] != GS2_OK ? L.status[t] : GS2_NOT_CONVERGED);
+        f.converged = *ab ? 0 : L.conv[t];
+        f.status = *ab ? GS2_ERR_HIP
+                       : L.conv[t] ? GS2_OK : (L.status[t] != GS2_OK ? L.status[t] : GS2_NOT_CONVERGED);
         f.seconds = 0.0;
         c.info[(int64_t)it.sys * nrhs + it.r0 + t] = f;
     }
@@ -903,21 +1040,30 @@ template <typename VT, typename AT, int R, int K>
 __global__ __launch_bounds__(BT) void k_batched(BConst c)
 {
     extern __shared__ double lds[];
-    __shared__ int s_item;
+    __shared__ int s_slot;
     BLds L = blds_carve(lds, c.m, R);
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(c.queue, 1u);
+        if (threadIdx.x == 0) s_slot = (int)atomicAdd(c.queue, 1u);
         __syncthreads();
-        const int item = s_item;
+        const int slot = __builtin_amdgcn_readfirstlane(s_slot); // uniform: the item's fields load into SGPRs
         __syncthreads();
-        if (item >= c.nitems) break;
-        b_solve_item<VT, AT, R, K>(c, c.items[item], L);
+        if (slot >= c.nslots) break;
+        const BSlot sl = c.slots[slot];
+        const BItem it = c.items[sl.item];
+        const BTeam T{it.G, sl.member, c.tbar + sl.item, c.xch + it.xoff, c.abort, c.spin_ticks, L.epoch, L.abort};
+        b_solve_item<VT, AT, R, K>(c, it, T, L);
     }
 }
 
-__global__ void k_reset_queue(unsigned *q)
+// a new solve: empty queue, team arrival counters and abort flag at zero
+__global__ void k_reset_queue(unsigned *q, unsigned *tbar, int nitems, int *abort)
 {
-    if (threadIdx.x == 0) q[0] = 0u;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        q[0] = 0u;
+        abort[0] = 0;
+    }
+    for (int k = i; k < nitems; k += gridDim.x * blockDim.x) tbar[k] = 0u;
 }
 
 // ---------------------------------------------------------------- host side
@@ -953,6 +1099,12 @@ struct Batch {
     BSys *d_sys = nullptr;
     BItem *d_items = nullptr;
     int nitems = 0;
+    int team_rows = 0; // rows x right-hand sides per team member (0 = default, < 0 = no teams)
+    BSlot *d_slots = nullptr;
+    int nslots = 0;
+    unsigned *tbar = nullptr;
+    double *xch = nullptr;
+    int *abort = nullptr;
     double *V = nullptr, *Z = nullptr, *W = nullptr;
     void *P = nullptr;
     unsigned *queue = nullptr;
@@ -971,27 +1123,61 @@ struct Batch {
         if (cap) (void)hipStreamDestroy(cap);
         for (Handle *h : hs) delete h;
         for (void *p : {(void *)rp, (void *)ci, (void *)va, (void *)d_sys, (void *)d_items, (void *)V, (void *)Z,
-                        (void *)W, P, (void *)queue, (void *)d_info, (void *)d_prm})
+                        (void *)W, P, (void *)queue, (void *)d_info, (void *)d_prm, (void *)d_slots, (void *)tbar,
+                        (void *)xch, (void *)abort})
             if (p) (void)hipFree(p);
         if (h_prm) (void)hipHostFree(h_prm);
     }
 };
 
+// Rows x right-hand sides per team member: an item of n rows and R
+// right-hand sides is solved by G = n R / team_rows workgroups (rounded,
+// 1..8).  Smaller shares pay more in team barriers than they gain (measured
+// on the 512-system convection-diffusion batch: 8192, 16384, 32768 and 65536
+// gave 3.50, 2.77, 2.72 and 3.03 s with R = 4, one workgroup per item 6.13
+// s; at most 16 members instead of 8 did not help).
+constexpr int64_t TEAM_ROWS_DEFAULT = 32768;
+constexpr int TEAM_MAX = 8;
+
+static int team_size(const Batch &b, int64_t n, int R)
+{
+    if (b.team_rows < 0) return 1;
+    const int64_t tr = b.team_rows > 0 ? b.team_rows : TEAM_ROWS_DEFAULT;
+    const int64_t g = (n * R + tr / 2) / tr;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(TEAM_MAX, g));
+}
+
 static int build_items(Batch &b, int R)
 {
-    if (b.d_items) (void)hipFree(b.d_items);
+    for (void *p : {(void *)b.d_items, (void *)b.d_slots, (void *)b.tbar, (void *)b.xch})
+        if (p) (void)hipFree(p);
     b.d_items = nullptr;
+    b.d_slots = nullptr;
+    b.tbar = nullptr;
+    b.xch = nullptr;
     std::vector<int> order(b.nsys);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b.sizes[a] > b.sizes[c]; });
     std::vector<int64_t> row0(b.nsys + 1, 0);
     for (int i = 0; i < b.nsys; ++i) row0[i + 1] = row0[i] + b.sizes[i];
     std::vector<BItem> items;
+    std::vector<BSlot> slots;
+    int64_t xoff = 0;
     for (int i : order)
-        for (int r0 = 0; r0 < b.nrhs; r0 += R) items.push_back(BItem{i, r0, row0[i] * b.nrhs + (int64_t)r0 * b.sizes[i]});
+        for (int r0 = 0; r0 < b.nrhs; r0 += R) {
+            const int G = team_size(b, b.sizes[i], R);
+            for (int q = 0; q < G; ++q) slots.push_back(BSlot{(int)items.size(), q});
+            items.push_back(BItem{i, r0, row0[i] * b.nrhs + (int64_t)r0 * b.sizes[i], G, 0, xoff});
+            if (G > 1) xoff += 2 * (int64_t)G * XS;
+        }
     b.nitems = (int)items.size();
+    b.nslots = (int)slots.size();
     GS2_TRY_HIP(hipMalloc(&b.d_items, sizeof(BItem) * items.size()));
     GS2_TRY_HIP(hipMemcpy(b.d_items, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice));
+    GS2_TRY_HIP(hipMalloc(&b.d_slots, sizeof(BSlot) * slots.size()));
+    GS2_TRY_HIP(hipMemcpy(b.d_slots, slots.data(), sizeof(BSlot) * slots.size(), hipMemcpyHostToDevice));
+    GS2_TRY_HIP(hipMalloc(&b.tbar, sizeof(unsigned) * items.size()));
+    GS2_TRY_HIP(hipMalloc(&b.xch, sizeof(double) * (size_t)std::max<int64_t>(xoff, 1)));
     return GS2_OK;
 }
 
@@ -1008,16 +1194,24 @@ static int configure(Batch &b, int R)
     int dev = 0, cus = 0;
     GS2_TRY_HIP(hipGetDevice(&dev));
     GS2_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    b.grid = std::max(1, std::min(b.nitems, std::max(1, per_cu) * cus));
+    // every workgroup can be resident at once, and a team (at most TEAM_MAX
+    // members) waits only for slots that running workgroups pop
+    b.grid = std::max(1, std::min(b.nslots, std::max(1, per_cu) * cus));
+    if (b.grid < std::min(b.nslots, TEAM_MAX)) return GS2_ERR_HIP;
     b.cst.items = b.d_items;
     b.cst.nitems = b.nitems;
+    b.cst.slots = b.d_slots;
+    b.cst.nslots = b.nslots;
+    b.cst.tbar = b.tbar;
+    b.cst.xch = b.xch;
     // (re)capture: queue reset + one persistent launch
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
     b.graph = nullptr;
     GS2_TRY_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
-    k_reset_queue<<<1, 64, 0, b.cap>>>(b.queue);
+    k_reset_queue<<<(unsigned)std::min(1024, (b.nitems + 255) / 256), 256, 0, b.cap>>>(b.queue, b.tbar, b.nitems,
+                                                                                   b.abort);
     kern<<<b.grid, BT, b.lds, b.cap>>>(b.cst);
     GS2_TRY_HIP(hipStreamEndCapture(b.cap, &b.graph));
     GS2_TRY_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
@@ -1105,6 +1299,7 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
     GS2_TRY_HIP(hipMalloc(&b.W, sizeof(double) * tot * 2));
     GS2_TRY_HIP(hipMalloc(&b.P, prec_bytes(o.precision) * tot * 5));
     GS2_TRY_HIP(hipMalloc(&b.queue, sizeof(unsigned) * 64));
+    GS2_TRY_HIP(hipMalloc(&b.abort, sizeof(int) * 64));
     GS2_TRY_HIP(hipMalloc(&b.d_info, sizeof(gs2_solve_info) * (size_t)nsys * nrhs));
     GS2_TRY_HIP(hipMalloc(&b.d_prm, sizeof(BParams)));
     GS2_TRY_HIP(hipHostMalloc((void **)&b.h_prm, sizeof(BParams), hipHostMallocDefault));
@@ -1124,6 +1319,14 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
     b.cst.W = b.W;
     b.cst.P = b.P;
     b.cst.queue = b.queue;
+    b.cst.abort = b.abort;
+    {
+        int dev = 0, khz = 0;
+        GS2_TRY_HIP(hipGetDevice(&dev));
+        GS2_TRY_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        b.cst.spin_ticks = (long long)std::max(khz, 1000) * 1000LL * 30; // 30 s per team barrier
+    }
+    b.team_rows = o.team_rows;
     b.cst.info = b.d_info;
     b.cst.prm = b.d_prm;
 
@@ -1150,8 +1353,10 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
         // One restart cycle per item, every right-hand side doing the same
         // work, measures throughput only.  In a real solve the right-hand
         // sides of an item converge at different steps and the item runs until
-        // its slowest one has (and the largest items form the critical path), so
-        // the smallest R within 25% of the best tuning time is taken.
+        // its slowest one has.  With one workgroup per item the largest items
+        // form the critical path, so the smallest R within 25% of the best
+        // tuning time is taken; with teams the largest items are split and the
+        // fastest R is taken.
         std::vector<float> ms_of(cands.size(), 0.f);
         float best = 1e30f;
         for (size_t c = 0; c < cands.size(); ++c) {
@@ -1164,8 +1369,9 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
             GS2_TRY_HIP(hipEventElapsedTime(&ms_of[c], e0, e1));
             best = std::min(best, ms_of[c]);
         }
+        const float slack = b.team_rows < 0 ? 1.25f : 1.0f;
         for (size_t c = 0; c < cands.size(); ++c) // cands is in decreasing R
-            if (ms_of[c] <= 1.25f * best) bestR = cands[c];
+            if (ms_of[c] <= slack * best) bestR = cands[c];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(Bt);

@@ -67,6 +67,42 @@ def test_batched_fp32_matches_oracle(rhs_per_item):
     check_against_oracle(mats, rhs, 4, infos, xs, oracle.FP32, 2, 2, 20)
 
 
+@pytest.mark.parametrize("rhs_per_item", [1, 2, 4])
+def test_batched_teams_match_oracle(rhs_per_item):
+    """Items split over teams of workgroups (team_rows small, so that the team
+    size runs from 1 to 8 across the batch) meet the same bar as
+    single-workgroup items, and replays are bitwise equal: the members' partial
+    sums are added in member order, whatever the timing."""
+    sides = [8, 13, 20, 31, 40, 9, 23, 64]
+    mats, rhs = make_batch(sides, 4, 11)
+    st, infos, xs, bh, B, X = run_batch(mats, rhs, 4, sweeps=2, inner=2, precision=g.FP32, restart=20,
+                                        rhs_per_item=rhs_per_item, team_rows=256)
+    assert st == 0
+    check_against_oracle(mats, rhs, 4, infos, xs, oracle.FP32, 2, 2, 20)
+    first = X.clone()
+    for rep in range(2):
+        X.zero_()
+        st2, infos2 = g.gmres_solve_batched(bh, 4, B, X, 1e-8, 5000)
+        torch.cuda.synchronize()
+        assert st2 == 0 and torch.equal(X, first)
+        assert [q["iterations"] for q in infos2] == [q["iterations"] for q in infos]
+
+
+def test_batched_teams_against_single_workgroups():
+    """The same batch solved with teams and with one workgroup per item: the
+    iteration counts agree within one and the solutions to the solver's
+    accuracy (only the summation order of the reductions differs)."""
+    mats, rhs = make_batch([48, 35, 57, 12], 2, 12)
+    ref = run_batch(mats, rhs, 2, sweeps=1, inner=1, precision=g.FP64, restart=15, team_rows=-1)
+    tm = run_batch(mats, rhs, 2, sweeps=1, inner=1, precision=g.FP64, restart=15, team_rows=300)
+    assert ref[0] == 0 and tm[0] == 0
+    for i in range(len(mats)):
+        for r in range(2):
+            assert abs(ref[1][i * 2 + r]["iterations"] - tm[1][i * 2 + r]["iterations"]) <= 1
+            a, b = ref[2][i][:, r], tm[2][i][:, r]
+            assert np.linalg.norm(a - b) / np.linalg.norm(a) <= 1e-6
+
+
 @pytest.mark.parametrize("precision", [g.FP64, g.FP16_SCALED])
 def test_batched_other_precisions(precision):
     mats, rhs = make_batch([17, 33, 12], 2, 8)
@@ -76,17 +112,19 @@ def test_batched_other_precisions(precision):
                          1, 1, 15)
 
 
-def test_batched_initial_guess_zero_rhs_and_replays():
+@pytest.mark.parametrize("team_rows", [0, 128])
+def test_batched_initial_guess_zero_rhs_and_replays(team_rows):
     """Nonzero initial guesses are honoured, an all-zero right-hand side gives
     x = 0 with no iteration, and replaying the captured graph several times
     (with other GPU work and synchronisations in between) gives bitwise-equal
-    results every time."""
+    results every time (single workgroups and teams)."""
     mats, rhs = make_batch([15, 26, 11], 4, 9)
     rhs[1][:, 2] = 0.0
     rng = np.random.default_rng(3)
     x0s = [rng.standard_normal((A.n, 4)) for A in mats]
     X0 = np.concatenate([x.ravel() for x in x0s])
-    st, infos, xs, bh, B, X = run_batch(mats, rhs, 4, X0=X0, sweeps=2, inner=2, precision=g.FP32, restart=20)
+    st, infos, xs, bh, B, X = run_batch(mats, rhs, 4, X0=X0, sweeps=2, inner=2, precision=g.FP32, restart=20,
+                                        team_rows=team_rows)
     assert st == 0
     f = infos[1 * 4 + 2]
     assert f["converged"] and f["iterations"] == 0 and not xs[1][:, 2].any()
@@ -109,15 +147,17 @@ def test_batched_initial_guess_zero_rhs_and_replays():
         assert [q["iterations"] for q in infos2] == [q["iterations"] for q in infos]
 
 
-def test_batched_not_converged_and_general_rows():
+@pytest.mark.parametrize("team_rows", [0, 64])
+def test_batched_not_converged_and_general_rows(team_rows):
     """maxit reached -> GS2_NOT_CONVERGED per right-hand side; a random
-    nonsymmetric matrix with long rows uses the 4-lanes-per-row schedule."""
+    nonsymmetric matrix with long rows uses the 4-lanes-per-row schedule
+    (single workgroups and teams)."""
     A = random_sparse(300, seed=12, avg_offdiag=30, long_rows=3, long_len=120)
     mats = [A, convdiff2d(10, 5.0, 1.0)]
     rng = np.random.default_rng(5)
     rhs = [rng.standard_normal((M.n, 2)) for M in mats]
     dm = [g.DeviceCSR.from_host(M) for M in mats]
-    bh = g.gs2_setup_batched(dm, nrhs=2, sweeps=1, inner=1, precision=g.FP64, restart=10)
+    bh = g.gs2_setup_batched(dm, nrhs=2, sweeps=1, inner=1, precision=g.FP64, restart=10, team_rows=team_rows)
     B = torch.as_tensor(np.concatenate([r.ravel() for r in rhs]), device=DEV)
     X = torch.zeros_like(B)
     st, infos = g.gmres_solve_batched(bh, 2, B, X, 1e-14, 3)
