@@ -219,10 +219,67 @@ void free_sell(Sell &S)
 {
     if (S.slice_ptr) (void)hipFree(S.slice_ptr);
     if (S.col) (void)hipFree(S.col);
+    if (S.off) (void)hipFree(S.off);
     if (S.val) (void)hipFree(S.val);
     S.slice_ptr = nullptr;
     S.col = nullptr;
+    S.off = nullptr;
     S.val = nullptr;
+}
+
+// One thread per (slice, lane): off = col - row, or a flag when it does not
+// fit in 16 bits.
+__global__ void k_col_offsets(int64_t nslices, int K, const int64_t *__restrict__ sp, const int32_t *__restrict__ col,
+                              int16_t *__restrict__ off, int *__restrict__ too_far)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t s = gid / WAVE;
+    if (s >= nslices) return;
+    const int l = (int)(gid % WAVE);
+    const int64_t row = s * (WAVE / K) + l / K;
+    const int64_t beg = sp[s];
+    const int steps = (int)((sp[s + 1] - beg) / WAVE);
+    int far = 0;
+    for (int t = 0; t < steps; ++t) {
+        const int64_t pos = beg + (int64_t)t * WAVE + l;
+        const int64_t d = (int64_t)col[pos] - row;
+        if (d < -32767 || d > 32767) far = 1;
+        else off[pos] = (int16_t)d;
+    }
+    if (far) atomicOr(too_far, 1);
+}
+
+int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *col, int64_t padded, int16_t **off,
+                      hipStream_t s)
+{
+    *off = nullptr;
+    if (nslices <= 0) return GS2_OK;
+    int16_t *o = nullptr;
+    int *flag = nullptr;
+    int h_flag = 0;
+    GS2_TRY_HIP(hipMalloc(&o, sizeof(int16_t) * std::max<int64_t>(padded, WAVE)));
+    if (hipMalloc(&flag, sizeof(int)) != hipSuccess) {
+        (void)hipFree(o);
+        return GS2_ERR_NOMEM;
+    }
+    const int tb = 256;
+    const int64_t threads = nslices * WAVE;
+    int st = GS2_OK;
+    if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) st = GS2_ERR_HIP;
+    if (st == GS2_OK) {
+        k_col_offsets<<<(unsigned)((threads + tb - 1) / tb), tb, 0, s>>>(nslices, K, sp, col, o, flag);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = GS2_ERR_HIP;
+    }
+    (void)hipFree(flag);
+    if (st != GS2_OK || h_flag) {
+        (void)hipFree(o);
+        return st;
+    }
+    *off = o;
+    return GS2_OK;
 }
 
 int choose_lanes(double avg_len, int max_len)
@@ -275,6 +332,7 @@ static int build_one(Sell &S, int64_t n, int K, int precision, const gs2_csr &A,
             k_fill<_Float16><<<grid, tb, 0, s>>>(n, S.nslices, K, A.rowptr, A.colind, A.val, R, sl, sr, S.slice_ptr,
                                                  S.col, (_Float16 *)S.val, err);
         GS2_TRY_HIP(hipGetLastError());
+        GS2_TRY(build_col_offsets(S.nslices, K, S.slice_ptr, S.col, S.padded, &S.off, s));
     }
     return GS2_OK;
 }
@@ -636,6 +694,7 @@ int gs2_handle_query(const gs2_handle *H, int64_t *n, int64_t *nnz_l, int64_t *n
     if (nnz_u) *nnz_u = h.U.nnz;
     if (bytes_stored)
         *bytes_stored = (h.L.padded + h.U.padded) * (int64_t)(4 + h.L.val_bytes) +
+                        h.L.padded * (h.L.off ? 2 : 0) + h.U.padded * (h.U.off ? 2 : 0) +
                         8 * (h.L.nslices + h.U.nslices + 2) + 16 * h.n;
     if (lanes_per_row) *lanes_per_row = h.L.K;
     if (levels_l) *levels_l = h.nlev_l;

@@ -23,10 +23,11 @@ enum : int { DST_G = 0, DST_XADD = 1, DST_XSET = 2, DST_ZADD = 3, DST_ZSET = 4 }
 struct SellView {
     const int64_t *sp;
     const int32_t *col;
+    const int16_t *off; // col - row per entry, when the triangle has them
     const void *val;
 };
 
-static SellView view(const Sell &S) { return SellView{S.slice_ptr, S.col, S.val}; }
+static SellView view(const Sell &S) { return SellView{S.slice_ptr, S.col, S.off, S.val}; }
 
 template <typename AT>
 __device__ __forceinline__ void finish(int dst, int64_t row, AT g, AT w, AT *gout, AT *xh, AT *xout, double *z,
@@ -54,8 +55,10 @@ constexpr int su_of()
     return sizeof(AT) == 8 ? 1 : 2;
 }
 
-// acc[u] += sum over the stored entries of slice s0 + u of val * src(col)
-template <typename VT, typename AT, int SUN, typename Src>
+// acc[u] += sum over the stored entries of slice s0 + u of val * src(col);
+// the column is row + off (2 index bytes per entry) when the triangle has
+// 16-bit offsets, else read in full.
+template <typename VT, typename AT, int SUN, int K, typename Src>
 __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t nslices, int lane, Src src,
                                            AT (&acc)[SUN])
 {
@@ -71,6 +74,23 @@ __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t
         tmax = steps[u] > tmax ? steps[u] : tmax;
     }
     const VT *__restrict__ val = (const VT *)T.val;
+    if (T.off) {
+        const int16_t *__restrict__ off = T.off;
+        int rw[SUN];
+#pragma unroll
+        for (int u = 0; u < SUN; ++u) rw[u] = (int)((s0 + u) * (WAVE / K) + lane / K);
+#pragma unroll 4
+        for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+            for (int u = 0; u < SUN; ++u) {
+                if (t < steps[u]) {
+                    const int64_t p = beg[u] + (int64_t)t * WAVE + lane;
+                    acc[u] += (AT)val[p] * src(rw[u] + (int)off[p]);
+                }
+            }
+        }
+        return;
+    }
     const int32_t *__restrict__ col = T.col;
 #pragma unroll 4
     for (int t = 0; t < tmax; ++t) {
@@ -103,8 +123,8 @@ __global__ __launch_bounds__(256) void k_inner(const int *__restrict__ stop, int
     AT acc[SUN];
 #pragma unroll
     for (int u = 0; u < SUN; ++u) acc[u] = AT(0);
-    if (gv) slice_dots<VT, AT, SUN>(T, s0, nslices, lane, [&](int c) { return (AT)(v[c] * sl[c]); }, acc);
-    else slice_dots<VT, AT, SUN>(T, s0, nslices, lane, [&](int c) { return gin[c]; }, acc);
+    if (gv) slice_dots<VT, AT, SUN, K>(T, s0, nslices, lane, [&](int c) { return (AT)(v[c] * sl[c]); }, acc);
+    else slice_dots<VT, AT, SUN, K>(T, s0, nslices, lane, [&](int c) { return gin[c]; }, acc);
 #pragma unroll
     for (int u = 0; u < SUN; ++u) {
         const AT a = K > 1 ? group_sum<K>(acc[u]) : acc[u];
@@ -145,9 +165,9 @@ __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int
 #pragma unroll
     for (int u = 0; u < SUN; ++u) acc[u] = AT(0);
     auto gx = [&](int c) { return xh[c]; };
-    slice_dots<VT, AT, SUN>(P, s0, nslices, lane, gx, acc);
-    if (two) slice_dots<VT, AT, SUN>(Q, s0, nslices, lane, gx, acc);
-    if (ye) slice_dots<VT, AT, SUN>(Ev, s0, nslices, lane, [&](int c) { return ye[c]; }, acc);
+    slice_dots<VT, AT, SUN, K>(P, s0, nslices, lane, gx, acc);
+    if (two) slice_dots<VT, AT, SUN, K>(Q, s0, nslices, lane, gx, acc);
+    if (ye) slice_dots<VT, AT, SUN, K>(Ev, s0, nslices, lane, [&](int c) { return ye[c]; }, acc);
 #pragma unroll
     for (int u = 0; u < SUN; ++u) {
         const AT a = K > 1 ? group_sum<K>(acc[u]) : acc[u];
@@ -287,7 +307,10 @@ struct Launch {
     }
     // algorithmic bytes of one pass: each stored entry (value + column) and
     // each vector element read or written once; padding is not counted
-    static double tri_bytes(const Sell &T) { return (double)T.nnz * (sizeof(VT) + 4) + 8.0 * (T.nslices + 1); }
+    static double tri_bytes(const Sell &T)
+    {
+        return (double)T.nnz * (sizeof(VT) + T.idx_bytes()) + 8.0 * (T.nslices + 1);
+    }
     static double dst_bytes(int dst)
     {
         const double bx = sizeof(AT);
