@@ -34,14 +34,17 @@ struct GState {
     double bnorm, beta, rtol, inv;
     double hA[MAXM + 2], hB[MAXM + 2], nrm[2];
     double g[MAXM + 2], cs[MAXM], sn[MAXM], y[MAXM];
-    double H[(MAXM + 1) * MAXM]; // H[k * MAXM + col], upper triangle R after rotations
     // delayed CGS2: scalars of the current step and the tentative column
     double bb, dd, wn2, nu, inv_alpha, e;
     double ht[MAXM + 2];
     // scale of the stored preconditioned vector of each step: step j works on
     // the unnormalised tentative vector, z_j = zs[j] * (stored Z column j)
     double zs[MAXM + 2];
+    // last, so that everything before it can be staged in LDS (8.5 KB)
+    double H[(MAXM + 1) * MAXM]; // H[k * MAXM + col], upper triangle R after rotations
 };
+constexpr int GSTATE_SMALL_WORDS = (int)(offsetof(GState, H) / 8);
+static_assert(offsetof(GState, H) % 8 == 0, "the staged part of the state is whole 8-byte words");
 
 struct GHeader {
     int j, done, kk, status;
@@ -477,50 +480,44 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, int64_t n, const 
         part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
 }
 
-// The small per-step scalar kernels are latency-bound: every value they need
-// is first copied from the device state into LDS by a whole wavefront, then
-// one lane runs the (inherently serial) rotation recurrence on LDS.
-struct RotLds {
-    double cs[MAXM], sn[MAXM], col[MAXM + 2];
-};
-
-__device__ void stage_rotations(const GState *st, RotLds &R, int cnt)
+// (one lane) Apply rotations 0..jc-1 to col (jc+1 entries used).  The entry
+// carried from one rotation to the next stays in a register, so the chain
+// is two multiply-adds per rotation; the loads run ahead of it.
+__device__ __forceinline__ void apply_rotations(const double *__restrict__ cs, const double *__restrict__ sn,
+                                                double *__restrict__ col, int jc)
 {
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-        R.cs[k] = st->cs[k];
-        R.sn[k] = st->sn[k];
+    double carry = col[0];
+    for (int k = 0; k < jc; ++k) {
+        const double x = col[k + 1];
+        col[k] = cs[k] * carry + sn[k] * x;
+        carry = -sn[k] * carry + cs[k] * x;
     }
+    col[jc] = carry;
 }
 
-// (one lane) Apply the committed rotations 0..jc-1 to col (jc+2 entries),
-// form rotation jc, store column jc of R and advance the residual
-// recurrence g.
-__device__ bool commit_column(GState *st, RotLds &R, double *col, int jc)
+// (one lane) Apply the committed rotations 0..jc-1 of the state ls (in
+// LDS) to col (jc+2 entries), form rotation jc, store column jc of R into H
+// (global) and advance the residual recurrence g.
+__device__ bool commit_column(GState *ls, double *__restrict__ H, double *col, int jc)
 {
-    for (int k = 0; k < jc; ++k) {
-        const double a = R.cs[k] * col[k] + R.sn[k] * col[k + 1];
-        col[k + 1] = -R.sn[k] * col[k] + R.cs[k] * col[k + 1];
-        col[k] = a;
-    }
+    apply_rotations(ls->cs, ls->sn, col, jc);
     const double rho = hypot(col[jc], col[jc + 1]);
     if (!isfinite(rho)) {
-        st->status = GS2_ERR_NONFINITE;
+        ls->status = GS2_ERR_NONFINITE;
         return false;
     }
     if (rho == 0.0) {
-        st->status = GS2_BREAKDOWN;
+        ls->status = GS2_BREAKDOWN;
         return false;
     }
     const double c = col[jc] / rho, sn = col[jc + 1] / rho;
-    st->cs[jc] = c;
-    st->sn[jc] = sn;
-    R.cs[jc] = c;
-    R.sn[jc] = sn;
+    ls->cs[jc] = c;
+    ls->sn[jc] = sn;
     col[jc] = rho;
-    for (int k = 0; k <= jc; ++k) st->H[k * MAXM + jc] = col[k];
-    const double gj = st->g[jc];
-    st->g[jc + 1] = -sn * gj;
-    st->g[jc] = c * gj;
+    for (int k = 0; k <= jc; ++k) H[k * MAXM + jc] = col[k];
+    const double gj = ls->g[jc];
+    ls->g[jc + 1] = -sn * gj;
+    ls->g[jc] = c * gj;
     return true;
 }
 
@@ -618,85 +615,84 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
 // tentative rotation of column j and the residual estimate, and either stop
 // the cycle or advance j (the next tentative vector keeps its scale 1/||w'||
 // in zs[j+1]).  When u fell into span(Q) the cycle ends on the tentative
-// column j-1.
+// column j-1.  The kernel is latency-bound: the whole workgroup stages the
+// state (all but H) in LDS together with the partial sums, so one round
+// trip to memory precedes the serial work of one lane, and writes it back.
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
-    __shared__ double as[MAXM + 2], cs_[MAXM + 2], ht[MAXM + 2], red[KT / WAVE], sc[2];
-    __shared__ RotLds R;
-    if (st->done) return;
-    const int j = st->j, t = threadIdx.x;
-    stage_rotations(st, R, j);
-    for (int k = t; k < j; k += KT) {
-        as[k] = st->hA[k];
-        cs_[k] = st->hB[k];
-        ht[k] = st->ht[k];
+    __shared__ unsigned long long sw[GSTATE_SMALL_WORDS];
+    __shared__ double col[MAXM + 2], red[KT / WAVE], sc[2];
+    GState *ls = reinterpret_cast<GState *>(sw);
+    const int t = threadIdx.x;
+    const unsigned long long *gw = reinterpret_cast<const unsigned long long *>(st);
+    for (int k = t; k < GSTATE_SMALL_WORDS; k += KT) sw[k] = gw[k];
+    double tot = 0.0;
+    for (int b = t; b < nb; b += KT) tot += part[b];
+    tot = block_sum(tot, red); // ends with a barrier: the staged state is complete
+    if (ls->done) return;
+    const int j = ls->j;
+    double alpha, e, a2;
+    const bool ok = reorth_scalars(ls, j, ls->hA, ls->hB, sc, &alpha, &e, &a2);
+    if (t == 0) {
+        const double nu_prev = ls->nu;
+        if (!ok) {
+            if (!isfinite(a2)) {
+                ls->status = GS2_ERR_NONFINITE;
+                ls->kk = j - 1;
+            } else {
+                for (int k = 0; k < j; ++k) col[k] = ls->ht[k];
+                col[j] = nu_prev;
+                ls->kk = commit_column(ls, st->H, col, j - 1) ? j : j - 1;
+            }
+            ls->done = 1;
+        } else {
+            bool good = true;
+            if (j > 0) {
+                for (int k = 0; k < j; ++k) col[k] = ls->ht[k] + nu_prev * ls->hA[k];
+                col[j] = nu_prev * alpha;
+                good = commit_column(ls, st->H, col, j - 1);
+            }
+            if (!good) {
+                ls->kk = j - 1;
+                ls->done = 1;
+            }
+        }
+        if (ok && !ls->done) {
+            ls->inv_alpha = 1.0 / alpha;
+            ls->e = e;
+            // tentative column j: [c, e; ||w'||]
+            for (int k = 0; k < j; ++k) ls->ht[k] = ls->hB[k];
+            ls->ht[j] = e;
+            const double nu = sqrt(tot);
+            ls->nu = nu;
+            for (int k = 0; k <= j; ++k) col[k] = ls->ht[k];
+            col[j + 1] = nu;
+            apply_rotations(ls->cs, ls->sn, col, j);
+            const double rho = hypot(col[j], col[j + 1]);
+            if (!isfinite(rho) || !isfinite(nu)) {
+                ls->status = GS2_ERR_NONFINITE;
+                ls->done = 1;
+                ls->kk = j;
+            } else {
+                const double est = rho > 0.0 ? fabs(col[j + 1] / rho * ls->g[j]) : 0.0;
+                const bool breakdown = nu <= 1e-14 * sqrt(ls->wn2);
+                ls->kk = j + 1;
+                if (est <= ls->rtol * ls->bnorm || breakdown || j + 1 >= ls->maxsteps) {
+                    for (int k = 0; k <= j; ++k) col[k] = ls->ht[k];
+                    col[j + 1] = nu;
+                    if (!commit_column(ls, st->H, col, j)) ls->kk = j;
+                    ls->done = 1;
+                } else {
+                    ls->inv = 1.0 / nu;
+                    ls->zs[j + 1] = 1.0 / nu;
+                    ls->j = j + 1;
+                }
+            }
+        }
     }
     __syncthreads();
-    double alpha, e, a2;
-    const bool ok = reorth_scalars(st, j, as, cs_, sc, &alpha, &e, &a2);
-    double tot = 0.0;
-    if (ok)
-        for (int b = t; b < nb; b += KT) tot += part[b];
-    tot = block_sum(tot, red);
-    if (t != 0) return;
-    double *col = R.col;
-    const double nu_prev = st->nu;
-    if (!ok) {
-        if (!isfinite(a2)) {
-            st->status = GS2_ERR_NONFINITE;
-            st->kk = j - 1;
-        } else {
-            for (int k = 0; k < j; ++k) col[k] = ht[k];
-            col[j] = nu_prev;
-            st->kk = commit_column(st, R, col, j - 1) ? j : j - 1;
-        }
-        st->done = 1;
-        return;
-    }
-    if (j > 0) {
-        for (int k = 0; k < j; ++k) col[k] = ht[k] + nu_prev * as[k];
-        col[j] = nu_prev * alpha;
-        if (!commit_column(st, R, col, j - 1)) {
-            st->kk = j - 1;
-            st->done = 1;
-            return;
-        }
-    }
-    st->inv_alpha = 1.0 / alpha;
-    st->e = e;
-    // tentative column j: [c, e; ||w'||]
-    for (int k = 0; k < j; ++k) ht[k] = cs_[k];
-    ht[j] = e;
-    for (int k = 0; k <= j; ++k) st->ht[k] = ht[k];
-    const double nu = sqrt(tot);
-    st->nu = nu;
-    for (int k = 0; k <= j; ++k) col[k] = ht[k];
-    col[j + 1] = nu;
-    for (int k = 0; k < j; ++k) {
-        const double a = R.cs[k] * col[k] + R.sn[k] * col[k + 1];
-        col[k + 1] = -R.sn[k] * col[k] + R.cs[k] * col[k + 1];
-        col[k] = a;
-    }
-    const double rho = hypot(col[j], col[j + 1]);
-    if (!isfinite(rho) || !isfinite(nu)) {
-        st->status = GS2_ERR_NONFINITE;
-        st->done = 1;
-        st->kk = j;
-        return;
-    }
-    const double est = rho > 0.0 ? fabs(col[j + 1] / rho * st->g[j]) : 0.0;
-    const bool breakdown = nu <= 1e-14 * sqrt(st->wn2);
-    st->kk = j + 1;
-    if (est <= st->rtol * st->bnorm || breakdown || j + 1 >= st->maxsteps) {
-        for (int k = 0; k <= j; ++k) col[k] = ht[k];
-        col[j + 1] = nu;
-        if (!commit_column(st, R, col, j)) st->kk = j;
-        st->done = 1;
-    } else {
-        st->inv = 1.0 / nu;
-        st->zs[j + 1] = 1.0 / nu;
-        st->j = j + 1;
-    }
+    unsigned long long *gwo = reinterpret_cast<unsigned long long *>(st);
+    for (int k = t; k < GSTATE_SMALL_WORDS; k += KT) gwo[k] = sw[k];
 }
 
 __global__ void k_cycle_init(GState *__restrict__ st, int maxsteps, double rtol)
