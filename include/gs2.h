@@ -94,6 +94,10 @@ typedef struct gs2_options {
                           /* sides is solved by round(n R / team_rows)       */
                           /* workgroups (1..8).  0 = default (32768), < 0 =  */
                           /* one workgroup per item                          */
+    int team_wait_ms;     /* batched: longest wait of a team member at a     */
+                          /* team barrier before the item is abandoned with  */
+                          /* GS2_ERR_HIP (0 = default, 30000; < 0 = no wait  */
+                          /* at all, which forces that path, for tests)      */
 } gs2_options;
 
 typedef struct gs2_solve_info {
@@ -238,8 +242,9 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * sides) item start to finish: flexible GMRES in float64 with delayed
  * reorthogonalisation, the preconditioner in the chosen precision.  A
  * team's members synchronise through a bounded wait; should one ever exceed
- * 30 s, the item is abandoned and reported with GS2_ERR_HIP instead of the
- * launch hanging.  Synchronises `stream`; allocates.  Errors as gs2_setup.
+ * opt->team_wait_ms, the item is abandoned and reported with GS2_ERR_HIP
+ * instead of the launch hanging.  Synchronises `stream`; allocates.  Errors
+ * as gs2_setup.
  */
 int gs2_setup_batched(const gs2_csr *As, int nsys, int sweeps, int inner, double damping, int variant,
                       const gs2_options *opt, int restart, int nrhs, void *stream, gs2_batch **out);

@@ -1324,7 +1324,9 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
         int dev = 0, khz = 0;
         GS2_TRY_HIP(hipGetDevice(&dev));
         GS2_TRY_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-        b.cst.spin_ticks = (long long)std::max(khz, 1000) * 1000LL * 30; // 30 s per team barrier
+        const long long ms = o.team_wait_ms > 0 ? o.team_wait_ms : 30000;
+        // a negative limit ends every wait at once: the abandon path, for tests
+        b.cst.spin_ticks = o.team_wait_ms < 0 ? -1 : (long long)std::max(khz, 1000) * ms;
     }
     b.team_rows = o.team_rows;
     b.cst.info = b.d_info;

@@ -606,6 +606,7 @@ void gs2_default_options(gs2_options *opt)
     opt->blocks = 1;
     opt->local_sweeps = 1;
     opt->team_rows = 0;
+    opt->team_wait_ms = 0;
 }
 
 int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,

@@ -38,7 +38,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("inner_damping", C.c_double), ("compact", C.c_int),
                 ("build_levels", C.c_int), ("autotune", C.c_int), ("lanes_per_row", C.c_int),
                 ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int), ("blocks", C.c_int),
-                ("local_sweeps", C.c_int), ("team_rows", C.c_int)]
+                ("local_sweeps", C.c_int), ("team_rows", C.c_int), ("team_wait_ms", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -301,13 +301,14 @@ class BatchHandle:
 
 def gs2_setup_batched(mats, sweeps=2, inner=2, damping=1.0, variant=FORWARD, precision=FP32, restart=20, nrhs=4,
                       inner_damping=1.0, autotune=True, lanes_per_row=0, rhs_per_item=0, compact=False, team_rows=0,
-                      stream=None) -> BatchHandle:
+                      team_wait_ms=0, stream=None) -> BatchHandle:
     """mats: list of DeviceCSR.  team_rows: rows x right-hand sides per
     workgroup of an item's team (0 = library default, < 0 = one workgroup
-    per item)."""
+    per item); team_wait_ms: longest team barrier wait (0 = default, < 0 =
+    none, which abandons every team item: the error path, for tests)."""
     descs = (CsrDesc * len(mats))(*[m.desc() for m in mats])
     opt = Options(precision, inner_damping, int(compact), 0, int(autotune), lanes_per_row, rhs_per_item, 0, 1, 1,
-                  team_rows)
+                  team_rows, team_wait_ms)
     out = C.c_void_p()
     st = lib().gs2_setup_batched(descs, len(mats), sweeps, inner, damping, variant, C.byref(opt), restart, nrhs,
                                  _stream(stream), C.byref(out))

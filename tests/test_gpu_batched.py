@@ -103,6 +103,31 @@ def test_batched_teams_against_single_workgroups():
             assert np.linalg.norm(a - b) / np.linalg.norm(a) <= 1e-6
 
 
+def test_batched_team_wait_limit_abandons_items():
+    """The team barrier's bounded wait, forced from the host (no wait at all):
+    every team item is abandoned with GS2_ERR_HIP instead of hanging, the
+    single-workgroup items still converge, and the launch ends normally.  A
+    handle with the default wait then solves the same batch."""
+    from paper_2104_01196_amd.native import ERR_HIP
+
+    mats, rhs = make_batch([12, 40, 44], 2, 13)  # 144 rows alone; 1600 and 1936 rows in teams
+    dm = [g.DeviceCSR.from_host(A) for A in mats]
+    bh = g.gs2_setup_batched(dm, nrhs=2, sweeps=1, inner=1, precision=g.FP64, restart=15, rhs_per_item=1,
+                             team_rows=256, team_wait_ms=-1)
+    B = torch.as_tensor(np.concatenate([r.ravel() for r in rhs]), device=DEV)
+    X = torch.zeros_like(B)
+    st, infos = g.gmres_solve_batched(bh, 2, B, X, 1e-8, 5000, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert st == ERR_HIP
+    for r in range(2):
+        assert infos[r]["converged"] and infos[r]["status"] == 0
+    assert all(f["status"] == ERR_HIP and not f["converged"] for f in infos[2:])
+    st, infos, xs, *_ = run_batch(mats, rhs, 2, sweeps=1, inner=1, precision=g.FP64, restart=15, rhs_per_item=1,
+                                  team_rows=256)
+    assert st == 0
+    check_against_oracle(mats, rhs, 2, infos, xs, oracle.FP64, 1, 1, 15)
+
+
 @pytest.mark.parametrize("precision", [g.FP64, g.FP16_SCALED])
 def test_batched_other_precisions(precision):
     mats, rhs = make_batch([17, 33, 12], 2, 8)
