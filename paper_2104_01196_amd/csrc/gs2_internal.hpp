@@ -155,10 +155,12 @@ struct Sell {
     int64_t padded = 0; // stored entries (multiple of 64 per slice)
     int64_t *slice_ptr = nullptr;
     int32_t *col = nullptr;
-    // col - row of every stored entry when all of them fit in 16 bits (the
-    // usual case for mesh matrices in their natural ordering), else null.
-    // The streaming kernels then read 2 instead of 4 index bytes per entry.
-    int16_t *off = nullptr;
+    // col - row - off_min of every stored entry as an unsigned 16-bit number
+    // when the offsets of the whole triangle span at most 65535 (the usual
+    // case for mesh matrices in their natural ordering), else null.  The
+    // streaming kernels then read 2 instead of 4 index bytes per entry.
+    uint16_t *off = nullptr;
+    int off_min = 0;
     void *val = nullptr;
     int val_bytes = 8;
     int idx_bytes() const { return off ? 2 : 4; }
@@ -166,9 +168,10 @@ struct Sell {
 
 // Build the 16-bit column offsets of a sliced-ELL array (K lanes per row,
 // slice pointers sp, padded entries, columns col; lane l of slice s holds row
-// s * 64/K + l/K).  *off is left null when some |col - row| exceeds 32767.
-int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *col, int64_t padded, int16_t **off,
-                      hipStream_t s);
+// s * 64/K + l/K): *off = col - row - *off_min.  *off is left null when the
+// offsets span more than 65535.
+int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *col, int64_t padded, uint16_t **off,
+                      int *off_min, hipStream_t s);
 
 struct GmresWork; // krylov.hip
 struct CgWork;    // cg.hip

@@ -227,10 +227,11 @@ void free_sell(Sell &S)
     S.val = nullptr;
 }
 
-// One thread per (slice, lane): off = col - row, or a flag when it does not
-// fit in 16 bits.
+// One thread per (slice, lane): d = col - row for each of its entries.
+// Pass 0 folds the smallest and largest d into mm[0], mm[1]; pass 1 writes
+// d - dmin.
 __global__ void k_col_offsets(int64_t nslices, int K, const int64_t *__restrict__ sp, const int32_t *__restrict__ col,
-                              int16_t *__restrict__ off, int *__restrict__ too_far)
+                              int pass, int dmin, uint16_t *__restrict__ off, int *__restrict__ mm)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t s = gid / WAVE;
@@ -239,46 +240,55 @@ __global__ void k_col_offsets(int64_t nslices, int K, const int64_t *__restrict_
     const int64_t row = s * (WAVE / K) + l / K;
     const int64_t beg = sp[s];
     const int steps = (int)((sp[s + 1] - beg) / WAVE);
-    int far = 0;
+    int lo = 0x7fffffff, hi = -0x7fffffff;
     for (int t = 0; t < steps; ++t) {
         const int64_t pos = beg + (int64_t)t * WAVE + l;
-        const int64_t d = (int64_t)col[pos] - row;
-        if (d < -32767 || d > 32767) far = 1;
-        else off[pos] = (int16_t)d;
+        const int d = (int)((int64_t)col[pos] - row);
+        if (pass == 0) {
+            lo = d < lo ? d : lo;
+            hi = d > hi ? d : hi;
+        } else {
+            off[pos] = (uint16_t)(d - dmin);
+        }
     }
-    if (far) atomicOr(too_far, 1);
+    if (pass == 0 && steps > 0) {
+        atomicMin(&mm[0], lo);
+        atomicMax(&mm[1], hi);
+    }
 }
 
-int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *col, int64_t padded, int16_t **off,
-                      hipStream_t s)
+int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *col, int64_t padded, uint16_t **off,
+                      int *off_min, hipStream_t s)
 {
     *off = nullptr;
+    *off_min = 0;
     if (nslices <= 0) return GS2_OK;
-    int16_t *o = nullptr;
-    int *flag = nullptr;
-    int h_flag = 0;
-    GS2_TRY_HIP(hipMalloc(&o, sizeof(int16_t) * std::max<int64_t>(padded, WAVE)));
-    if (hipMalloc(&flag, sizeof(int)) != hipSuccess) {
-        (void)hipFree(o);
-        return GS2_ERR_NOMEM;
-    }
+    int *mm = nullptr;
+    GS2_TRY_HIP(hipMalloc(&mm, 2 * sizeof(int)));
+    const int init[2] = {0x7fffffff, -0x7fffffff};
+    int h[2] = {0, 0};
     const int tb = 256;
-    const int64_t threads = nslices * WAVE;
+    const unsigned grid = (unsigned)((nslices * WAVE + tb - 1) / tb);
     int st = GS2_OK;
-    if (hipMemsetAsync(flag, 0, sizeof(int), s) != hipSuccess) st = GS2_ERR_HIP;
+    if (hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) st = GS2_ERR_HIP;
     if (st == GS2_OK) {
-        k_col_offsets<<<(unsigned)((threads + tb - 1) / tb), tb, 0, s>>>(nslices, K, sp, col, o, flag);
-        if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        k_col_offsets<<<grid, tb, 0, s>>>(nslices, K, sp, col, 0, 0, nullptr, mm);
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             st = GS2_ERR_HIP;
     }
-    (void)hipFree(flag);
-    if (st != GS2_OK || h_flag) {
+    (void)hipFree(mm);
+    if (st != GS2_OK) return st;
+    if (h[0] > h[1] || (int64_t)h[1] - (int64_t)h[0] > 65535) return GS2_OK; // no entries, or too wide: 32 bits
+    uint16_t *o = nullptr;
+    GS2_TRY_HIP(hipMalloc(&o, sizeof(uint16_t) * std::max<int64_t>(padded, WAVE)));
+    k_col_offsets<<<grid, tb, 0, s>>>(nslices, K, sp, col, 1, h[0], o, nullptr);
+    if (hipGetLastError() != hipSuccess) {
         (void)hipFree(o);
-        return st;
+        return GS2_ERR_HIP;
     }
     *off = o;
+    *off_min = h[0];
     return GS2_OK;
 }
 
@@ -332,7 +342,7 @@ static int build_one(Sell &S, int64_t n, int K, int precision, const gs2_csr &A,
             k_fill<_Float16><<<grid, tb, 0, s>>>(n, S.nslices, K, A.rowptr, A.colind, A.val, R, sl, sr, S.slice_ptr,
                                                  S.col, (_Float16 *)S.val, err);
         GS2_TRY_HIP(hipGetLastError());
-        GS2_TRY(build_col_offsets(S.nslices, K, S.slice_ptr, S.col, S.padded, &S.off, s));
+        GS2_TRY(build_col_offsets(S.nslices, K, S.slice_ptr, S.col, S.padded, &S.off, &S.off_min, s));
     }
     return GS2_OK;
 }

@@ -23,11 +23,12 @@ enum : int { DST_G = 0, DST_XADD = 1, DST_XSET = 2, DST_ZADD = 3, DST_ZSET = 4 }
 struct SellView {
     const int64_t *sp;
     const int32_t *col;
-    const int16_t *off; // col - row per entry, when the triangle has them
+    const uint16_t *off; // col - row - off_min per entry, when the triangle has them
+    int off_min;
     const void *val;
 };
 
-static SellView view(const Sell &S) { return SellView{S.slice_ptr, S.col, S.off, S.val}; }
+static SellView view(const Sell &S) { return SellView{S.slice_ptr, S.col, S.off, S.off_min, S.val}; }
 
 template <typename AT>
 __device__ __forceinline__ void finish(int dst, int64_t row, AT g, AT w, AT *gout, AT *xh, AT *xout, double *z,
@@ -56,8 +57,8 @@ constexpr int su_of()
 }
 
 // acc[u] += sum over the stored entries of slice s0 + u of val * src(col);
-// the column is row + off (2 index bytes per entry) when the triangle has
-// 16-bit offsets, else read in full.
+// the column is row + off_min + off (2 index bytes per entry) when the
+// triangle has 16-bit offsets, else read in full.
 template <typename VT, typename AT, int SUN, int K, typename Src>
 __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t nslices, int lane, Src src,
                                            AT (&acc)[SUN])
@@ -75,10 +76,10 @@ __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t
     }
     const VT *__restrict__ val = (const VT *)T.val;
     if (T.off) {
-        const int16_t *__restrict__ off = T.off;
+        const uint16_t *__restrict__ off = T.off;
         int rw[SUN];
 #pragma unroll
-        for (int u = 0; u < SUN; ++u) rw[u] = (int)((s0 + u) * (WAVE / K) + lane / K);
+        for (int u = 0; u < SUN; ++u) rw[u] = (int)((s0 + u) * (WAVE / K) + lane / K) + T.off_min;
 #pragma unroll 4
         for (int t = 0; t < tmax; ++t) {
 #pragma unroll
