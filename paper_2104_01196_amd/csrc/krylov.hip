@@ -148,6 +148,29 @@ static int alloc_work(GmresWork **out, int64_t n, int m)
 // ---------------------------------------------------------------- kernels
 
 // Sum of one value per thread over the workgroup; result valid in thread 0.
+// Sum of p[b] over this thread's b = threadIdx.x, + KT, ... < cnt.  Eight
+// loads are in flight at once (a plain strided loop waits for each load
+// before the next: one memory latency per partial); the eight running sums
+// are added in a fixed order.
+__device__ __forceinline__ double strided_sum(const double *__restrict__ p, int cnt)
+{
+    constexpr int U = 8;
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    for (int b0 = threadIdx.x; b0 < cnt; b0 += KT * U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * KT;
+            acc[u] += b < cnt ? p[b] : 0.0;
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += acc[u];
+    return s;
+}
+
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
     v = wave_sum(v);
@@ -349,8 +372,7 @@ __global__ __launch_bounds__(KT) void k_reduce(const double *__restrict__ part, 
     const int cnt = fixed_cnt > 0 ? fixed_cnt : st->j + 1 + cnt_extra;
     const int k = blockIdx.x;
     if (k >= cnt) return;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += KT) s += part[(int64_t)k * nb + b];
+    double s = strided_sum(part + (int64_t)k * nb, nb);
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
         switch (dst) {
@@ -625,9 +647,22 @@ __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ p
     GState *ls = reinterpret_cast<GState *>(sw);
     const int t = threadIdx.x;
     const unsigned long long *gw = reinterpret_cast<const unsigned long long *>(st);
-    for (int k = t; k < GSTATE_SMALL_WORDS; k += KT) sw[k] = gw[k];
-    double tot = 0.0;
-    for (int b = t; b < nb; b += KT) tot += part[b];
+    {
+        // all of this thread's words in flight at once, then into LDS
+        constexpr int SQ = (GSTATE_SMALL_WORDS + KT - 1) / KT;
+        unsigned long long v[SQ];
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) {
+            const int k = t + q * KT;
+            v[q] = k < GSTATE_SMALL_WORDS ? gw[k] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) {
+            const int k = t + q * KT;
+            if (k < GSTATE_SMALL_WORDS) sw[k] = v[q];
+        }
+    }
+    double tot = strided_sum(part, nb);
     tot = block_sum(tot, red); // ends with a barrier: the staged state is complete
     if (ls->done) return;
     const int j = ls->j;
