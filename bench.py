@@ -367,7 +367,8 @@ def bench_batched(args, g, torch, np):
             each.append(time.perf_counter() - te)
         its = [f["iterations"] for f in infos]
         res[name] = {"time_s": float(np.mean(each)), "median_s": float(np.median(each)), "min_s": min(each),
-                     "max_s": max(each), "setup_s": setup_s, "status": st, "iterations_max": max(its),
+                     "max_s": max(each), "setup_s": setup_s, "status": st, "iterations": its,
+                     "iterations_max": max(its),
                      "iterations_mean": float(np.mean(its)), "worst_relres_true": check(X.cpu().numpy())}
         log(f"[bench] {name}: {res[name]['time_s'] * 1e3:.1f} ms for all {len(its)} pairs, its mean "
             f"{res[name]['iterations_mean']:.0f} max {max(its)}, worst relres {res[name]['worst_relres_true']:.2e}")
@@ -407,6 +408,9 @@ def bench_batched(args, g, torch, np):
     log(f"[bench] sequential_fp64: {seq * 1e3:.1f} ms, its mean {np.mean(its):.0f} max {max(its)}, worst relres "
         f"{res['sequential_fp64']['worst_relres_true']:.2e}")
     head = res["batched_fp32"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = batched_cpu_baseline(mats, rhs, res["batched_fp32"]["iterations"], restart, rtol, maxit, np)
     out = {
         "metric": "GS2-GMRES time-to-solution (s), batched form vs plain FP64 form",
         "value": head["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -415,10 +419,47 @@ def bench_batched(args, g, torch, np):
         "config": {"workload": "512 convdiff2d upwind systems (sides U{16..256}, Pe U(0,50)) x 4 RHS, GS2(2,2) "
                                "FP32 preconditioner, GMRES(20) FP64, rtol 1e-8, one persistent launch",
                    "systems": len(mats), "rows": sum(A.n for A in mats), "nrhs": nrhs},
+        "cpu_baseline": cpu,
         "forms": res,
         "speedup_vs_sequential_fp64": seq / head["time_s"],
     }
     print(json.dumps(out), flush=True)
+
+
+def batched_cpu_baseline(mats, rhs, gpu_its, restart, rtol, maxit, np):
+    """The oracle on a bounded sample of the batch: one right-hand side of
+    every 16th system (sizes across the whole range), the float32-form GS2(2,2)
+    GMRES(20) solves run by host threads at once (each oracle solve is one C
+    call, outside the interpreter lock).  Extrapolated to all pairs by rows x
+    iterations (the GPU's counts for the pairs not in the sample)."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    nrhs = rhs[0].shape[1]
+    sample = list(range(0, len(mats), 16))
+    threads = max(1, min(16, os.cpu_count() or 1, len(sample)))
+
+    def one(i):
+        _, oi = oracle.gmres(mats[i], rhs[i][:, 0], restart=restart, rtol=rtol, maxit=maxit, prec="gs2",
+                             sweeps=2, inner=2, precision=oracle.FP32)
+        return i, oi["iterations"], oi["seconds"]
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        done = list(ex.map(one, sample))
+    wall = time.perf_counter() - t0
+    busy = sum(t for *_, t in done)
+    work_sample = sum(mats[i].n * its for i, its, _ in done)
+    work_all = sum(mats[i].n * gpu_its[i * nrhs + r] for i in range(len(mats)) for r in range(nrhs))
+    # the threads kept perfectly busy: the CPU's best case for the whole batch
+    value = busy / threads * work_all / max(work_sample, 1)
+    log(f"[bench] cpu oracle: {len(sample)} pairs in {wall:.1f}s on {threads} threads "
+        f"(thread time {busy:.1f}s) -> {value:.1f} s extrapolated")
+    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} pairs (right-hand side 0 of every 16th system), {busy:.1f}s of oracle time on "
+                      f"{threads} host threads ({wall:.1f}s wall); extrapolated to all {len(mats) * nrhs} pairs by "
+                      f"rows x iterations, the threads assumed perfectly busy"}
 
 
 if __name__ == "__main__":
