@@ -238,6 +238,7 @@ def main():
                              variant=pv, sweeps=psw, inner=pin)
         per_step = oi["seconds"] / max(oi["iterations"], 1)
         cpu = {"value": per_step * head["iterations"], "unit": "s", "cores": nthreads, "kind": "oracle",
+               "host": cpu_model(),
                "sample": f"first GMRES(50) cycle ({oi['iterations']} Arnoldi steps, {oi['seconds']:.1f}s) of the "
                          f"same float64 solve, extrapolated to the GPU's {head['iterations']} iterations"}
         log(f"[bench] cpu oracle: {per_step:.3f} s/step -> {cpu['value']:.1f} s extrapolated")
@@ -262,6 +263,20 @@ def main():
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    """The host CPU's model name and logical CPU count, for the baseline records."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name}, {os.cpu_count()} logical CPUs visible"
 
 
 def bench_compare(args, g, torch, np):
@@ -456,7 +471,7 @@ def batched_cpu_baseline(mats, rhs, gpu_its, restart, rtol, maxit, np):
     value = busy / threads * work_all / max(work_sample, 1)
     log(f"[bench] cpu oracle: {len(sample)} pairs in {wall:.1f}s on {threads} threads "
         f"(thread time {busy:.1f}s) -> {value:.1f} s extrapolated")
-    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle",
+    return {"value": value, "unit": "s", "cores": threads, "kind": "oracle", "host": cpu_model(),
             "sample": f"{len(sample)} pairs (right-hand side 0 of every 16th system), {busy:.1f}s of oracle time on "
                       f"{threads} host threads ({wall:.1f}s wall); extrapolated to all {len(mats) * nrhs} pairs by "
                       f"rows x iterations, the threads assumed perfectly busy"}
