@@ -13,9 +13,10 @@
 // team's rows are split among its members; its passes are separated by a
 // barrier on a per-item arrival counter (agent-scope release / acquire), and
 // its reductions sum the members' partials in member order, so every member
-// holds bit-identical scalars and repeats the small serial work itself.  The R right-hand sides of
-// an item are stored interleaved (row-major n x R), so each matrix entry is
-// loaded once per group and applied to R vectors (an SpMM-like access).
+// holds bit-identical scalars and repeats the small serial work itself.  The
+// R right-hand sides of an item are stored interleaved (row-major n x R), so
+// each matrix entry is loaded once per group and applied to R vectors (an
+// SpMM-like access).
 // Each right-hand side keeps its own Hessenberg matrix, rotations and
 // convergence flag; a right-hand side that has converged stops contributing
 // while the others continue.  The Arnoldi process is classical Gram-Schmidt
