@@ -163,8 +163,21 @@ struct Sell {
     int off_min = 0;
     void *val = nullptr;
     int val_bytes = 8;
+    // stream the values and offsets past the caches (set for large triangles)
+    int nt = 0;
     int idx_bytes() const { return off ? 2 : 4; }
+    double stored_bytes() const { return (double)padded * (val_bytes + idx_bytes()); }
 };
+
+// The sweep kernels load a triangle with the non-temporal policy once both
+// triangles together store more than this: below it they stay in the 256 MB
+// last-level cache from one pass to the next and the normal policy is
+// faster (128^3 Laplacian, float64, 126 MB: 38.2 ms normal, 40.7 ms
+// non-temporal); above it every pass streams them from HBM and keeping them
+// out of the caches leaves those to the gathered vectors (192^3 problem:
+// 425 / 255 / 170 MB in float64 / float32 / scaled float16: 260.5 / 244.0 /
+// 238.8 ms normal, 252.1 / 239.1 / 236.4 ms non-temporal).
+constexpr double NT_TRIANGLES_BYTES = 150e6;
 
 // Build the 16-bit column offsets of a sliced-ELL array (K lanes per row,
 // slice pointers sp, padded entries, columns col; lane l of slice s holds row

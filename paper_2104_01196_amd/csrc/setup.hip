@@ -572,6 +572,7 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
     GS2_TRY(build_part(h, h.U, PART_U, K, A, sc, s));
     h.U.nnz = count_total(sc.R.tot, n, s, &cst);
     GS2_TRY(cst);
+    h.L.nt = h.U.nt = h.L.stored_bytes() + h.U.stored_bytes() > NT_TRIANGLES_BYTES ? 1 : 0;
     if (h.blocks > 1) {
         GS2_TRY(build_part(h, h.E, PART_E, K, A, sc, s));
         h.E.nnz = count_total(sc.R.tot, n, s, &cst);

@@ -25,10 +25,11 @@ struct SellView {
     const int32_t *col;
     const uint16_t *off; // col - row - off_min per entry, when the triangle has them
     int off_min;
+    int nt; // load values and offsets with the non-temporal policy
     const void *val;
 };
 
-static SellView view(const Sell &S) { return SellView{S.slice_ptr, S.col, S.off, S.off_min, S.val}; }
+static SellView view(const Sell &S) { return SellView{S.slice_ptr, S.col, S.off, S.off_min, S.nt, S.val}; }
 
 template <typename AT>
 __device__ __forceinline__ void finish(int dst, int64_t row, AT g, AT w, AT *gout, AT *xh, AT *xout, double *z,
@@ -58,7 +59,8 @@ constexpr int su_of()
 
 // acc[u] += sum over the stored entries of slice s0 + u of val * src(col);
 // the column is row + off_min + off (2 index bytes per entry) when the
-// triangle has 16-bit offsets, else read in full.
+// triangle has 16-bit offsets, else read in full.  A large triangle's values
+// and offsets are streamed with the non-temporal policy.
 template <typename VT, typename AT, int SUN, int K, typename Src>
 __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t nslices, int lane, Src src,
                                            AT (&acc)[SUN])
@@ -80,6 +82,20 @@ __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t
         int rw[SUN];
 #pragma unroll
         for (int u = 0; u < SUN; ++u) rw[u] = (int)((s0 + u) * (WAVE / K) + lane / K) + T.off_min;
+        if (T.nt) {
+#pragma unroll 4
+            for (int t = 0; t < tmax; ++t) {
+#pragma unroll
+                for (int u = 0; u < SUN; ++u) {
+                    if (t < steps[u]) {
+                        const int64_t p = beg[u] + (int64_t)t * WAVE + lane;
+                        acc[u] += (AT)__builtin_nontemporal_load(&val[p]) *
+                                  src(rw[u] + (int)__builtin_nontemporal_load(&off[p]));
+                    }
+                }
+            }
+            return;
+        }
 #pragma unroll 4
         for (int t = 0; t < tmax; ++t) {
 #pragma unroll
@@ -147,8 +163,8 @@ __global__ __launch_bounds__(256) void k_inner(const int *__restrict__ stop, int
 // The result goes to rh (DST_G) or is fused into a Jacobi-type update of xh
 // written to xout (double-buffered: xh is gathered here).  The couplings to
 // other blocks (hybrid relaxation) multiply the values frozen at the last
-// exchange.  (Loading the triangles here with the non-temporal policy was
-// measured: no gain in float64, 3 % slower solves in the 32-bit forms.)
+// exchange.  The triangles' cache policy is the size-based one of
+// slice_dots.
 template <typename VT, typename AT, int K>
 __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView P,
                                                SellView Q, int two, const AT *__restrict__ xh,
