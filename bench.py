@@ -53,6 +53,8 @@ def parse():
                     help="with --config 2: GMRES(50) with each preconditioner of the comparison (GS2, SGS2, JR, "
                          "exact level-scheduled GS, multicolor GS) instead of the default measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="config 5: skip the one-solve-per-pair comparison (e.g. under a kernel tracer)")
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16 preconditioner solves")
     ap.add_argument("--profile", choices=["on", "off"], default="on",
                     help="per-kernel HIP-event timing of the float64 solves (a second pass of the same solves)")
@@ -389,8 +391,34 @@ def bench_batched(args, g, torch, np):
             f"{res[name]['iterations_mean']:.0f} max {max(its)}, worst relres {res[name]['worst_relres_true']:.2e}")
         del bh
 
-    # plain FP64 path: one handle per system, one solve per pair (per-system b/x
-    # buffers so each system's captured restart cycle is replayed for all its pairs)
+    seq = None
+    if not args.no_sequential:
+        seq = sequential_pairs(g, torch, np, mats, dm, B, nrhs, restart, rtol, maxit, check, res)
+    head = res["batched_fp32"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = batched_cpu_baseline(mats, rhs, res["batched_fp32"]["iterations"], restart, rtol, maxit, np)
+    for r in res.values():
+        r.pop("iterations", None)
+    out = {
+        "metric": "GS2-GMRES time-to-solution (s), batched form vs plain FP64 form",
+        "value": head["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["time_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 preconditioner / f64 Krylov", "data": "synthetic",
+        "config": {"workload": "512 convdiff2d upwind systems (sides U{16..256}, Pe U(0,50)) x 4 RHS, GS2(2,2) "
+                               "FP32 preconditioner, GMRES(20) FP64, rtol 1e-8, one persistent launch",
+                   "systems": len(mats), "rows": sum(A.n for A in mats), "nrhs": nrhs},
+        "cpu_baseline": cpu,
+        "forms": res,
+        "speedup_vs_sequential_fp64": seq / head["time_s"] if seq else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def sequential_pairs(g, torch, np, mats, dm, B, nrhs, restart, rtol, maxit, check, res):
+    """The plain FP64 path: one handle per system, one solve per pair
+    (per-system b/x buffers so each system's captured restart cycle is
+    replayed for all its pairs).  Returns the wall time of all pairs."""
     ts = time.time()
     hs = [g.gs2_setup(d, 2, 2, 1.0, g.FORWARD, precision=g.FP64) for d in dm]
     bb = [torch.empty(A.n, dtype=torch.float64, device="cuda") for A in mats]
@@ -422,23 +450,7 @@ def bench_batched(args, g, torch, np):
                               "iterations_mean": float(np.mean(its)), "worst_relres_true": check(Xs.cpu().numpy())}
     log(f"[bench] sequential_fp64: {seq * 1e3:.1f} ms, its mean {np.mean(its):.0f} max {max(its)}, worst relres "
         f"{res['sequential_fp64']['worst_relres_true']:.2e}")
-    head = res["batched_fp32"]
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = batched_cpu_baseline(mats, rhs, res["batched_fp32"]["iterations"], restart, rtol, maxit, np)
-    out = {
-        "metric": "GS2-GMRES time-to-solution (s), batched form vs plain FP64 form",
-        "value": head["time_s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": head["time_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 preconditioner / f64 Krylov", "data": "synthetic",
-        "config": {"workload": "512 convdiff2d upwind systems (sides U{16..256}, Pe U(0,50)) x 4 RHS, GS2(2,2) "
-                               "FP32 preconditioner, GMRES(20) FP64, rtol 1e-8, one persistent launch",
-                   "systems": len(mats), "rows": sum(A.n for A in mats), "nrhs": nrhs},
-        "cpu_baseline": cpu,
-        "forms": res,
-        "speedup_vs_sequential_fp64": seq / head["time_s"],
-    }
-    print(json.dumps(out), flush=True)
+    return seq
 
 
 def batched_cpu_baseline(mats, rhs, gpu_its, restart, rtol, maxit, np):
