@@ -217,6 +217,13 @@ struct Handle {
     GmresWork *gw = nullptr;
     CgWork *cw = nullptr;
     const int *stop = nullptr; // device flag: kernels return at once when set (GMRES)
+    // GMRES: the serial work that closes its previous Arnoldi step, run by one
+    // extra workgroup of the next apply's first pass (consumed by that apply)
+    struct FinJob {
+        const double *part = nullptr;
+        int nb = 0;
+        void *st = nullptr;
+    } fin;
     ~Handle();
 };
 

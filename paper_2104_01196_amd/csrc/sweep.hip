@@ -13,6 +13,7 @@
 // needs no SpMV.  Every pass reads its triangle exactly once.
 #include <algorithm>
 
+#include "dcgs_state.hpp"
 #include "gs2_internal.hpp"
 
 namespace gs2 {
@@ -123,19 +124,31 @@ __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t
 
 // Inner JR pass: g_new = rh - w T g_old (optionally damped with gamma), one
 // or two slices of T per wavefront.  rv: rh_i = AT(v_i s_l[i]) (first half
-// of an apply); gv: g_old_j = AT(v_j s_l[j]) (its first inner pass).
+// of an apply); gv: g_old_j = AT(v_j s_l[j]) (its first inner pass).  With
+// fst, the first workgroup instead runs the serial work that closes the
+// previous GMRES step (dcgs_finish_block): it reads only that step's partial
+// sums and the solver state, nothing this pass touches, so the two overlap
+// (it is dispatched first, before the pass fills the machine) and the step
+// saves a launch.
 template <typename VT, typename AT, int K>
-__global__ __launch_bounds__(256) void k_inner(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView T,
-                                               const AT *__restrict__ rh, const AT *__restrict__ gin,
-                                               const double *__restrict__ v, const double *__restrict__ sl, int rv,
-                                               int gv, int damp, AT w, AT gamma, int dst, AT *__restrict__ gout,
-                                               AT *__restrict__ xh, double *__restrict__ z,
-                                               const double *__restrict__ sr)
+__global__ __launch_bounds__(KT) void k_inner(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView T,
+                                              const AT *__restrict__ rh, const AT *__restrict__ gin,
+                                              const double *__restrict__ v, const double *__restrict__ sl, int rv,
+                                              int gv, int damp, AT w, AT gamma, int dst, AT *__restrict__ gout,
+                                              AT *__restrict__ xh, double *__restrict__ z,
+                                              const double *__restrict__ sr, const double *__restrict__ fpart,
+                                              int fnb, void *fst)
 {
     constexpr int SUN = su_of<AT>();
+    if (fst && blockIdx.x == 0) {
+        dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+        return;
+    }
     if (stop && *stop) return;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t s0 = (xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE) * SUN;
+    const unsigned sh = fst ? 1u : 0u;
+    const int64_t s0 =
+        (xcd_remap(blockIdx.x - sh, gridDim.x - sh) * (blockDim.x / WAVE) + threadIdx.x / WAVE) * SUN;
     if (s0 >= nslices) return;
     AT acc[SUN];
 #pragma unroll
@@ -303,7 +316,7 @@ __global__ void k_color(const int *__restrict__ stop, const int32_t *__restrict_
 
 // ------------------------------------------------------------ host drivers
 
-constexpr int TB = 256; // 4 wavefronts per workgroup, one slice each
+constexpr int TB = KT; // 4 wavefronts per workgroup, one or two slices each
 
 static inline unsigned grid_for(int64_t nslices, int su)
 {
@@ -316,11 +329,13 @@ template <typename VT, typename AT>
 struct Launch {
     template <int K>
     static void inner_k(const Handle &h, const Sell &T, const AT *rh, const AT *gin, const double *v, int rv, int gv,
-                        int dst, AT *gout, AT *xh, double *z, hipStream_t s)
+                        int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
     {
         const int damp = h.gamma != 1.0;
-        k_inner<VT, AT, K><<<grid_for(T.nslices, su_of<AT>()), TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv, gv, damp,
-                                                              (AT)h.omega, (AT)h.gamma, dst, gout, xh, z, h.sr);
+        const unsigned grid = grid_for(T.nslices, su_of<AT>()) + (fj.st ? 1u : 0u);
+        k_inner<VT, AT, K><<<grid, TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv, gv, damp,
+                                               (AT)h.omega, (AT)h.gamma, dst, gout, xh, z, h.sr, fj.part, fj.nb,
+                                               fj.st);
     }
     // algorithmic bytes of one pass: each stored entry (value + column) and
     // each vector element read or written once; padding is not counted
@@ -340,19 +355,20 @@ struct Launch {
         }
     }
     static void inner(const Handle &h, const Sell &T, const AT *rh, const AT *gin, const double *v, int rv, int gv,
-                      int dst, AT *gout, AT *xh, double *z, hipStream_t s)
+                      int dst, AT *gout, AT *xh, double *z, hipStream_t s,
+                      const Handle::FinJob &fj = Handle::FinJob{})
     {
         const double bx = sizeof(AT);
         const double src = gv ? 16.0 : rv ? 16.0 + bx : 2 * bx;
         Prof pr(s, PK_INNER, tri_bytes(T) + (double)h.n * (src + dst_bytes(dst)));
         switch (T.K) {
-        case 1: inner_k<1>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
-        case 2: inner_k<2>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
-        case 4: inner_k<4>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
-        case 8: inner_k<8>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
-        case 16: inner_k<16>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
-        case 32: inner_k<32>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
-        default: inner_k<64>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s); break;
+        case 1: inner_k<1>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 2: inner_k<2>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 4: inner_k<4>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 8: inner_k<8>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 16: inner_k<16>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 32: inner_k<32>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        default: inner_k<64>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
         }
     }
     template <int K>
@@ -388,6 +404,10 @@ struct Launch {
     {
         AT *xc = (AT *)h.xh, *xo = (AT *)h.xh2, *rh = (AT *)h.rh, *ga = (AT *)h.ga, *gb = (AT *)h.gb;
         AT *y = (AT *)h.yh;
+        // a GMRES step's closing work rides on this apply's first pass (an inner pass)
+        Handle::FinJob fj = h.fin;
+        h.fin = Handle::FinJob{};
+        if (fj.st && h.inner < 1) return GS2_ERR_ARG;
         const int per = h.variant == GS2_SYMMETRIC ? 2 : 1;
         const bool hyb = h.blocks > 1;
         const int nk = hyb ? h.local_sweeps : 1;
@@ -438,7 +458,8 @@ struct Launch {
                             AT *gout = (j & 1) ? ga : gb;
                             const int dst =
                                 !last ? DST_G : fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
-                            inner(h, T, rh, gin, v, rv, gv, dst, gout, xc, z, s);
+                            inner(h, T, rh, gin, v, rv, gv, dst, gout, xc, z, s, fj);
+                            fj = Handle::FinJob{};
                             gin = gout;
                         }
                     }
