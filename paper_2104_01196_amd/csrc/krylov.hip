@@ -717,11 +717,11 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         cycles++;
         const int steps = std::min(m, maxit - total);
         // one restart cycle, enqueued on stream `cs`
-        // The serial work closing step j (k_dcgs_finish) can run as one extra
-        // workgroup of the next step's first preconditioner pass when that pass
-        // is an inner GS2 pass: it needs only step j's partial sums and the
-        // state, and the pass needs neither.  The last step's runs alone.
-        const bool fuse_fin = orth == 0 && kind == GS2_PREC_GS2 && P && P->h.inner >= 1;
+        // The serial work closing step j (k_dcgs_finish) runs as one extra
+        // workgroup of the next step's first preconditioner pass when that is
+        // a GS2 or JR pass: it needs only step j's partial sums and the state,
+        // and the pass needs neither.  The last step's runs alone.
+        const bool fuse_fin = orth == 0 && P && (kind == GS2_PREC_GS2 || kind == GS2_PREC_JR);
         auto enqueue_cycle = [&](hipStream_t cs) -> int {
             k_cycle_init<<<1, 64, 0, cs>>>(st, steps, rtol);
             k_scale0<<<gE, 256, 0, cs>>>(n, W->V, st);

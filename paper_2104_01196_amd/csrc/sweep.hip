@@ -209,13 +209,21 @@ __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int
 }
 
 // First half of JR from xh = 0: xh = w S_l v, or z = S_r w S_l v if final.
+// With fst, the first workgroup closes the previous GMRES step (as in
+// k_inner).
 template <typename AT>
-__global__ void k_first_jr(const int *__restrict__ stop, int64_t n, const double *__restrict__ v, const double *__restrict__ sl,
-                           const double *__restrict__ sr, AT w, int final_, AT *__restrict__ xh,
-                           double *__restrict__ z)
+__global__ __launch_bounds__(KT) void k_first_jr(const int *__restrict__ stop, int64_t n,
+                                                 const double *__restrict__ v, const double *__restrict__ sl,
+                                                 const double *__restrict__ sr, AT w, int final_, AT *__restrict__ xh,
+                                                 double *__restrict__ z, const double *__restrict__ fpart, int fnb,
+                                                 void *fst)
 {
+    if (fst && blockIdx.x == 0) {
+        dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+        return;
+    }
     if (stop && *stop) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)(blockIdx.x - (fst ? 1u : 0u)) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const AT r = (AT)(v[i] * sl[i]);
     if (final_) z[i] = sr[i] * (double)(w * r);
@@ -404,10 +412,9 @@ struct Launch {
     {
         AT *xc = (AT *)h.xh, *xo = (AT *)h.xh2, *rh = (AT *)h.rh, *ga = (AT *)h.ga, *gb = (AT *)h.gb;
         AT *y = (AT *)h.yh;
-        // a GMRES step's closing work rides on this apply's first pass (an inner pass)
+        // a GMRES step's closing work rides on this apply's first pass
         Handle::FinJob fj = h.fin;
         h.fin = Handle::FinJob{};
-        if (fj.st && h.inner < 1) return GS2_ERR_ARG;
         const int per = h.variant == GS2_SYMMETRIC ? 2 : 1;
         const bool hyb = h.blocks > 1;
         const int nk = hyb ? h.local_sweeps : 1;
@@ -436,8 +443,9 @@ struct Launch {
                     if (h.inner == 0) {
                         if (xzero) {
                             Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (fin ? 16.0 : sizeof(AT))));
-                            k_first_jr<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0,
-                                                                         xc, z);
+                            k_first_jr<AT><<<grid_rows(h.n) + (fj.st ? 1u : 0u), TB, 0, s>>>(
+                                h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0, xc, z, fj.part, fj.nb, fj.st);
+                            fj = Handle::FinJob{};
                         } else {
                             const int dst = fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
                             if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, dst, nullptr, xo, z, s);
@@ -481,8 +489,12 @@ struct Launch {
         const int nk = hyb ? h.local_sweeps : 1;
         const int total = sweeps * nk;
         {
+            // a GMRES step's closing work rides on this first pass
+            const Handle::FinJob fj = h.fin;
+            h.fin = Handle::FinJob{};
             Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (total == 1 ? 16.0 : sizeof(AT))));
-            k_first_jr<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w, total == 1 ? 1 : 0, xc, z);
+            k_first_jr<AT><<<grid_rows(h.n) + (fj.st ? 1u : 0u), TB, 0, s>>>(
+                h.stop, h.n, v, h.sl, h.sr, w, total == 1 ? 1 : 0, xc, z, fj.part, fj.nb, fj.st);
         }
         bool yzero = true;
         for (int step = 1; step < total; ++step) {
