@@ -1,7 +1,7 @@
 // The device-side state of a GMRES restart cycle and the serial work that
 // closes an Arnoldi step of the delayed reorthogonalisation.  Shared by the
 // Krylov kernels and by the first preconditioner pass of the next step,
-// which runs that work in one extra workgroup (see k_inner).
+// which runs that work in one extra workgroup (k_inner, k_first_jr).
 #pragma once
 
 #include <cstddef>
@@ -146,9 +146,10 @@ __device__ inline bool reorth_scalars(const GState *st, int j, const double *as,
 // tentative rotation of column j and the residual estimate, and either stop
 // the cycle or advance j (the next tentative vector keeps its scale 1/||w'||
 // in zs[j+1]).  When u fell into span(Q) the cycle ends on the tentative
-// column j-1.  The kernel is latency-bound: the whole workgroup stages the
-// state (all but H) in LDS together with the partial sums, so one round
-// trip to memory precedes the serial work of one lane, and writes it back.
+// column j-1.  The work is latency-bound: the whole workgroup (KT threads)
+// stages the state (all but H) in LDS together with the partial sums, so one
+// round trip to memory precedes the serial work of one lane, and writes it
+// back.
 __device__ __forceinline__ void dcgs_finish_block(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
     __shared__ unsigned long long sw[GSTATE_SMALL_WORDS];
