@@ -269,10 +269,12 @@ static int cg_impl(const gs2_csr &A, const double *b, double *x, double rtol, in
     };
     // ||b||, initial state
     {
+        // staged in the pinned mirror (no copy from it is in flight here)
         CState init{};
         init.rtol = rtol;
         init.maxit = maxit;
-        GS2_TRY_HIP(hipMemcpyAsync(st, &init, sizeof(CState), hipMemcpyHostToDevice, s));
+        *W->hst = init;
+        GS2_TRY_HIP(hipMemcpyAsync(st, W->hst, sizeof(CState), hipMemcpyHostToDevice, s));
     }
     k_cg_dot<<<gN, CT, 0, s>>>(n, b, b, nullptr, W->part);
     k_cg_reduce<<<1, CT, 0, s>>>(W->part, nb, st, 0, &st->bnorm);
@@ -288,11 +290,12 @@ static int cg_impl(const gs2_csr &A, const double *b, double *x, double rtol, in
     }
     const double bnorm = std::sqrt(bn2);
     {
-        CState init{};
+        CState init{}; // the mirror was last filled by read_state, which synchronised
         init.bnorm = bnorm;
         init.rtol = rtol;
         init.maxit = maxit;
-        GS2_TRY_HIP(hipMemcpyAsync(st, &init, sizeof(CState), hipMemcpyHostToDevice, s));
+        *W->hst = init;
+        GS2_TRY_HIP(hipMemcpyAsync(st, W->hst, sizeof(CState), hipMemcpyHostToDevice, s));
     }
     int status = GS2_OK, runs = 0;
     for (;;) {

@@ -270,7 +270,9 @@ int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *
     const int tb = 256;
     const unsigned grid = (unsigned)((nslices * WAVE + tb - 1) / tb);
     int st = GS2_OK;
-    if (hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) st = GS2_ERR_HIP;
+    // a blocking copy: init lives on this stack frame
+    if (hipStreamSynchronize(s) != hipSuccess || hipMemcpy(mm, init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess)
+        st = GS2_ERR_HIP;
     if (st == GS2_OK) {
         k_col_offsets<<<grid, tb, 0, s>>>(nslices, K, sp, col, 0, 0, nullptr, mm);
         if (hipGetLastError() != hipSuccess || hipMemcpyAsync(h, mm, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
