@@ -144,6 +144,40 @@ def test_gs2_apply_reduced_precision(name, prec, tol, variant, sweeps, inner, w)
     assert rel_inf(host(z), ref) <= tol
 
 
+def test_wide_offsets_keep_32bit_columns():
+    """Triangles whose column offsets span more than 65535 keep their 32-bit
+    columns in the sweep kernels (the 16-bit offset form does not apply to
+    them): applies in every precision, JR and a GMRES solve meet the same
+    bars as on the other matrices."""
+    A = random_sparse(70000, seed=33, avg_offdiag=4)
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    d = A.colind.astype(np.int64) - rows
+    lo = d[d < 0]
+    assert 0 - lo.min() > 65535  # the strictly lower part alone spans more than 16 bits
+    dA = g.DeviceCSR.from_host(A)
+    v = vec(A.n, 41)
+    for variant, sweeps, inner, w in [(g.SYMMETRIC, 2, 2, 0.9), (g.FORWARD, 2, 1, 1.0)]:
+        h = g.gs2_setup(dA, sweeps, inner, w, variant)
+        z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+        g.gs2_apply(h, dev(v), z)
+        ref = oracle.gs2_apply(A, v, variant, sweeps, inner, w)
+        assert rel_inf(host(z), ref) <= 1e-12 * sweeps * 2
+        g.jr_apply(h, 3, 0.8, dev(v), z)
+        assert rel_inf(host(z), oracle.jr_sweep(A, v, np.zeros(A.n), 3, 0.8)) <= 3e-12
+    for prec, tol in [(g.FP32, 2e-5), (g.FP16_SCALED, 1e-4)]:
+        h = g.gs2_setup(dA, 2, 1, 1.0, g.FORWARD, precision=prec)
+        z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+        g.gs2_apply(h, dev(v), z)
+        assert rel_inf(host(z), oracle.gs2_apply_lp(A, v, prec, g.FORWARD, 2, 1, 1.0)) <= tol
+    b = A.to_scipy() @ vec(A.n, 42)
+    xo, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", sweeps=1, inner=1)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 30, 1e-8, 20000, g.PREC_GS2, h)
+    assert io["converged"] and info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+    assert np.linalg.norm(b - A.to_scipy() @ host(x)) / np.linalg.norm(b) <= 1e-8
+
+
 @pytest.mark.parametrize("name", list(MATS))
 @pytest.mark.parametrize("sweeps,w", [(1, 1.0), (3, 0.7)])
 def test_jr_apply(name, sweeps, w):
