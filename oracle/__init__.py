@@ -8,8 +8,10 @@ module only marshals numpy arrays through ctypes.
 
 Parity status per function (what pins it lives in tests/test_oracle_*.py):
   spmv, gs2_apply / gs2_sweep, jr_sweep, sor_sweep, levels, gmres,
-  round_f16, gs2_apply_lp (FP32 / FP16-scaled), gs2c_sweep (compact form), pcg:
-  all pinned.  inner_residuals: pinned only by its n_j -> depth limit.
+  round_f16, gs2_apply_lp (FP32 / FP16-scaled, including the binary32 rounding
+  of its row sums), gs2c_sweep (compact form), pcg, inner_residuals (dense
+  Neumann partial sums at damping != 1, and the n_j -> depth limit): all
+  pinned.
 """
 from __future__ import annotations
 

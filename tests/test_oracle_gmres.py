@@ -121,3 +121,29 @@ def test_solution_accuracy_config1():
     x, info = oracle.gmres(p["A"], p["b"], restart=30, rtol=1e-8, prec="gs2", sweeps=1, inner=1)
     assert info["converged"] and info["relres"] <= 1e-8
     assert np.linalg.norm(x - p["x_true"]) / np.linalg.norm(p["x_true"]) < 1e-4
+
+
+@pytest.mark.parametrize("cgs2", [False, True])
+def test_happy_breakdown_ends_the_cycle(cgs2):
+    """Happy breakdown (reading of the stopping rule: the Krylov space has
+    become invariant).  A = diag(1..6) and b in the span of its first two
+    eigenvectors: the Krylov space of b has dimension 2, so the second
+    Arnoldi step leaves only rounding noise (h_{3,2} ~ 1e-17).  rtol = 0 keeps
+    the residual-estimate test from ending the cycle (the recorded estimate
+    after step 2 is nonzero), so only the breakdown branch can: the first cycle
+    must end after exactly 2 steps with the exact solution, and the third step
+    then belongs to a second cycle."""
+    n = 6
+    d = np.arange(1, n + 1, dtype=np.float64)
+    A = CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d.copy())
+    b = np.array([0.3, 0.7, 0, 0, 0, 0])
+    # one cycle only: the breakdown leaves the cycle after step 2 with the exact solution
+    x, info = oracle.gmres(A, b, restart=10, rtol=0.0, maxit=2, prec="none", cgs2=cgs2, history=True)
+    assert info["iterations"] == 2 and info["restarts"] == 0
+    assert info["history"][2] > 0.0  # the estimate did not reach rtol = 0
+    np.testing.assert_allclose(x, b / d, rtol=0, atol=1e-15)
+    # a third step: it must start a second cycle (restart count 1)
+    x, info = oracle.gmres(A, b, restart=10, rtol=0.0, maxit=3, prec="none", cgs2=cgs2, history=True)
+    assert info["iterations"] == 3 and info["restarts"] == 1, info
+    assert info["history"][2] > 0.0
+    np.testing.assert_allclose(x, b / d, rtol=0, atol=1e-15)

@@ -310,3 +310,25 @@ def test_inner_residual_diagnostic():
     assert out[0] == pytest.approx(np.linalg.norm(L @ (r / np.diag(D))) / np.linalg.norm(r), rel=1e-12)
     assert out[6] < 1e-14 and out[7] < 1e-14
     assert all(out[j] > 1e-8 for j in range(6))
+
+
+@pytest.mark.parametrize("name", ["rand_nonsym", "rand_negdiag", "vardiff3d_3"])
+@pytest.mark.parametrize("w", [0.8, 1.3])
+def test_inner_residual_diagnostic_damped(name, w):
+    """The diagnostic for a damping w != 1 (Section 8, inner convergence):
+    g_j is the dense Neumann partial sum sum_{k<=j} (-w D^{-1} L)^k D^{-1} r
+    (Section 4), and the reported value is ||r - (wL + D) g_j|| / ||r||."""
+    A = MATS[name]()
+    L, D, U, M = parts(A)
+    r = np.random.default_rng(11).standard_normal(A.n)
+    J = 6
+    out = oracle.inner_residuals(A, r, J, omega=w)
+    Di = np.diag(1 / np.diag(D))
+    K = -w * Di @ L
+    g = np.zeros(A.n)
+    term = Di @ r
+    for j in range(J + 1):
+        g = g + term
+        ref = np.linalg.norm(r - (w * L + D) @ g) / np.linalg.norm(r)
+        assert out[j] == pytest.approx(ref, rel=1e-10, abs=1e-15), (j, out[j], ref)
+        term = K @ term

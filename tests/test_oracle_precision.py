@@ -97,3 +97,72 @@ def test_gmres_reduced_precision_reaches_tolerance():
         its[p] = info["iterations"]
     assert abs(its[oracle.FP32] - its[oracle.FP64]) <= 1
     assert abs(its[oracle.FP16S] - its[oracle.FP64]) <= max(2, its[oracle.FP64] // 10)
+
+
+# ------------------------------------------------ binary32 accumulation pin
+#
+# The reduced forms accumulate every row sum in binary32 (Section 10: the
+# preconditioner runs in single precision).  On a unit-diagonal matrix the
+# scaling is exact (s = 1) and every entry below is representable in binary32
+# and binary16 (2^-24 is the smallest binary16 subnormal), so only the
+# rounding of the partial sums can change the result.  Row 3 sums, in CSR
+# order, 1 * 1 + 2^-24 * 1 + 2^-24 * 1:
+#   binary32: 1 + 2^-24 lies halfway between 1 and 1 + 2^-23; round to
+#             nearest even keeps 1 (even significand); the second 2^-24 is
+#             again a tie and again gives 1.  The sum is 1.
+#   binary64: 1 + 2^-24 + 2^-24 = 1 + 2^-23 exactly.
+# With v_3 = 2 the inner step gives g_3 = 2 - 1 = 1 in binary32, while an
+# accumulation in binary64 would give 2 - (1 + 2^-23) = 1 - 2^-23, which is
+# representable in binary32 (spacing 2^-24 below 1) and so survives the
+# final rounding.
+
+def _tie_matrix(lower=True):
+    """4x4 unit-diagonal matrix whose only coupled row sums 1, 2^-24, 2^-24
+    (in CSR order) against the identity rows."""
+    e = 2.0 ** -24
+    if lower:  # row 3: columns 0, 1, 2 off the diagonal
+        rp = np.array([0, 1, 2, 3, 7], np.int32)
+        ci = np.array([0, 1, 2, 0, 1, 2, 3], np.int32)
+        va = np.array([1.0, 1.0, 1.0, 1.0, e, e, 1.0])
+        row = 3
+    else:  # row 0: columns 1, 2, 3 off the diagonal
+        rp = np.array([0, 4, 5, 6, 7], np.int32)
+        ci = np.array([0, 1, 2, 3, 1, 2, 3], np.int32)
+        va = np.array([1.0, 1.0, e, e, 1.0, 1.0, 1.0])
+        row = 0
+    return CSR(4, rp, ci, va), row
+
+
+@pytest.mark.parametrize("prec", [oracle.FP32, oracle.FP16S])
+@pytest.mark.parametrize("lower", [True, False])
+def test_binary32_accumulation_inner_sum(prec, lower):
+    """One GS2 half with one inner sweep from zero: the coupled row's inner
+    sum must round in binary32 (result exactly 1.0), while the float64
+    textbook form gives 1 - 2^-23."""
+    A, row = _tie_matrix(lower)
+    v = np.ones(4)
+    v[row] = 2.0
+    variant = F if lower else B
+    z = oracle.gs2_apply_lp(A, v, prec, variant, 1, 1, 1.0)
+    expect = np.ones(4)  # identity rows: z = v = 1; coupled row: 2 - 1 = 1
+    assert np.array_equal(z, expect), z
+    z64 = oracle.gs2_apply(A, v, variant, 1, 1, 1.0)
+    assert z64[row] == 1.0 - 2.0 ** -23
+
+
+@pytest.mark.parametrize("prec", [oracle.FP32, oracle.FP16S])
+@pytest.mark.parametrize("lower", [True, False])
+def test_binary32_accumulation_residual_sum(prec, lower):
+    """Two Jacobi-Richardson sweeps (n_j = 0): the second sweep's outer
+    residual of the coupled row is, in binary32 and CSR order,
+    ((2 - 2) - 1*1) - 2^-24 - 2^-24 = -1 (both subtractions are ties that
+    round to the even -1), so x = 2 + (-1) = 1 exactly; in binary64 the
+    residual is -(1 + 2^-23) and x = 1 - 2^-23."""
+    A, row = _tie_matrix(lower)
+    v = np.ones(4)
+    v[row] = 2.0
+    variant = F if lower else B
+    z = oracle.gs2_apply_lp(A, v, prec, variant, 2, 0, 1.0)
+    assert np.array_equal(z, np.ones(4)), z
+    z64 = oracle.gs2_apply(A, v, variant, 2, 0, 1.0)
+    assert z64[row] == 1.0 - 2.0 ** -23
