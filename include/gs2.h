@@ -42,14 +42,19 @@ extern "C" {
 #define GS2_ERR_FP16_RANGE (-7) /* scaled value outside binary16 range      */
 #define GS2_ERR_NO_LEVELS (-8)  /* trisolve on a handle built without levels */
 #define GS2_NOT_CONVERGED 1     /* maxit Arnoldi steps without reaching rtol */
-#define GS2_BREAKDOWN 2         /* singular Hessenberg (no usable direction) */
+#define GS2_BREAKDOWN_EXACT 2   /* exact breakdown: a Givens radius of zero, */
+                                /* the Hessenberg is singular and the step   */
+                                /* gives no usable direction.  (A happy      */
+                                /* breakdown, h_{j+1,j} ~ 0 with a nonzero   */
+                                /* radius, only ends the restart cycle.)     */
+#define GS2_BREAKDOWN GS2_BREAKDOWN_EXACT /* earlier name of the same code  */
 
 /* variant: which triangle the inner sweeps invert (Section 3 splitting) */
 #define GS2_FORWARD 0   /* M = D + wL                                      */
 #define GS2_BACKWARD 1  /* M = D + wU                                      */
 #define GS2_SYMMETRIC 2 /* forward half, then backward half, per sweep     */
 
-/* preconditioner storage / arithmetic precision (Section 9) */
+/* preconditioner storage / arithmetic precision (Section 10) */
 #define GS2_FP64 0        /* values and vectors float64                    */
 #define GS2_FP32 1        /* values and vectors float32                    */
 #define GS2_FP16_SCALED 2 /* values binary16 after diagonal scaling,       */
@@ -230,7 +235,7 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * Many independent systems of uneven sizes, each with nrhs right-hand sides,
  * solved by GS2-preconditioned GMRES in one persistent kernel launch replayed
  * from a HIP graph (the multiple right-hand sides of segregated systems,
- * Section 10, motivate it).  Every system uses the same GS2 parameters.
+ * Section 11, motivate it).  Every system uses the same GS2 parameters.
  */
 
 /*

@@ -331,7 +331,7 @@ int or_inner_residuals(int n, const int32_t *rp, const int32_t *ci, const double
 /* ------------------------------------------- reduced-precision preconditioner
  *
  * The paper runs the preconditioner in single precision while the Krylov
- * solver stays in double (Section 9).  Its GS2 code keeps D^{-1}L prescaled
+ * solver stays in double (Section 10).  Its GS2 code keeps D^{-1}L prescaled
  * (Section 6, two-stage Gauss-Seidel).  The reduced-precision forms here are
  * defined in symmetrically scaled variables, which GS2 is invariant under in
  * exact arithmetic:
@@ -824,7 +824,7 @@ int or_mtgs_sweep(int n, const int32_t *rp, const int32_t *ci, const double *va,
 /* ---------------------------------------------------------------------- CG
  *
  * Preconditioned conjugate gradients (the Krylov solver of the paper's
- * symmetric positive definite experiments, Sections 8 and 9) in the
+ * symmetric positive definite experiments, Sections 9 and 10) in the
  * textbook form:
  *   r = b - A x, z = M^{-1} r, p = z, rz = r.z
  *   repeat: q = A p, alpha = rz / p.q, x += alpha p, r -= alpha q,

@@ -1,6 +1,6 @@
 // Batched GS2-preconditioned GMRES for many independent systems of uneven
 // sizes, each with several right-hand sides (the segregated multiple-RHS
-// systems of Section 10 motivate it).
+// systems of Section 11 motivate it).
 //
 // One persistent kernel launch solves everything.  A work item is one system
 // together with a group of R right-hand sides, solved start to finish by a
@@ -807,7 +807,7 @@ __device__ __forceinline__ bool bcommit(BLds &L, int R, int m, int r, double *co
         return false;
     }
     if (rho == 0.0) {
-        L.status[r] = GS2_BREAKDOWN;
+        L.status[r] = GS2_BREAKDOWN_EXACT;
         return false;
     }
     const double cs = col[jc] / rho, sn = col[jc + 1] / rho;

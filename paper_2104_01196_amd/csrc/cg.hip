@@ -1,5 +1,5 @@
 // Preconditioned conjugate gradients in float64 (the Krylov solver of the
-// paper's symmetric positive definite experiments, Sections 8 and 9), for
+// paper's symmetric positive definite experiments, Sections 9 and 10), for
 // use with the symmetric GS2 (SGS2) preconditioner.  Textbook recurrences;
 // the recurrence residual decides when to stop, the true residual is then
 // checked and the iteration restarts from it if it has drifted.  Every

@@ -96,7 +96,7 @@ __device__ inline bool commit_column(GState *ls, double *__restrict__ H, double 
         return false;
     }
     if (rho == 0.0) {
-        ls->status = GS2_BREAKDOWN;
+        ls->status = GS2_BREAKDOWN_EXACT;
         return false;
     }
     const double c = col[jc] / rho, sn = col[jc + 1] / rho;

@@ -371,7 +371,7 @@ __global__ __launch_bounds__(WAVE) void k_givens(GState *__restrict__ st)
         return;
     }
     if (rho == 0.0) {
-        st->status = GS2_BREAKDOWN;
+        st->status = GS2_BREAKDOWN_EXACT;
         st->done = 1;
         st->kk = j;
         return;

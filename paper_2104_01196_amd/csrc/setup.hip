@@ -2,7 +2,7 @@
 // scaling vectors, split the scaled matrix into its strictly lower and upper
 // triangles in sliced-ELL layout and the requested precision, optionally
 // build level sets, and pick a lane-per-row schedule.  The paper notes that
-// GS2 needs no eigenvalue estimate and only this cheap setup (Section 11).
+// GS2 needs no eigenvalue estimate and only this cheap setup (Section 12).
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -693,7 +693,7 @@ const char *gs2_status_string(int status)
     case GS2_ERR_FP16_RANGE: return "scaled matrix value outside binary16 range";
     case GS2_ERR_NO_LEVELS: return "handle was built without level sets";
     case GS2_NOT_CONVERGED: return "not converged within maxit iterations";
-    case GS2_BREAKDOWN: return "GMRES breakdown (singular Hessenberg)";
+    case GS2_BREAKDOWN_EXACT: return "GMRES exact breakdown (singular Hessenberg)";
     default: return "unknown status";
     }
 }

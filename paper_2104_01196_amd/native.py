@@ -17,7 +17,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "gs2.h")
 
 OK, ERR_ARG, ERR_BAD_CSR, ERR_ZERO_DIAG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_FP16_RANGE, ERR_NO_LEVELS = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-NOT_CONVERGED, BREAKDOWN = 1, 2
+NOT_CONVERGED, BREAKDOWN_EXACT = 1, 2
+BREAKDOWN = BREAKDOWN_EXACT  # earlier name of the same code
 FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
 FP64, FP32, FP16_SCALED = 0, 1, 2
 PREC_NONE, PREC_GS2, PREC_JR, PREC_GS_TRISOLVE, PREC_MTGS = 0, 1, 2, 3, 4
@@ -218,7 +219,7 @@ def mtgs_apply(h: Handle, variant, damping, v, z, stream=None):
 def gmres_solve(A: DeviceCSR, b, x, restart=30, rtol=1e-8, maxit=10000, prec_kind=PREC_GS2, prec: Handle = None,
                 stream=None, raise_on_error=True) -> dict:
     """Returns the gs2_solve_info fields as a dict.  Hard errors raise;
-    GS2_NOT_CONVERGED / GS2_BREAKDOWN are reported in the dict."""
+    GS2_NOT_CONVERGED / GS2_BREAKDOWN_EXACT are reported in the dict."""
     import torch
 
     info = SolveInfo()

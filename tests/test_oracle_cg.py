@@ -73,7 +73,7 @@ def test_pcg_finite_termination_and_status():
 
 
 def test_pcg_reduced_precision_keeps_iterations():
-    """Single-precision SGS2 keeps the CG iteration count (Section 9)."""
+    """Single-precision SGS2 keeps the CG iteration count (Section 10)."""
     A = laplace3d(10)
     b = np.random.default_rng(4).standard_normal(A.n)
     its = [oracle.pcg(A, b, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=1, precision=p)[1]["iterations"]

@@ -2,7 +2,7 @@
 diagonally scaled FP16 storage with FP32 arithmetic).
 
 The paper fixes only that the preconditioner runs in single precision while
-the Krylov solver stays in double (Section 9).  The forms are defined in
+the Krylov solver stays in double (Section 10).  The forms are defined in
 symmetrically scaled variables (exact-arithmetic invariant); these tests pin
 (1) the binary16 rounding against numpy's IEEE conversion, (2) exactness on
 dyadic data where no rounding can occur, so the reduced forms must equal the
@@ -87,7 +87,7 @@ def test_fp16_range_error():
 
 def test_gmres_reduced_precision_reaches_tolerance():
     """The FP64 outer Krylov loop recovers full accuracy with an FP32 / FP16
-    preconditioner, with about the same iteration count (Section 9)."""
+    preconditioner, with about the same iteration count (Section 10)."""
     A = vardiff3d(10, seed=9)
     b = np.random.default_rng(3).standard_normal(A.n)
     its = {}
