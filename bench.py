@@ -1,27 +1,31 @@
 """Benchmark: GS2-preconditioned GMRES time to solution on one MI355X.
 
-Workload (default): 3D 7-point Dirichlet Laplacian on a 128^3 grid
-(n = 2,097,152, nnz = 14,581,760), CSR float64 in natural ordering,
-b = A x_true with x_true ~ N(0,1) from a fixed seed, x0 = 0.
-GMRES(50) to ||b - A x|| / ||b|| <= 1e-8, right-preconditioned by forward GS2
-with 2 outer sweeps and 1 inner Jacobi-Richardson sweep (damping 1.0).
+Workload (default, --config 4): the precision-form study on the 3D
+variable-coefficient diffusion problem, 192^3 cells (n = 7,077,888,
+nnz = 49,324,032), kappa log-uniform over [1e-2, 1e2], CSR float64 in
+natural ordering, b = A x_true with x_true ~ N(0,1) from a fixed seed,
+x0 = 0.  GMRES(50) to ||b - A x|| / ||b|| <= 1e-8, right-preconditioned by
+symmetric GS2 with 1 outer and 1 inner sweep (SGS2(1,1), damping 1.0, the
+paper's mixed-precision setting), preconditioner stored and computed in
+float64, float32 and diagonally scaled float16 (float32 arithmetic); the
+Krylov loop is float64 in every form.
 One "step" is one complete solve (the whole preconditioned Krylov path:
 setup excluded, done once before timing).  `value` is the mean time to
 solution of the float64-preconditioner solve over the timed steps (median and
 spread reported with it); the float32 and scaled-float16 preconditioner
-solves are timed the same way and reported next to it, each with the
+solves are timed the same way and reported under `forms`, each with its
+iteration count, its error against the float64 CPU oracle's solution (stored
+by tests/golden/make_oracle_solves.py, which calls only the oracle) and the
 algorithmic bandwidth of its sweep kernels from a profiled pass.
 
-Two further measurements print their own JSON line (not the default):
---config 4 times the precision forms (FP64 / FP32 / scaled-FP16 SGS2(1,1)
-preconditioner, GMRES(50)) on the 192^3 variable-coefficient diffusion
-problem; --config 5 times the batched persistent solver (512 uneven
-convection-diffusion systems x 4 right-hand sides, GS2(2,2), GMRES(20),
-FP32 and FP64 preconditioner) against the plain FP64 path that solves the
-2048 systems one gmres_solve at a time.
+--config 2 runs the same measurement on the 128^3 Laplacian with forward
+GS2(2 sweeps, 1 inner); --config 5 times the batched persistent solver (512
+uneven convection-diffusion systems x 4 right-hand sides, GS2(2,2),
+GMRES(20), FP32 and FP64 preconditioner) against the plain FP64 path that
+solves the 2048 systems one gmres_solve at a time.
 
---compare times GMRES(50) on the default workload with each preconditioner
-of the paper's comparison (GS2, SGS2, JR, exact level-scheduled GS/SGS,
+--compare times GMRES(50) on the 128^3 Laplacian with each preconditioner of
+the paper's comparison (GS2, SGS2, JR, exact level-scheduled GS/SGS,
 multicolor GS, none).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size N] [--config 2|4|5] [--compare]
@@ -46,11 +50,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=None, help="grid side (default: the configuration's)")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 4, 5],
-                    help="2: the benchmark workload (default); 4: precision forms on the 192^3 variable-coefficient "
-                         "problem; 5: batched form on 512 convection-diffusion systems x 4 right-hand sides")
+    ap.add_argument("--config", type=int, default=4, choices=[2, 4, 5],
+                    help="4: precision forms on the 192^3 variable-coefficient problem (default); 2: the 128^3 "
+                         "Laplacian; 5: batched form on 512 convection-diffusion systems x 4 right-hand sides")
     ap.add_argument("--compare", action="store_true",
-                    help="with --config 2: GMRES(50) with each preconditioner of the comparison (GS2, SGS2, JR, "
+                    help="GMRES(50) on the 128^3 Laplacian with each preconditioner of the comparison (GS2, SGS2, JR, "
                          "exact level-scheduled GS, multicolor GS) instead of the default measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true",
@@ -99,6 +103,57 @@ def stream_ceiling(torch, nbytes=1 << 31, reps=5):
     return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
+def oracle_reference(wname, x_true, np):
+    """The float64 oracle's solution of the workload and its iteration counts,
+    from the record tests/golden/make_oracle_solves.py writes (it calls only
+    the CPU oracle): x_oracle = x_true + the stored float32 difference.
+    (None, record or None) when the record or its array is missing or stale."""
+    import hashlib
+
+    rec_path = os.path.join(ROOT, "tests", "golden", f"{wname}_oracle.json")
+    if not os.path.exists(rec_path):
+        log(f"[bench] no oracle record {rec_path}: errors against the oracle reported as null")
+        return None, None
+    rec = json.load(open(rec_path))
+    f64 = rec["solves"]["fp64"]
+    dx_path = os.path.join(ROOT, "tests", "golden", f64["dx_file"])
+    if not os.path.exists(dx_path):
+        log(f"[bench] {dx_path} is missing (python tests/golden/make_oracle_solves.py {wname} writes it)")
+        return None, rec
+    raw = open(dx_path, "rb").read()
+    if hashlib.sha256(raw).hexdigest() != f64["dx_sha256"]:
+        log(f"[bench] {dx_path} does not match its record: errors against the oracle reported as null")
+        return None, rec
+    dx = np.load(dx_path)
+    return x_true + dx.astype(np.float64), rec
+
+
+def oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, gpu_iterations, np):
+    """The oracle (one host thread, as written) on a bounded sample of the
+    same float64 solve: its first 4 and first 12 Arnoldi steps, timed apart.
+    A step's cost is modelled as c0 + c1 (j + 1) (preconditioner and product,
+    plus one Gram-Schmidt pass per basis vector), fitted to the two samples
+    and summed over the GPU's steps (cycles of `restart` steps)."""
+    import oracle
+
+    k1, k2 = 4, 12
+    t = {}
+    for k in (k1, k2):
+        _, oi = oracle.gmres(A, b, restart=restart, rtol=rtol, maxit=k, prec="gs2", variant=pv, sweeps=psw, inner=pin)
+        t[k] = oi["seconds"]
+    # steps 0..k1-1 and k1..k2-1: mean (j + 1) is (k1 + 1) / 2 and (k1 + k2 + 1) / 2
+    m1, m2 = (k1 + 1) / 2.0, (k1 + k2 + 1) / 2.0
+    p1, p2 = t[k1] / k1, (t[k2] - t[k1]) / (k2 - k1)
+    c1 = max((p2 - p1) / (m2 - m1), 0.0)
+    c0 = p1 - c1 * m1
+    steps = [j % restart for j in range(gpu_iterations)]
+    total = sum(c0 + c1 * (j + 1) for j in steps)
+    return {"value": total, "unit": "s", "cores": 1, "kind": "oracle", "host": cpu_model(),
+            "sample": f"oracle float64 solve cut at its first {k1} and {k2} Arnoldi steps ({t[k1]:.1f} s, "
+                      f"{t[k2]:.1f} s); per-step cost c0 + c1 (j + 1) fitted to them (c0 {c0:.3f} s, c1 "
+                      f"{c1 * 1e3:.2f} ms) and summed over the GPU's {gpu_iterations} steps"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -141,6 +196,7 @@ def main():
     forms = [("fp64", g.FP64)] + ([] if args.no_forms else [("fp32", g.FP32), ("fp16_scaled", g.FP16_SCALED)])
     results = {}
     x = torch.zeros(A.n, dtype=torch.float64, device=dev)
+    x_or, orec = oracle_reference(wname, p["x_true"], np)
     xref = None
     prof = None
     prof_solve_s = None
@@ -150,6 +206,7 @@ def main():
         torch.cuda.synchronize()
         setup_s = time.time() - ts
         lanes = g.gs2_handle_query(h)["lanes_per_row"]
+        sched = g.gs2_handle_schedule(h)
         for _ in range(args.warmup):
             solve(h, x)
         torch.cuda.synchronize()
@@ -186,17 +243,34 @@ def main():
         results[name] = {"time_to_solution_s": dt, "median_s": float(np.median(each)), "min_s": min(each),
                          "max_s": max(each), "iterations": info["iterations"], "restarts": info["restarts"],
                          "converged": info["converged"], "relres_true": rel, "setup_s": setup_s, "lanes_per_row": lanes,
-                         "rel_err_vs_fp64_solution": float(np.linalg.norm(xs - xref) / np.linalg.norm(xref)),
+                         "schedule": sched,
+                         "rel_err_vs_oracle_fp64": (float(np.linalg.norm(xs - x_or) / np.linalg.norm(x_or))
+                                                    if x_or is not None else None),
+                         "oracle_iterations": (orec["solves"][name]["iterations"]
+                                               if orec and name in orec["solves"] else None),
+                         "rel_err_vs_fp64_gpu_solution": float(np.linalg.norm(xs - xref) / np.linalg.norm(xref)),
                          "rel_err_vs_x_true": float(np.linalg.norm(xs - p["x_true"]) / np.linalg.norm(p["x_true"]))}
-        if form_prof:  # the sweep kernels' algorithmic bandwidth in this form
-            results[name]["sweep_GBps"] = {
-                k: (r["bytes"] / r["launches"]) / ((r["ms"] / r["launches"]) * 1e-3) / 1e9
-                for k, r in form_prof.items() if k in ("gs2_inner", "gs2_resid", "gs2_first_jr") and r["bytes"]}
+        if form_prof:  # the sweep kernels' roofline in this form
+            sweep = {}
+            for k, r in form_prof.items():
+                if k not in ("gs2_inner", "gs2_resid", "gs2_first_jr") or not r["bytes"]:
+                    continue
+                ach = (r["bytes"] / r["launches"]) / ((r["ms"] / r["launches"]) * 1e-3) / 1e9
+                sweep[k] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBS, "avg_launch_us": r["ms"] / r["launches"] * 1e3,
+                            "algorithmic_bytes_per_launch": r["bytes"] / r["launches"],
+                            "traffic": traffic_of(k, wname, name)}
+            results[name]["sweep_roofline"] = sweep
+            apply_ms = sum(form_prof[k]["ms"] for k in sweep) / max(info["iterations"] * args.steps, 1)
+            results[name]["precond_us_per_apply"] = apply_ms * 1e3
             log(f"[bench] {name} sweep kernels: " + ", ".join(
-                f"{k} {v:.0f} GB/s ({100 * v / HBM_PEAK_GBS:.1f}%)" for k, v in results[name]["sweep_GBps"].items()))
+                f"{k} {v['achieved']:.0f} GB/s ({100 * v['frac']:.1f}%, {v['avg_launch_us']:.1f} us)"
+                for k, v in sweep.items()) + f"; preconditioner {apply_ms * 1e3:.1f} us per apply")
+        eo = results[name]["rel_err_vs_oracle_fp64"]
         log(f"[bench] {name}: {dt * 1e3:.2f} ms/solve (median {np.median(each) * 1e3:.2f}, spread "
-            f"{min(each) * 1e3:.2f}-{max(each) * 1e3:.2f}), its={info['iterations']}, relres={rel:.2e}, "
-            f"setup {setup_s:.2f}s, {lanes} lanes/row")
+            f"{min(each) * 1e3:.2f}-{max(each) * 1e3:.2f}), its={info['iterations']} (oracle "
+            f"{results[name]['oracle_iterations']}), relres={rel:.2e}, err vs oracle "
+            f"{'n/a' if eo is None else f'{eo:.2e}'}, setup {setup_s:.2f}s, schedule {sched}")
         del h
     head = results["fp64"]
 
@@ -211,14 +285,7 @@ def main():
         dom = max(prof, key=lambda k: prof[k]["ms"])
         r = prof[dom]
         ach = (r["bytes"] / r["launches"]) / ((r["ms"] / r["launches"]) * 1e-3) / 1e9
-        traffic = None
-        tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{wname}.json")
-        if os.path.exists(tf):
-            rec = json.load(open(tf))
-            if rec.get("source_sha256") == source_digest():
-                traffic = rec.get("hbm_bytes_per_launch")
-            else:
-                log(f"[bench] {tf} was measured on other kernel sources: traffic reported as null")
+        traffic = traffic_of(dom, wname, "fp64")
         ceiling = stream_ceiling(torch)
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
@@ -231,19 +298,9 @@ def main():
             f"{100 * ach / ceiling:.1f}% of the measured {ceiling:.0f} GB/s copy)")
 
     cpu = None
-    if not args.no_cpu_baseline and cfg == 2:
-        import oracle
-
-        nthreads = 1
-        sample_steps = restart
-        _, oi = oracle.gmres(A, b, restart=restart, rtol=rtol, maxit=sample_steps, prec="gs2",
-                             variant=pv, sweeps=psw, inner=pin)
-        per_step = oi["seconds"] / max(oi["iterations"], 1)
-        cpu = {"value": per_step * head["iterations"], "unit": "s", "cores": nthreads, "kind": "oracle",
-               "host": cpu_model(),
-               "sample": f"first GMRES(50) cycle ({oi['iterations']} Arnoldi steps, {oi['seconds']:.1f}s) of the "
-                         f"same float64 solve, extrapolated to the GPU's {head['iterations']} iterations"}
-        log(f"[bench] cpu oracle: {per_step:.3f} s/step -> {cpu['value']:.1f} s extrapolated")
+    if not args.no_cpu_baseline:
+        cpu = oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, head["iterations"], np)
+        log(f"[bench] cpu oracle: {cpu['value']:.1f} s extrapolated ({cpu['sample']})")
 
     out = {
         "metric": "GS2-GMRES time-to-solution (s) + sweep HBM GB/s, FP64 vs FP32/FP16 precond",
@@ -265,6 +322,22 @@ def main():
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
+
+
+def traffic_of(kernel, wname, form):
+    """HBM bytes per launch of a kernel from the counter record
+    profiles/traffic_<kernel>_<workload>[_<form>].json (FETCH_SIZE and
+    WRITE_SIZE runs, scaled by a copy kernel's calibration), or None when no
+    record exists or it was measured on other kernel sources."""
+    for tf in (os.path.join(ROOT, "profiles", f"traffic_{kernel}_{wname}_{form}.json"),
+               os.path.join(ROOT, "profiles", f"traffic_{kernel}_{wname}.json") if form == "fp64" else None):
+        if tf and os.path.exists(tf):
+            rec = json.load(open(tf))
+            if rec.get("source_sha256") == source_digest():
+                return rec.get("hbm_bytes_per_launch")
+            log(f"[bench] {tf} was measured on other kernel sources: traffic reported as null")
+            return None
+    return None
 
 
 def cpu_model():

@@ -48,6 +48,9 @@ extern "C" {
                                 /* breakdown, h_{j+1,j} ~ 0 with a nonzero   */
                                 /* radius, only ends the restart cycle.)     */
 #define GS2_BREAKDOWN GS2_BREAKDOWN_EXACT /* earlier name of the same code  */
+#define GS2_STAGNATED 3         /* gmres_solve: the true residual at the end */
+                                /* of a restart cycle has not halved over    */
+                                /* the last stagnation_cycles cycles         */
 
 /* variant: which triangle the inner sweeps invert (Section 3 splitting) */
 #define GS2_FORWARD 0   /* M = D + wL                                      */
@@ -103,7 +106,25 @@ typedef struct gs2_options {
                           /* team barrier before the item is abandoned with  */
                           /* GS2_ERR_HIP (0 = default, 30000; < 0 = no wait  */
                           /* at all, which forces that path, for tests)      */
+    int format;           /* storage of L and U for the GS2 / JR passes:     */
+                          /* GS2_FORMAT_AUTO (0, timed at setup), _SELL (1), */
+                          /* _DIA (2; GS2_ERR_ARG if the matrix does not     */
+                          /* qualify, see gs2_setup)                         */
+    int rows_per_lane;    /* diagonal layout: rows per lane R (vector width  */
+                          /* R x value bytes, 2..16): 0 = timed, else forced */
+    int lds_staging;      /* diagonal layout: stage the source vector in LDS */
+                          /* for offsets |col - row| <= 64: 0 = timed,       */
+                          /* 1 = off, 2 = on                                 */
+    int stagnation_cycles; /* gmres_solve with this handle: stop with        */
+                           /* GS2_STAGNATED when the true residual has not   */
+                           /* halved over this many restart cycles (0 =      */
+                           /* default 50, also without a handle; < 0 = never)*/
 } gs2_options;
+
+/* gs2_options.format */
+#define GS2_FORMAT_AUTO 0
+#define GS2_FORMAT_SELL 1 /* sliced ELL, K lanes per row, column indices   */
+#define GS2_FORMAT_DIA 2  /* diagonal-interleaved, no column indices       */
 
 typedef struct gs2_solve_info {
     int iterations; /* Arnoldi steps (preconditioner applications)          */
@@ -126,7 +147,11 @@ void gs2_default_options(gs2_options *opt);
  * parts Ah = S_l A S_r (S_r = |D|^-1/2, S_l = sign(D) S_r, unit diagonal),
  * stores them apart from A in a sliced-ELL layout in the chosen precision,
  * and allocates every temporary the applies need (they persist with the
- * handle).  sweeps >= 1 outer sweeps (n_t n_k of Fig. code:two-stage on one
+ * handle).  When each triangle has at most 32 distinct offsets col - row
+ * (stencil matrices in natural order), their stored diagonals hold at most
+ * 1.5x the entries, n <= 2^30 and blocks <= 1, a second, diagonal-
+ * interleaved copy is built and the passes use whichever layout the timing
+ * picks (gs2_handle_schedule).  sweeps >= 1 outer sweeps (n_t n_k of Fig. code:two-stage on one
  * GPU), inner >= 0 inner JR sweeps (inner = 0 is Jacobi-Richardson), damping
  * w in (0, 2) (Section 4, damping factor), variant GS2_FORWARD/BACKWARD/
  * SYMMETRIC, opt may be NULL.  A's arrays are only read during the call; the
@@ -190,7 +215,9 @@ int mtgs_apply(gs2_handle *h, int variant, double damping, const double *v, doub
  * captured once into a HIP graph (keyed by A, b, x, handle, kind, restart,
  * step count, rtol) and replayed (see gs2_graphs; not while gs2_profile is
  * on).  Returns GS2_OK,
- * GS2_NOT_CONVERGED (maxit reached), GS2_BREAKDOWN, or an error; `info`
+ * GS2_NOT_CONVERGED (maxit reached), GS2_BREAKDOWN_EXACT, GS2_STAGNATED (the
+ * true residual at the end of a restart cycle has not halved for the
+ * handle's stagnation_cycles cycles, 50 by default), or an error; `info`
  * (host, may be NULL) is filled in every case.
  */
 int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit, int prec_kind,
@@ -216,6 +243,20 @@ int gs2_graphs(int enable);
 int cg_solve(const gs2_csr *A, const double *b, double *x, double rtol, int maxit, int prec_kind, gs2_handle *prec,
              gs2_solve_info *info, void *stream);
 
+/*
+ * Inner-iteration diagnostic (Section 8, the convergence of the inner JR
+ * sweeps on their own): for the lower triangular system (wL + D) g = r with
+ * the handle's damping w, its stored L and precision, runs the inner
+ * iteration g_0 = D^{-1} r, g_{j+1} = D^{-1}(r - w L g_j) (with the handle's
+ * inner damping gamma, if not 1) and writes out[j] = ||r - (wL + D) g_j||_2 /
+ * ||r||_2 for j = 0 .. inner (host array of inner + 1 doubles).  r: device,
+ * n float64.  Uses the handle's work vectors (do not overlap with an apply
+ * on the same handle), allocates its partial sums and synchronises
+ * `stream`.  Errors: GS2_ERR_ARG (inner < 0, NULL pointers, a hybrid-block
+ * handle), GS2_ERR_NOMEM, GS2_ERR_HIP.
+ */
+int gs2_inner_residuals(gs2_handle *h, const double *r, int inner, double *out, void *stream);
+
 /* Free a handle (NULL is ignored).  Synchronises the device. */
 void gs2_destroy(gs2_handle *h);
 
@@ -229,6 +270,23 @@ const char *gs2_status_string(int status);
  */
 int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *nnz_u, int64_t *bytes_stored,
                      int *lanes_per_row, int *levels_l, int *levels_u);
+
+/*
+ * The schedule the setup chose for the GS2 / JR passes (host outputs, any
+ * may be NULL): format GS2_FORMAT_SELL or GS2_FORMAT_DIA; lanes_per_row of
+ * the sliced-ELL layout; rows_per_lane and vector_bytes (rows_per_lane x
+ * value bytes, the width of one value load) and lds_staging (0/1) of the
+ * diagonal layout (0 when it is not used); ndiag_l / ndiag_u, the diagonals
+ * of L and U (0 if the matrix does not qualify for the diagonal layout);
+ * tuned = 1 if the choice was timed (or taken from the process-wide cache of
+ * timed choices), 0 if it was forced or defaulted.  Candidates and timing:
+ * the sliced-ELL layout at K = 1, 2, 4, ... lanes per row, then the diagonal
+ * layout at every rows_per_lane whose load is 2 to 16 bytes, with and
+ * without LDS staging; each is timed on one inner pass over L plus one
+ * residual pass over L and U (Section 4 passes), the fastest kept.
+ */
+int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,
+                        int *lds_staging, int *ndiag_l, int *ndiag_u, int *tuned);
 
 /* --------------------------------------------------------------- batched
  *

@@ -186,6 +186,34 @@ constexpr double NT_TRIANGLES_BYTES = 150e6;
 int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *col, int64_t padded, uint16_t **off,
                       int *off_min, hipStream_t s);
 
+// One triangle in the diagonal-interleaved layout (chosen by the setup's
+// timing when the triangle has few distinct offsets col - row, as stencil
+// matrices in their natural ordering do).  Diagonal d holds, for every row
+// i, the value of entry (i, i + off[d]) (0 where the triangle has none or
+// the column falls outside the matrix).  Rows are grouped in blocks of 64 R
+// (one wavefront, R rows per lane): lane l of block b owns rows
+// b*64R + k*64 + l, k < R, and its R values of a diagonal are stored
+// contiguously at b*64R + l*R, so they arrive in one R * b_v byte load
+// while every gather x[row + off] of the wavefront reads 64 consecutive
+// elements.  No column indices are stored.
+constexpr int DIA_MAX = 32;   // most diagonals per triangle
+constexpr int DIA_HALO = 64;  // LDS staging covers offsets |off| <= DIA_HALO
+constexpr int DIA_THREADS = 256; // threads per workgroup of the passes on it
+struct Dia {
+    int ndiag = 0;
+    int R = 1;          // rows per lane
+    int64_t stride = 0; // entries per diagonal (rows padded to 64 R)
+    int64_t nnz = 0;    // real entries
+    int off[DIA_MAX] = {};
+    void *val = nullptr;
+    int val_bytes = 8;
+    int nt = 0; // stream the values with the non-temporal policy
+    double stored_bytes() const { return (double)ndiag * (double)stride * val_bytes; }
+};
+
+// The schedule the setup picked for the sweep kernels.
+enum : int { FMT_SELL = 0, FMT_DIA = 1 };
+
 struct GmresWork; // krylov.hip
 struct CgWork;    // cg.hip
 
@@ -195,8 +223,13 @@ struct Handle {
     double omega = 1.0, gamma = 1.0;
     int compact = 0;
     int orth = 0;        // GMRES orthogonalisation (0 delayed CGS2, 1 CGS2)
+    int stag_cycles = 0; // GMRES stagnation window in restart cycles (0 default, < 0 off)
     int block_waves = 4; // wavefronts per workgroup in the sweep kernels
     Sell L, U;
+    // diagonal-interleaved copies of L and U, used by the GS2 / JR passes
+    // when fmt == FMT_DIA (rows per lane dl.R, LDS staging if lds)
+    int fmt = FMT_SELL, lds = 0, tuned = 0;
+    Dia DL, DU;
     // hybrid relaxation: `blocks` contiguous row blocks; L and U then hold the
     // block-local triangles and E the couplings between blocks, applied to
     // values frozen once per global sweep (`local_sweeps` local sweeps each)
@@ -230,6 +263,7 @@ struct Handle {
 // setup.hip
 int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t s, bool alloc_vecs);
 void free_sell(Sell &S);
+void free_dia(Dia &D);
 int choose_lanes(double avg_len, int max_len);
 
 // sweep.hip
@@ -237,7 +271,8 @@ int apply_gs2(Handle &h, const double *v, double *z, hipStream_t s);
 int apply_jr(Handle &h, int sweeps, double omega, const double *v, double *z, hipStream_t s);
 int apply_trisolve(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s);
 int apply_mtgs(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s);
-int time_inner_pass(Handle &h, hipStream_t s, float *ms);
+int time_inner_pass(Handle &h, hipStream_t s, float *ms, bool with_resid = false);
+int inner_residuals(Handle &h, const double *r, int inner, double *out, hipStream_t s);
 
 // krylov.hip, cg.hip
 void free_gmres_work(GmresWork *w);

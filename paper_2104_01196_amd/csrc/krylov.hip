@@ -687,6 +687,11 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     double *Zb = W->Z;
     int total = 0, cycles = 0, status = GS2_OK;
     bool have_prev = false;
+    // stagnation: the true residual at the end of a cycle has not halved for
+    // `stag` consecutive cycles (0 = default 50; < 0 = no test)
+    const int stag = P ? (P->h.stag_cycles == 0 ? 50 : P->h.stag_cycles) : 50;
+    double ref_res = -1.0;
+    int ref_cycle = 0;
     // algorithmic bytes: SpMV with A (entries, slice pointers, z gathered once,
     // w written), and one pass over nk Krylov vectors
     const double spmv_b = 12.0 * (double)A.nnz + 8.0 * (W->A.nslices + 1) + 16.0 * n;
@@ -713,6 +718,13 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         if (!std::isfinite(beta)) { status = GS2_ERR_NONFINITE; break; }
         if (info->relres <= rtol) { info->converged = 1; break; }
         if (total >= maxit) { status = GS2_NOT_CONVERGED; break; }
+        if (ref_res < 0.0 || info->relres < 0.5 * ref_res) {
+            ref_res = info->relres;
+            ref_cycle = cycles;
+        } else if (stag > 0 && cycles - ref_cycle >= stag) {
+            status = GS2_STAGNATED;
+            break;
+        }
         if (cycles > 0) info->restarts++;
         cycles++;
         const int steps = std::min(m, maxit - total);

@@ -294,6 +294,113 @@ int build_col_offsets(int64_t nslices, int K, const int64_t *sp, const int32_t *
     return GS2_OK;
 }
 
+// ------------------------------------------- diagonal-interleaved triangles
+
+void free_dia(Dia &D)
+{
+    if (D.val) (void)hipFree(D.val);
+    D.val = nullptr;
+}
+
+struct DiaOffs {
+    int nd;
+    int off[DIA_MAX];
+};
+
+// Distinct offsets col - row of the strictly lower and upper parts, ascending,
+// and their entry counts, from a host copy of the pattern.  False when either
+// part has more than DIA_MAX offsets.  Columns are sorted within a row, so a
+// row's offsets ascend; each is looked up by binary search.
+static bool dia_offsets(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int64_t n,
+                        std::vector<int> &offL, std::vector<int> &offU, int64_t &nnzL, int64_t &nnzU)
+{
+    offL.clear();
+    offU.clear();
+    nnzL = nnzU = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int d = (int)((int64_t)ci[k] - i);
+            if (d == 0) continue;
+            std::vector<int> &o = d < 0 ? offL : offU;
+            (d < 0 ? nnzL : nnzU)++;
+            auto it = std::lower_bound(o.begin(), o.end(), d);
+            if (it == o.end() || *it != d) {
+                if ((int)o.size() == DIA_MAX) return false;
+                o.insert(it, d);
+            }
+        }
+    }
+    return true;
+}
+
+// One thread per row: the row's entries of one part go to their diagonal at
+// the row's interleaved position, value (s_l[i] * a_ij) * s_r[j] rounded once
+// to VT.  The array is zeroed beforehand (rows past n and absent entries).
+template <typename VT>
+__global__ void k_dia_fill(int64_t n, int R, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ va, const int32_t *__restrict__ lcnt, int lower, DiaOffs o,
+                           const double *__restrict__ sl, const double *__restrict__ sr, int64_t stride,
+                           VT *__restrict__ val, int *__restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t blk = (int64_t)WAVE * R;
+    const int64_t pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
+    const int64_t b = lower ? rp[i] : rp[i] + lcnt[i] + 1, e = lower ? rp[i] + lcnt[i] : rp[i + 1];
+    const double srow = sl[i];
+    int t = 0, ovf = 0;
+    for (int64_t k = b; k < e; ++k) {
+        const int c = ci[k];
+        const int d = (int)((int64_t)c - i);
+        while (t < o.nd - 1 && o.off[t] < d) ++t; // offsets ascend within a row
+        if (o.off[t] != d) {
+            atomicOr(err, ERRF_BAD_CSR); // cannot happen for a pattern the offsets came from
+            return;
+        }
+        val[(int64_t)t * stride + pos] = convert_scaled<VT>((srow * va[k]) * sr[c], &ovf);
+    }
+    if (ovf) atomicOr(err, ERRF_FP16);
+}
+
+// Build one triangle (lower or upper) in the diagonal-interleaved layout
+// with R rows per lane; rows are padded to whole workgroups of the sweep
+// kernels (DIA_THREADS * R rows) so that every launched lane has a slot.
+static int build_dia(Dia &D, int64_t n, int precision, int lower, int R, const std::vector<int> &offs, int64_t nnz,
+                     const gs2_csr &A, const int32_t *lcnt, const double *sl, const double *sr, int *err,
+                     hipStream_t s)
+{
+    free_dia(D);
+    D.ndiag = (int)offs.size();
+    D.R = R;
+    D.nnz = nnz;
+    D.val_bytes = precision == GS2_FP64 ? 8 : precision == GS2_FP32 ? 4 : 2;
+    const int64_t wg = (int64_t)DIA_THREADS * R;
+    D.stride = std::max<int64_t>(1, (n + wg - 1) / wg) * wg;
+    DiaOffs o;
+    o.nd = D.ndiag;
+    for (int d = 0; d < DIA_MAX; ++d) {
+        D.off[d] = d < D.ndiag ? offs[d] : 0;
+        o.off[d] = D.off[d];
+    }
+    const size_t bytes = (size_t)std::max(1, D.ndiag) * (size_t)D.stride * D.val_bytes;
+    GS2_TRY_HIP(hipMalloc(&D.val, bytes));
+    GS2_TRY_HIP(hipMemsetAsync(D.val, 0, bytes, s));
+    if (D.ndiag == 0 || n == 0) return GS2_OK;
+    const int tb = 256;
+    const unsigned g = (unsigned)((n + tb - 1) / tb);
+    if (precision == GS2_FP64)
+        k_dia_fill<double><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
+                                            (double *)D.val, err);
+    else if (precision == GS2_FP32)
+        k_dia_fill<float><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
+                                           (float *)D.val, err);
+    else
+        k_dia_fill<_Float16><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
+                                              (_Float16 *)D.val, err);
+    GS2_TRY_HIP(hipGetLastError());
+    return GS2_OK;
+}
+
 int choose_lanes(double avg_len, int max_len)
 {
     (void)max_len;
@@ -396,6 +503,114 @@ static int64_t count_total(const int32_t *tot, int64_t n, hipStream_t s, int *st
     int64_t c = 0;
     for (int32_t v : t) c += v;
     return c;
+}
+
+// Schedules of the diagonal layout chosen by timing, per (size bucket, mean
+// row length, longest-row bucket, precision, diagonal counts).
+struct DiaChoice {
+    int fmt, R, lds;
+};
+static std::map<std::string, DiaChoice> g_dia_cache;
+
+// Decide the layout of the GS2 / JR passes: keep the sliced-ELL triangles, or
+// build diagonal-interleaved copies (Dia) and time them against sliced ELL.
+static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, SetupScratch &sc, hipStream_t s,
+                         bool can_time, const std::string &key_base)
+{
+    h.fmt = FMT_SELL;
+    h.lds = 0;
+    h.tuned = 0;
+    if (o.format == GS2_FORMAT_SELL) return GS2_OK;
+    // the automatic choice is made by timing only; without it sliced ELL stays
+    if (o.format == GS2_FORMAT_AUTO && !(can_time && o.autotune)) return GS2_OK;
+    const int64_t n = h.n;
+    bool ok = h.blocks == 1 && n > 0 && n <= (int64_t(1) << 30);
+    std::vector<int> offL, offU;
+    int64_t nnzL = 0, nnzU = 0;
+    if (ok) {
+        std::vector<int32_t> rp(n + 1), ci(std::max<int64_t>(A.nnz, 1));
+        GS2_TRY_HIP(hipMemcpyAsync(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        if (A.nnz)
+            GS2_TRY_HIP(hipMemcpyAsync(ci.data(), A.colind, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, s));
+        GS2_TRY_HIP(hipStreamSynchronize(s));
+        ok = dia_offsets(rp, ci, n, offL, offU, nnzL, nnzU);
+        // stored diagonal entries (padding included) at most 1.5x the real ones
+        ok = ok && (double)offL.size() * n <= 1.5 * nnzL + 64.0 * offL.size() &&
+             (double)offU.size() * n <= 1.5 * nnzU + 64.0 * offU.size();
+    }
+    h.DL.ndiag = ok ? (int)offL.size() : 0;
+    h.DU.ndiag = ok ? (int)offU.size() : 0;
+    if (!ok) return o.format == GS2_FORMAT_DIA ? GS2_ERR_ARG : GS2_OK;
+    const int vb = h.precision == GS2_FP64 ? 8 : h.precision == GS2_FP32 ? 4 : 2;
+    std::vector<int> Rs, ldss;
+    for (int R = 1; R <= 8; R *= 2)
+        if (R * vb >= 2 && R * vb <= 16 && (o.rows_per_lane == 0 || o.rows_per_lane == R)) Rs.push_back(R);
+    if (Rs.empty()) return GS2_ERR_ARG; // a forced rows-per-lane whose load is not 2..16 bytes
+    if (o.lds_staging == 0) ldss = {0, 1};
+    else ldss = {o.lds_staging == 2 ? 1 : 0};
+    auto build = [&](int R) -> int {
+        GS2_TRY(build_dia(h.DL, n, h.precision, 1, R, offL, nnzL, A, sc.lcnt, h.sl, h.sr, sc.err, s));
+        GS2_TRY(build_dia(h.DU, n, h.precision, 0, R, offU, nnzU, A, sc.lcnt, h.sl, h.sr, sc.err, s));
+        h.DL.nt = h.DU.nt = h.DL.stored_bytes() + h.DU.stored_bytes() > NT_TRIANGLES_BYTES ? 1 : 0;
+        return GS2_OK;
+    };
+    const bool timed = can_time && o.autotune && (o.format == GS2_FORMAT_AUTO || Rs.size() > 1 || ldss.size() > 1);
+    if (!timed) {
+        if (o.format != GS2_FORMAT_DIA) return GS2_OK; // untimed automatic choice: sliced ELL
+        GS2_TRY(build(Rs.back()));                       // forced: the widest load allowed
+        h.fmt = FMT_DIA;
+        h.lds = ldss.back();
+        return GS2_OK;
+    }
+    char kb[48];
+    std::snprintf(kb, sizeof kb, "_d%d_%d_f%d_r%d_s%d", h.DL.ndiag, h.DU.ndiag, o.format, o.rows_per_lane,
+                  o.lds_staging);
+    const std::string key = key_base + kb;
+    DiaChoice ch{FMT_SELL, 0, 0};
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_dia_cache.find(key);
+        if (it != g_dia_cache.end()) {
+            ch = it->second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        float best = 1e30f;
+        if (o.format == GS2_FORMAT_AUTO) {
+            h.fmt = FMT_SELL;
+            GS2_TRY(time_inner_pass(h, s, &best, true));
+        }
+        for (int R : Rs) {
+            GS2_TRY(build(R));
+            for (int l : ldss) {
+                h.fmt = FMT_DIA;
+                h.lds = l;
+                float ms = 0.f;
+                GS2_TRY(time_inner_pass(h, s, &ms, true));
+                // a new candidate must win by more than the timing noise
+                if (ms < 0.97f * best) {
+                    best = ms;
+                    ch = DiaChoice{FMT_DIA, R, l};
+                }
+            }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_dia_cache[key] = ch;
+    }
+    h.tuned = 1;
+    if (ch.fmt == FMT_SELL) {
+        h.fmt = FMT_SELL;
+        h.lds = 0;
+        free_dia(h.DL);
+        free_dia(h.DU);
+        return GS2_OK;
+    }
+    if (!h.DL.val || h.DL.R != ch.R) GS2_TRY(build(ch.R));
+    h.fmt = FMT_DIA;
+    h.lds = ch.lds;
+    return GS2_OK;
 }
 
 static int read_err(int *err, hipStream_t s)
@@ -575,6 +790,7 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
     h.U.nnz = count_total(sc.R.tot, n, s, &cst);
     GS2_TRY(cst);
     h.L.nt = h.U.nt = h.L.stored_bytes() + h.U.stored_bytes() > NT_TRIANGLES_BYTES ? 1 : 0;
+    GS2_TRY(choose_format(h, A, o, sc, s, alloc_vecs && n >= 4096, tune_key(n, avg, maxlen, h.precision)));
     if (h.blocks > 1) {
         GS2_TRY(build_part(h, h.E, PART_E, K, A, sc, s));
         h.E.nnz = count_total(sc.R.tot, n, s, &cst);
@@ -596,6 +812,8 @@ Handle::~Handle()
     free_sell(L);
     free_sell(U);
     free_sell(E);
+    free_dia(DL);
+    free_dia(DU);
     for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, yh, (void *)lev_rows_l, (void *)lev_rows_u,
                     (void *)color_rows})
         if (p) (void)hipFree(p);
@@ -620,6 +838,10 @@ void gs2_default_options(gs2_options *opt)
     opt->local_sweeps = 1;
     opt->team_rows = 0;
     opt->team_wait_ms = 0;
+    opt->format = GS2_FORMAT_AUTO;
+    opt->rows_per_lane = 0;
+    opt->lds_staging = 0;
+    opt->stagnation_cycles = 0;
 }
 
 int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
@@ -641,6 +863,9 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
         (int64_t)o.blocks > std::max<int64_t>(A->n, 1))
         return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
+    if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_DIA || o.rows_per_lane < 0 || o.lds_staging < 0 ||
+        o.lds_staging > 2)
+        return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;
     if (!H) return GS2_ERR_NOMEM;
     Handle &h = H->h;
@@ -652,6 +877,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     h.gamma = o.inner_damping;
     h.compact = o.compact ? 1 : 0;
     h.orth = o.orthogonalization;
+    h.stag_cycles = o.stagnation_cycles;
     h.blocks = std::max(1, o.blocks);
     h.local_sweeps = std::max(1, o.local_sweeps);
     h.precision = o.precision;
@@ -694,6 +920,7 @@ const char *gs2_status_string(int status)
     case GS2_ERR_NO_LEVELS: return "handle was built without level sets";
     case GS2_NOT_CONVERGED: return "not converged within maxit iterations";
     case GS2_BREAKDOWN_EXACT: return "GMRES exact breakdown (singular Hessenberg)";
+    case GS2_STAGNATED: return "GMRES stagnated (true residual not halved over the stagnation window)";
     default: return "unknown status";
     }
 }
@@ -713,6 +940,23 @@ int gs2_handle_query(const gs2_handle *H, int64_t *n, int64_t *nnz_l, int64_t *n
     if (lanes_per_row) *lanes_per_row = h.L.K;
     if (levels_l) *levels_l = h.nlev_l;
     if (levels_u) *levels_u = h.nlev_u;
+    return GS2_OK;
+}
+
+int gs2_handle_schedule(const gs2_handle *H, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,
+                        int *lds_staging, int *ndiag_l, int *ndiag_u, int *tuned)
+{
+    if (!H) return GS2_ERR_ARG;
+    const Handle &h = H->h;
+    const bool dia = h.fmt == FMT_DIA;
+    if (format) *format = dia ? GS2_FORMAT_DIA : GS2_FORMAT_SELL;
+    if (lanes_per_row) *lanes_per_row = h.L.K;
+    if (rows_per_lane) *rows_per_lane = dia ? h.DL.R : 0;
+    if (vector_bytes) *vector_bytes = dia ? h.DL.R * h.DL.val_bytes : 0;
+    if (lds_staging) *lds_staging = dia ? h.lds : 0;
+    if (ndiag_l) *ndiag_l = h.DL.ndiag;
+    if (ndiag_u) *ndiag_u = h.DU.ndiag;
+    if (tuned) *tuned = h.tuned;
     return GS2_OK;
 }
 

@@ -12,6 +12,7 @@
 // half of an apply starts from xh = 0, so its residual is S_l v exactly and
 // needs no SpMV.  Every pass reads its triangle exactly once.
 #include <algorithm>
+#include <cmath>
 
 #include "dcgs_state.hpp"
 #include "gs2_internal.hpp"
@@ -130,7 +131,7 @@ __device__ __forceinline__ void slice_dots(const SellView T, int64_t s0, int64_t
 // sums and the solver state, nothing this pass touches, so the two overlap
 // (it is dispatched first, before the pass fills the machine) and the step
 // saves a launch.
-template <typename VT, typename AT, int K>
+template <typename VT, typename AT, int K, bool FIN>
 __global__ __launch_bounds__(KT) void k_inner(const int *__restrict__ stop, int64_t n, int64_t nslices, SellView T,
                                               const AT *__restrict__ rh, const AT *__restrict__ gin,
                                               const double *__restrict__ v, const double *__restrict__ sl, int rv,
@@ -140,13 +141,18 @@ __global__ __launch_bounds__(KT) void k_inner(const int *__restrict__ stop, int6
                                               int fnb, void *fst)
 {
     constexpr int SUN = su_of<AT>();
-    if (fst && blockIdx.x == 0) {
-        dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
-        return;
+    if constexpr (FIN) {
+        if (blockIdx.x == 0) {
+            dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+            return;
+        }
     }
+    // In a FIN launch the first workgroup may set the stop flag while the
+    // others read it; either value is correct: a pass that runs after the
+    // cycle has converged only writes vectors the cycle no longer reads.
     if (stop && *stop) return;
     const int lane = threadIdx.x & (WAVE - 1);
-    const unsigned sh = fst ? 1u : 0u;
+    const unsigned sh = FIN ? 1u : 0u;
     const int64_t s0 =
         (xcd_remap(blockIdx.x - sh, gridDim.x - sh) * (blockDim.x / WAVE) + threadIdx.x / WAVE) * SUN;
     if (s0 >= nslices) return;
@@ -211,19 +217,21 @@ __global__ __launch_bounds__(256) void k_resid(const int *__restrict__ stop, int
 // First half of JR from xh = 0: xh = w S_l v, or z = S_r w S_l v if final.
 // With fst, the first workgroup closes the previous GMRES step (as in
 // k_inner).
-template <typename AT>
+template <typename AT, bool FIN>
 __global__ __launch_bounds__(KT) void k_first_jr(const int *__restrict__ stop, int64_t n,
                                                  const double *__restrict__ v, const double *__restrict__ sl,
                                                  const double *__restrict__ sr, AT w, int final_, AT *__restrict__ xh,
                                                  double *__restrict__ z, const double *__restrict__ fpart, int fnb,
                                                  void *fst)
 {
-    if (fst && blockIdx.x == 0) {
-        dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
-        return;
+    if constexpr (FIN) {
+        if (blockIdx.x == 0) {
+            dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+            return;
+        }
     }
-    if (stop && *stop) return;
-    const int64_t i = (int64_t)(blockIdx.x - (fst ? 1u : 0u)) * blockDim.x + threadIdx.x;
+    if (stop && *stop) return; // may race with a FIN workgroup's write, harmlessly (as in k_inner)
+    const int64_t i = (int64_t)(blockIdx.x - (FIN ? 1u : 0u)) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const AT r = (AT)(v[i] * sl[i]);
     if (final_) z[i] = sr[i] * (double)(w * r);
@@ -322,6 +330,268 @@ __global__ void k_color(const int *__restrict__ stop, const int32_t *__restrict_
     x[i] = (AT(1) - w) * x[i] + w * ((AT)(v[i] * sl[i]) - acc);
 }
 
+// ------------------------------------------------ diagonal-interleaved passes
+//
+// The same passes on the diagonal-interleaved copies of the triangles (Dia in
+// gs2_internal.hpp).  A lane owns R rows, 64 apart, so every gather and every
+// per-row load or store of a wavefront covers 64 consecutive elements, and
+// the lane's R values of one diagonal arrive in a single R * sizeof(VT) byte
+// load.  No column index is loaded: the column of diagonal d is row + off[d],
+// clamped into [0, n) (a clamped column only ever meets a stored zero).
+// With LDS staging the workgroup first copies the source vector over its rows
+// plus DIA_HALO elements on each side into LDS, and the diagonals with
+// |off| <= DIA_HALO (the neighbours in the fastest grid direction) read from
+// there.
+
+// the FIN variants run the Krylov step's finish, written for KT threads
+static_assert(DIA_THREADS == KT, "one workgroup size for the diagonal passes and the step finish");
+
+struct DiaView {
+    int ndiag;
+    int nt;
+    int64_t stride;
+    const void *val;
+    int off[DIA_MAX];
+};
+
+static DiaView dview(const Dia &D)
+{
+    DiaView v;
+    v.ndiag = D.ndiag;
+    v.nt = D.nt;
+    v.stride = D.stride;
+    v.val = D.val;
+    for (int d = 0; d < DIA_MAX; ++d) v.off[d] = D.off[d];
+    return v;
+}
+
+template <int BYTES>
+struct RawVec;
+template <>
+struct RawVec<16> {
+    typedef unsigned int T __attribute__((ext_vector_type(4)));
+};
+template <>
+struct RawVec<8> {
+    typedef unsigned int T __attribute__((ext_vector_type(2)));
+};
+template <>
+struct RawVec<4> {
+    typedef unsigned int T;
+};
+template <>
+struct RawVec<2> {
+    typedef unsigned short T;
+};
+
+// The R values a lane holds on one diagonal, in one load.
+template <typename VT, typename AT, int R>
+__device__ __forceinline__ void dia_vals(const VT *__restrict__ p, int nt, AT (&a)[R])
+{
+    static_assert(R * sizeof(VT) >= 2 && R * sizeof(VT) <= 16, "one load of 2 to 16 bytes per lane");
+    using RV = typename RawVec<R * (int)sizeof(VT)>::T;
+    const RV raw = nt ? __builtin_nontemporal_load((const RV *)p) : *(const RV *)p;
+    VT t[R];
+    __builtin_memcpy(t, &raw, sizeof(t));
+#pragma unroll
+    for (int k = 0; k < R; ++k) a[k] = (AT)t[k];
+}
+
+__device__ __forceinline__ int clamp_col(int c, int n) { return c < 0 ? 0 : (c >= n ? n - 1 : c); }
+
+// acc[k] += sum_d T_d(row_k) * x(row_k + off_d) for row_k = rb + 64k; pos is
+// the lane's first value of diagonal 0.  src(c) loads the source at a column
+// c in [0, n); with LDS, xs holds the source over [base, base + span).
+// Columns need clamping only in the workgroups whose rows [w0, w0 + RB),
+// shifted by the offset, leave [0, n) (a uniform test per diagonal); the
+// others load at row + off directly, R loads 64 elements apart from one
+// address.
+template <typename VT, typename AT, int R, bool LDS, typename Src>
+__device__ __forceinline__ void dia_dots(const DiaView &T, int64_t pos, int w0, int rb, int n, Src src, const AT *xs,
+                                         int base, AT (&acc)[R])
+{
+    constexpr int RB = DIA_THREADS * R;
+    const VT *__restrict__ val = (const VT *)T.val;
+#pragma unroll 2
+    for (int d = 0; d < T.ndiag; ++d) {
+        AT a[R];
+        dia_vals<VT, AT, R>(val + (int64_t)d * T.stride + pos, T.nt, a);
+        const int o = T.off[d];
+        if (LDS && o >= -DIA_HALO && o <= DIA_HALO) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += a[k] * xs[rb + k * WAVE + o - base];
+        } else if (w0 + o >= 0 && w0 + RB + o <= n) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += a[k] * src(rb + o + k * WAVE);
+        } else {
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += a[k] * src(clamp_col(rb + k * WAVE + o, n));
+        }
+    }
+}
+
+// Copy src over [base, base + span) into xs (columns clamped into [0, n));
+// thread 0 also reads the stop flag, so that every wavefront of the workgroup
+// takes the same early exit after the barrier.  Returns the flag.
+template <typename AT, int SPAN, typename Src>
+__device__ __forceinline__ int dia_stage(AT *xs, int base, int n, Src src, const int *stop, int *sflag)
+{
+    for (int e = threadIdx.x; e < SPAN; e += DIA_THREADS) xs[e] = src(clamp_col(base + e, n));
+    if (threadIdx.x == 0) *sflag = stop ? *stop : 0;
+    __syncthreads();
+    return *sflag;
+}
+
+// Inner JR pass on a diagonal-interleaved triangle (as k_inner).  FIN: the
+// first workgroup closes the previous GMRES step instead (as in k_inner);
+// the other workgroups may then read the stop flag while that workgroup sets
+// it, and either value is correct: a pass that runs after the cycle has
+// converged only writes vectors the cycle no longer reads.
+template <typename VT, typename AT, int R, bool LDS, bool FIN>
+__global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict__ stop, int n, DiaView T,
+                                                  const AT *__restrict__ rh, const AT *__restrict__ gin,
+                                                  const double *__restrict__ v, const double *__restrict__ sl, int rv,
+                                                  int gv, int damp, AT w, AT gamma, int dst, AT *__restrict__ gout,
+                                                  AT *__restrict__ xh, double *__restrict__ z,
+                                                  const double *__restrict__ sr, const double *__restrict__ fpart,
+                                                  int fnb, void *fst)
+{
+    constexpr int RB = DIA_THREADS * R; // rows per workgroup
+    constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
+    if constexpr (FIN) {
+        if (blockIdx.x == 0) {
+            dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+            return;
+        }
+    }
+    const int sh = FIN ? 1 : 0;
+    const int wg = (int)xcd_remap(blockIdx.x - sh, gridDim.x - sh);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int w0 = wg * RB;
+    const int rb = w0 + wv * (WAVE * R) + lane;
+    const int64_t pos = (int64_t)w0 + wv * (WAVE * R) + lane * R;
+    auto sv = [&](int c) { return (AT)(v[c] * sl[c]); };
+    auto sg = [&](int c) { return gin[c]; };
+    AT acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = AT(0);
+    if constexpr (LDS) {
+        __shared__ AT xs[SPAN];
+        __shared__ int sflag;
+        const int base = w0 - DIA_HALO;
+        if (gv) {
+            if (dia_stage<AT, SPAN>(xs, base, n, sv, stop, &sflag)) return;
+            dia_dots<VT, AT, R, true>(T, pos, w0, rb, n, sv, xs, base, acc);
+        } else {
+            if (dia_stage<AT, SPAN>(xs, base, n, sg, stop, &sflag)) return;
+            dia_dots<VT, AT, R, true>(T, pos, w0, rb, n, sg, xs, base, acc);
+        }
+    } else {
+        if (stop && *stop) return;
+        if (gv) dia_dots<VT, AT, R, false>(T, pos, w0, rb, n, sv, nullptr, 0, acc);
+        else dia_dots<VT, AT, R, false>(T, pos, w0, rb, n, sg, nullptr, 0, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int row = rb + k * WAVE;
+        if (row >= n) break;
+        const AT r = rv ? (AT)(v[row] * sl[row]) : rh[row];
+        AT g = r - w * acc[k];
+        if (damp) {
+            const AT go = gv ? (AT)(v[row] * sl[row]) : gin[row];
+            g = (AT(1) - gamma) * go + gamma * g;
+        }
+        finish<AT>(dst, row, g, w, gout, xh, xh, z, sr);
+    }
+}
+
+// Outer residual pass on diagonal-interleaved triangles (as k_resid without
+// the hybrid term): rh = S_l v - cdiag xh - P xh [- Q xh].
+template <typename VT, typename AT, int R, bool LDS>
+__global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict__ stop, int n, DiaView P, DiaView Q, int two,
+                                                  const AT *__restrict__ xh, const double *__restrict__ v,
+                                                  const double *__restrict__ sl, AT cdiag, AT w, int dst,
+                                                  AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
+                                                  const double *__restrict__ sr)
+{
+    constexpr int RB = DIA_THREADS * R;
+    constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
+    const int wg = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int w0 = wg * RB;
+    const int rb = w0 + wv * (WAVE * R) + lane;
+    const int64_t pos = (int64_t)w0 + wv * (WAVE * R) + lane * R;
+    auto sx = [&](int c) { return xh[c]; };
+    AT acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = AT(0);
+    AT own[R];
+    if constexpr (LDS) {
+        __shared__ AT xs[SPAN];
+        __shared__ int sflag;
+        const int base = w0 - DIA_HALO;
+        if (dia_stage<AT, SPAN>(xs, base, n, sx, stop, &sflag)) return;
+        dia_dots<VT, AT, R, true>(P, pos, w0, rb, n, sx, xs, base, acc);
+        if (two) dia_dots<VT, AT, R, true>(Q, pos, w0, rb, n, sx, xs, base, acc);
+#pragma unroll
+        for (int k = 0; k < R; ++k) own[k] = xs[rb + k * WAVE - base];
+    } else {
+        if (stop && *stop) return;
+        dia_dots<VT, AT, R, false>(P, pos, w0, rb, n, sx, nullptr, 0, acc);
+        if (two) dia_dots<VT, AT, R, false>(Q, pos, w0, rb, n, sx, nullptr, 0, acc);
+#pragma unroll
+        for (int k = 0; k < R; ++k) own[k] = xh[clamp_col(rb + k * WAVE, n)];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int row = rb + k * WAVE;
+        if (row >= n) break;
+        const AT r = ((AT)(v[row] * sl[row]) - cdiag * own[k]) - acc[k];
+        finish<AT>(dst, row, r, w, rh, const_cast<AT *>(xh), xout, z, sr);
+    }
+}
+
+// ---------------------------------------- inner-iteration diagnostic (f1)
+//
+// Section 8 follows the inner JR iteration on its own: for a fixed r, the
+// relative residual ||r - (wL + D) g_j|| / ||r|| of the lower triangular
+// system after j inner steps.  In scaled space S_l (r - (wL + D) g) =
+// rh - (I + w Lh) gh = gh_{j+1} - gh_j, since gh_{j+1} = rh - w Lh gh_j: the
+// residual of step j is the change made by step j + 1, unscaled by 1/s_l.
+
+// part[blockIdx] = sum over the workgroup's rows of ((gnew - gold) / s_l)^2,
+// gold = AT(r s_l) when gold is null (step 0); with gnew null, the sum of
+// r^2 instead.  One partial per workgroup, summed later in a fixed order.
+template <typename AT>
+__global__ __launch_bounds__(KT) void k_diff_sums(int64_t n, const AT *__restrict__ gnew, const AT *__restrict__ gold,
+                                                  const double *__restrict__ r, const double *__restrict__ sl,
+                                                  double *__restrict__ part)
+{
+    __shared__ double red[KT / WAVE];
+    const int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x;
+    double t = 0.0;
+    if (i < n) {
+        if (!gnew) {
+            t = r[i] * r[i];
+        } else {
+            const double go = gold ? (double)gold[i] : (double)(AT)(r[i] * sl[i]);
+            const double d = ((double)gnew[i] - go) / sl[i];
+            t = d * d;
+        }
+    }
+    const double sblk = block_sum(t, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sblk;
+}
+
+// out[q] = sum of part[q * nb .. q * nb + nb) in a fixed order, q < nq.
+__global__ __launch_bounds__(KT) void k_sum_parts(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+    __shared__ double red[KT / WAVE];
+    const double t = strided_sum(part + (int64_t)blockIdx.x * nb, nb);
+    const double sblk = block_sum(t, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = sblk;
+}
+
 // ------------------------------------------------------------ host drivers
 
 constexpr int TB = KT; // 4 wavefronts per workgroup, one or two slices each
@@ -335,15 +605,91 @@ static inline unsigned grid_rows(int64_t n) { return (unsigned)std::max<int64_t>
 
 template <typename VT, typename AT>
 struct Launch {
+    // rows per lane of the diagonal-interleaved layout: one load of 2..16 bytes
+    template <int R>
+    static constexpr bool r_ok()
+    {
+        return R * sizeof(VT) >= 2 && R * sizeof(VT) <= 16;
+    }
+    static double dia_bytes(const Dia &D) { return (double)D.nnz * sizeof(VT); }
+    static const Dia &dia_of(const Handle &h, const Sell &T) { return &T == &h.L ? h.DL : h.DU; }
+
+    template <int R, bool LDS>
+    static void dia_inner_r(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
+                            int gv, int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
+    {
+        const int damp = h.gamma != 1.0;
+        const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R)) + (fj.st ? 1u : 0u);
+        if (fj.st)
+            k_dia_inner<VT, AT, R, LDS, true><<<grid, DIA_THREADS, 0, s>>>(h.stop, (int)h.n, dview(T), rh, gin, v, h.sl, rv,
+                                                                gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
+                                                                z, h.sr, fj.part, fj.nb, fj.st);
+        else
+            k_dia_inner<VT, AT, R, LDS, false><<<grid, DIA_THREADS, 0, s>>>(h.stop, (int)h.n, dview(T), rh, gin, v, h.sl, rv,
+                                                                 gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
+                                                                 z, h.sr, nullptr, 0, nullptr);
+    }
+    template <bool LDS>
+    static void dia_inner_l(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
+                            int gv, int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
+    {
+        switch (T.R) {
+        case 1:
+            if constexpr (r_ok<1>()) dia_inner_r<1, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            break;
+        case 2:
+            if constexpr (r_ok<2>()) dia_inner_r<2, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            break;
+        case 4:
+            if constexpr (r_ok<4>()) dia_inner_r<4, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            break;
+        default:
+            if constexpr (r_ok<8>()) dia_inner_r<8, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            break;
+        }
+    }
+    template <int R, bool LDS>
+    static void dia_resid_r(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
+                            AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
+    {
+        const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R));
+        k_dia_resid<VT, AT, R, LDS><<<grid, DIA_THREADS, 0, s>>>(h.stop, (int)h.n, dview(P), Q ? dview(*Q) : dview(P),
+                                                        Q ? 1 : 0, xh, v, h.sl, cdiag, w, dst, rh, xout, z, h.sr);
+    }
+    template <bool LDS>
+    static void dia_resid_l(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
+                            AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
+    {
+        switch (P.R) {
+        case 1:
+            if constexpr (r_ok<1>()) dia_resid_r<1, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            break;
+        case 2:
+            if constexpr (r_ok<2>()) dia_resid_r<2, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            break;
+        case 4:
+            if constexpr (r_ok<4>()) dia_resid_r<4, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            break;
+        default:
+            if constexpr (r_ok<8>()) dia_resid_r<8, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            break;
+        }
+    }
+
     template <int K>
     static void inner_k(const Handle &h, const Sell &T, const AT *rh, const AT *gin, const double *v, int rv, int gv,
                         int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
     {
         const int damp = h.gamma != 1.0;
         const unsigned grid = grid_for(T.nslices, su_of<AT>()) + (fj.st ? 1u : 0u);
-        k_inner<VT, AT, K><<<grid, TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv, gv, damp,
-                                               (AT)h.omega, (AT)h.gamma, dst, gout, xh, z, h.sr, fj.part, fj.nb,
-                                               fj.st);
+        if (fj.st)
+            k_inner<VT, AT, K, true><<<grid, TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv, gv,
+                                                         damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z, h.sr,
+                                                         fj.part, fj.nb, fj.st);
+        else
+            k_inner<VT, AT, K, false><<<grid, TB, 0, s>>>(h.stop, h.n, T.nslices, view(T), rh, gin, v, h.sl, rv,
+                                                          gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
+                                                          h.sr, nullptr, 0, nullptr);
     }
     // algorithmic bytes of one pass: each stored entry (value + column) and
     // each vector element read or written once; padding is not counted
@@ -368,6 +714,13 @@ struct Launch {
     {
         const double bx = sizeof(AT);
         const double src = gv ? 16.0 : rv ? 16.0 + bx : 2 * bx;
+        if (h.fmt == FMT_DIA) {
+            const Dia &D = dia_of(h, T);
+            Prof pr(s, PK_INNER, dia_bytes(D) + (double)h.n * (src + dst_bytes(dst)));
+            if (h.lds) dia_inner_l<true>(h, D, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            else dia_inner_l<false>(h, D, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            return;
+        }
         Prof pr(s, PK_INNER, tri_bytes(T) + (double)h.n * (src + dst_bytes(dst)));
         switch (T.K) {
         case 1: inner_k<1>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
@@ -392,6 +745,14 @@ struct Launch {
                       int dst, AT *rh, AT *xout, double *z, hipStream_t s, const AT *ye = nullptr)
     {
         const double out = (dst == DST_ZADD || dst == DST_ZSET) ? 16.0 : (double)sizeof(AT);
+        if (h.fmt == FMT_DIA && !ye) {
+            const Dia &DP = dia_of(h, P);
+            const Dia *DQ = Q ? &dia_of(h, *Q) : nullptr;
+            Prof pr(s, PK_RESID, dia_bytes(DP) + (DQ ? dia_bytes(*DQ) : 0.0) + (double)h.n * (16.0 + sizeof(AT) + out));
+            if (h.lds) dia_resid_l<true>(h, DP, DQ, xh, v, cdiag, w, dst, rh, xout, z, s);
+            else dia_resid_l<false>(h, DP, DQ, xh, v, cdiag, w, dst, rh, xout, z, s);
+            return;
+        }
         Prof pr(s, PK_RESID,
                 tri_bytes(P) + (Q ? tri_bytes(*Q) : 0.0) + (ye ? tri_bytes(h.E) + (double)h.n * sizeof(AT) : 0.0) +
                     (double)h.n * (16.0 + sizeof(AT) + out));
@@ -443,8 +804,12 @@ struct Launch {
                     if (h.inner == 0) {
                         if (xzero) {
                             Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (fin ? 16.0 : sizeof(AT))));
-                            k_first_jr<AT><<<grid_rows(h.n) + (fj.st ? 1u : 0u), TB, 0, s>>>(
-                                h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0, xc, z, fj.part, fj.nb, fj.st);
+                            if (fj.st)
+                                k_first_jr<AT, true><<<grid_rows(h.n) + 1u, TB, 0, s>>>(
+                                    h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0, xc, z, fj.part, fj.nb, fj.st);
+                            else
+                                k_first_jr<AT, false><<<grid_rows(h.n), TB, 0, s>>>(
+                                    h.stop, h.n, v, h.sl, h.sr, w, fin ? 1 : 0, xc, z, nullptr, 0, nullptr);
                             fj = Handle::FinJob{};
                         } else {
                             const int dst = fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
@@ -493,8 +858,12 @@ struct Launch {
             const Handle::FinJob fj = h.fin;
             h.fin = Handle::FinJob{};
             Prof pr(s, PK_FIRST_JR, (double)h.n * (16.0 + (total == 1 ? 16.0 : sizeof(AT))));
-            k_first_jr<AT><<<grid_rows(h.n) + (fj.st ? 1u : 0u), TB, 0, s>>>(
-                h.stop, h.n, v, h.sl, h.sr, w, total == 1 ? 1 : 0, xc, z, fj.part, fj.nb, fj.st);
+            if (fj.st)
+                k_first_jr<AT, true><<<grid_rows(h.n) + 1u, TB, 0, s>>>(
+                    h.stop, h.n, v, h.sl, h.sr, w, total == 1 ? 1 : 0, xc, z, fj.part, fj.nb, fj.st);
+            else
+                k_first_jr<AT, false><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, v, h.sl, h.sr, w,
+                                                                    total == 1 ? 1 : 0, xc, z, nullptr, 0, nullptr);
         }
         bool yzero = true;
         for (int step = 1; step < total; ++step) {
@@ -567,10 +936,48 @@ struct Launch {
         return GS2_OK;
     }
 
-    // Time of one inner pass over L: batches of back-to-back passes between
-    // one pair of events (timing-only events, no cache writeback), best of
-    // three batches after a warm-up batch.
-    static int time_inner(Handle &h, hipStream_t s, float *ms)
+    // The diagnostic of Section 8 for j = 0 .. inner with the handle's L,
+    // damping and precision: out (host, inner + 1 values).  Allocates its
+    // partial sums; synchronises the stream.
+    static int inner_residuals(Handle &h, const double *r, int nj, double *out, hipStream_t s)
+    {
+        const int nb = (int)((h.n + KT - 1) / KT);
+        const int nq = nj + 2; // quantities: steps 0..inner, then ||r||^2
+        double *part = nullptr, *sums = nullptr;
+        GS2_TRY_HIP(hipMalloc(&part, sizeof(double) * (size_t)nb * nq));
+        if (hipMalloc(&sums, sizeof(double) * nq) != hipSuccess) {
+            (void)hipFree(part);
+            return GS2_ERR_NOMEM;
+        }
+        AT *ga = (AT *)h.ga, *gb = (AT *)h.gb;
+        const AT *gold = nullptr;
+        for (int j = 0; j <= nj; ++j) {
+            AT *gnew = (j & 1) ? gb : ga; // gh_{j+1}
+            inner(h, h.L, nullptr, gold, r, 1, j == 0 ? 1 : 0, DST_G, gnew, nullptr, nullptr, s);
+            k_diff_sums<AT><<<nb, KT, 0, s>>>(h.n, gnew, gold, r, h.sl, part + (size_t)j * nb);
+            gold = gnew;
+        }
+        k_diff_sums<AT><<<nb, KT, 0, s>>>(h.n, nullptr, nullptr, r, h.sl, part + (size_t)(nj + 1) * nb);
+        k_sum_parts<<<nq, KT, 0, s>>>(part, nb, sums);
+        std::vector<double> hs(nq);
+        int st = GS2_OK;
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(hs.data(), sums, sizeof(double) * nq, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = GS2_ERR_HIP;
+        (void)hipFree(part);
+        (void)hipFree(sums);
+        if (st != GS2_OK) return st;
+        const double rn = std::sqrt(hs[nj + 1]);
+        for (int j = 0; j <= nj; ++j) out[j] = std::sqrt(hs[j]) / rn;
+        return GS2_OK;
+    }
+
+    // Time of one inner pass over L (and, with resid, one residual pass over
+    // both triangles): batches of back-to-back passes between one pair of
+    // events (timing-only events, no cache writeback), best of three batches
+    // after a warm-up batch.
+    static int time_inner(Handle &h, hipStream_t s, float *ms, bool with_resid)
     {
         constexpr int BATCH = 5;
         hipEvent_t e0, e1;
@@ -580,9 +987,13 @@ struct Launch {
         float best = 1e30f;
         for (int rep = 0; rep < 4; ++rep) {
             GS2_TRY_HIP(hipEventRecord(e0, s));
-            for (int b = 0; b < BATCH; ++b)
+            for (int b = 0; b < BATCH; ++b) {
                 inner(h, h.L, (const AT *)h.ga, (const AT *)h.ga, nullptr, 0, 0, DST_G, (AT *)h.gb, nullptr, nullptr,
                       s);
+                if (with_resid)
+                    resid(h, h.L, &h.U, (const AT *)h.ga, h.sl, AT(1), AT(1), DST_G, (AT *)h.rh, nullptr,
+                          nullptr, s);
+            }
             GS2_TRY_HIP(hipEventRecord(e1, s));
             GS2_TRY_HIP(hipEventSynchronize(e1));
             float t = 0.f;
@@ -629,9 +1040,14 @@ int apply_mtgs(Handle &h, int variant, double omega, const double *v, double *z,
     return st;
 }
 
-int time_inner_pass(Handle &h, hipStream_t s, float *ms)
+int inner_residuals(Handle &h, const double *r, int inner, double *out, hipStream_t s)
 {
-    int st = GS2_DISPATCH(h, time_inner(h, s, ms));
+    return GS2_DISPATCH(h, inner_residuals(h, r, inner, out, s));
+}
+
+int time_inner_pass(Handle &h, hipStream_t s, float *ms, bool with_resid)
+{
+    int st = GS2_DISPATCH(h, time_inner(h, s, ms, with_resid));
     GS2_TRY_HIP(hipGetLastError());
     return st;
 }
@@ -675,6 +1091,13 @@ int mtgs_apply(gs2_handle *H, int variant, double damping, const double *v, doub
     if (H->h.n == 0) return GS2_OK;
     if (H->h.ncolors == 0) return GS2_ERR_NO_LEVELS;
     return apply_mtgs(H->h, variant, damping, v, z, (hipStream_t)stream);
+}
+
+int gs2_inner_residuals(gs2_handle *H, const double *r, int inner, double *out, void *stream)
+{
+    if (!H || inner < 0 || !out || (H->h.n > 0 && !r)) return GS2_ERR_ARG;
+    if (H->h.n == 0 || H->h.blocks > 1) return H->h.n == 0 ? GS2_OK : GS2_ERR_ARG;
+    return inner_residuals(H->h, r, inner, out, (hipStream_t)stream);
 }
 
 } // extern "C"

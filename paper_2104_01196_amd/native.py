@@ -17,10 +17,12 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "gs2.h")
 
 OK, ERR_ARG, ERR_BAD_CSR, ERR_ZERO_DIAG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_FP16_RANGE, ERR_NO_LEVELS = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
-NOT_CONVERGED, BREAKDOWN_EXACT = 1, 2
+NOT_CONVERGED, BREAKDOWN_EXACT, STAGNATED = 1, 2, 3
 BREAKDOWN = BREAKDOWN_EXACT  # earlier name of the same code
 FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
 FP64, FP32, FP16_SCALED = 0, 1, 2
+FORMAT_AUTO, FORMAT_SELL, FORMAT_DIA = 0, 1, 2
+LDS_AUTO, LDS_OFF, LDS_ON = 0, 1, 2
 PREC_NONE, PREC_GS2, PREC_JR, PREC_GS_TRISOLVE, PREC_MTGS = 0, 1, 2, 3, 4
 
 
@@ -39,7 +41,9 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("inner_damping", C.c_double), ("compact", C.c_int),
                 ("build_levels", C.c_int), ("autotune", C.c_int), ("lanes_per_row", C.c_int),
                 ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int), ("blocks", C.c_int),
-                ("local_sweeps", C.c_int), ("team_rows", C.c_int), ("team_wait_ms", C.c_int)]
+                ("local_sweeps", C.c_int), ("team_rows", C.c_int), ("team_wait_ms", C.c_int),
+                ("format", C.c_int), ("rows_per_lane", C.c_int), ("lds_staging", C.c_int),
+                ("stagnation_cycles", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -77,6 +81,8 @@ def lib():
         i64p = C.POINTER(C.c_int64)
         ip = C.POINTER(C.c_int)
         L.gs2_handle_query.argtypes = [vp, i64p, i64p, i64p, i64p, ip, ip, ip]
+        L.gs2_handle_schedule.argtypes = [vp, ip, ip, ip, ip, ip, ip, ip, ip]
+        L.gs2_inner_residuals.argtypes = [vp, vp, i, C.POINTER(C.c_double), vp]
         L.gs2_profile.argtypes = [i]
         L.gs2_graphs.argtypes = [i]
         L.gs2_profile_kernel_count.argtypes = []
@@ -170,9 +176,11 @@ class Handle:
 
 def gs2_setup(A: DeviceCSR, sweeps=1, inner=1, damping=1.0, variant=FORWARD, precision=FP64, inner_damping=1.0,
               compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0, blocks=1,
-              local_sweeps=1, stream=None) -> Handle:
+              local_sweeps=1, format=FORMAT_AUTO, rows_per_lane=0, lds_staging=0, stagnation_cycles=0,
+              stream=None) -> Handle:
     opt = Options(precision, inner_damping, int(compact), int(build_levels), int(autotune), lanes_per_row, 0,
-                  orthogonalization, blocks, local_sweeps)
+                  orthogonalization, blocks, local_sweeps, 0, 0, format, rows_per_lane, lds_staging,
+                  stagnation_cycles)
     out = C.c_void_p()
     d = A.desc()
     st = lib().gs2_setup(C.byref(d), sweeps, inner, damping, variant, C.byref(opt), _stream(stream), C.byref(out))
@@ -219,7 +227,7 @@ def mtgs_apply(h: Handle, variant, damping, v, z, stream=None):
 def gmres_solve(A: DeviceCSR, b, x, restart=30, rtol=1e-8, maxit=10000, prec_kind=PREC_GS2, prec: Handle = None,
                 stream=None, raise_on_error=True) -> dict:
     """Returns the gs2_solve_info fields as a dict.  Hard errors raise;
-    GS2_NOT_CONVERGED / GS2_BREAKDOWN_EXACT are reported in the dict."""
+    GS2_NOT_CONVERGED / GS2_BREAKDOWN_EXACT / GS2_STAGNATED are reported in the dict."""
     import torch
 
     info = SolveInfo()
@@ -261,6 +269,27 @@ def gs2_handle_query(h: Handle) -> dict:
         raise Gs2Error(st, "gs2_handle_query")
     keys = ["n", "nnz_l", "nnz_u", "bytes_stored", "lanes_per_row", "levels_l", "levels_u"]
     return {k: x.value for k, x in zip(keys, v)}
+
+
+def gs2_handle_schedule(h: Handle) -> dict:
+    v = [C.c_int() for _ in range(8)]
+    st = lib().gs2_handle_schedule(h.ptr, *[C.byref(x) for x in v])
+    if st != OK:
+        raise Gs2Error(st, "gs2_handle_schedule")
+    keys = ["format", "lanes_per_row", "rows_per_lane", "vector_bytes", "lds_staging", "ndiag_l", "ndiag_u", "tuned"]
+    return {k: x.value for k, x in zip(keys, v)}
+
+
+def gs2_inner_residuals(h: Handle, r, inner: int, stream=None):
+    """||r - (wL + D) g_j|| / ||r|| for j = 0..inner (numpy array)."""
+    import numpy as np
+    import torch
+
+    out = (C.c_double * (inner + 1))()
+    st = lib().gs2_inner_residuals(h.ptr, _ptr(r, torch.float64, h.n, "r"), inner, out, _stream(stream))
+    if st != OK:
+        raise Gs2Error(st, "gs2_inner_residuals")
+    return np.array(out[:], dtype=np.float64)
 
 
 def gs2_profile(enable: bool):

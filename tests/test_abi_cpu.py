@@ -18,7 +18,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings_and_defaults():
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 1, 2):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 1, 2, 3):
         assert native.status_string(code) not in ("", "unknown status")
     assert native.status_string(12345) == "unknown status"
     o = native.Options()

@@ -1,0 +1,165 @@
+"""GPU parity of the diagonal-interleaved layout of the triangles (every rows-
+per-lane candidate, with and without LDS staging of the source vector)
+against the CPU oracle, through the C ABI.  Same bars as the sliced-ELL
+applies (tests/test_gpu_parity.py): 1e-12 per half sweep in float64 (the
+scaled-space kernels and the textbook oracle differ only in rounding
+order), 2e-5 / 1e-4 against the oracle's float32 / scaled-float16 forms
+(same stored values, different summation order), GMRES within one
+iteration of the oracle.
+
+The matrices span several workgroups with a ragged last one (a workgroup
+covers 256 R rows), and have offsets both inside the LDS halo (|col - row|
+<= 64) and beyond it."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_2104_01196_amd as g  # noqa: E402
+from gen import laplace3d, poisson2d, vardiff3d, convdiff2d, elasticity_q1, random_sparse, config_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+MATS = {
+    "laplace3d_17": lambda: laplace3d(17),        # offsets 1, 17 (staged) and 289 (not)
+    "vardiff3d_23": lambda: vardiff3d(23, seed=5),  # 12167 rows: several workgroups at every R, ragged
+    "poisson2d_45": lambda: poisson2d(45),        # 2025 rows: fewer than one workgroup at R >= 8
+    "convdiff_71": lambda: convdiff2d(71, 35.0, 2.2),  # nonsymmetric, offsets 1 and 71 (beyond the halo)
+}
+_cache = {}
+
+R_OF = {g.FP64: [1, 2], g.FP32: [1, 2, 4], g.FP16_SCALED: [1, 2, 4, 8]}
+TOL = {g.FP64: None, g.FP32: 2e-5, g.FP16_SCALED: 1e-4}
+
+
+def mat(name):
+    if name not in _cache:
+        A = MATS[name]()
+        _cache[name] = (A, g.DeviceCSR.from_host(A))
+    return _cache[name]
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel_inf(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def reference(A, v, prec, variant, sweeps, inner, w, gamma=1.0):
+    if prec == g.FP64:
+        return oracle.gs2_apply(A, v, variant, sweeps, inner, w, gamma)
+    return oracle.gs2_apply_lp(A, v, prec, variant, sweeps, inner, w)
+
+
+def schedules():
+    for prec, Rs in R_OF.items():
+        for R in Rs:
+            for lds in (g.LDS_OFF, g.LDS_ON):
+                yield prec, R, lds
+
+
+CASES = [(g.FORWARD, 2, 1, 1.0), (g.SYMMETRIC, 1, 2, 0.9), (g.BACKWARD, 1, 3, 0.8), (g.FORWARD, 3, 0, 0.7)]
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("prec,R,lds", list(schedules()))
+def test_dia_apply_every_schedule(name, prec, R, lds):
+    A, dA = mat(name)
+    v = np.random.default_rng(11).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    for variant, sweeps, inner, w in CASES:
+        h = g.gs2_setup(dA, sweeps, inner, w, variant, precision=prec, format=g.FORMAT_DIA, rows_per_lane=R,
+                        lds_staging=lds)
+        sch = g.gs2_handle_schedule(h)
+        assert (sch["format"], sch["rows_per_lane"], sch["lds_staging"]) == (g.FORMAT_DIA, R, lds == g.LDS_ON)
+        assert sch["vector_bytes"] == R * {g.FP64: 8, g.FP32: 4, g.FP16_SCALED: 2}[prec]
+        g.gs2_apply(h, dev(v), z)
+        ref = reference(A, v, prec, variant, sweeps, inner, w)
+        halves = sweeps * (2 if variant == g.SYMMETRIC else 1)
+        tol = TOL[prec] or 1e-12 * halves
+        assert rel_inf(host(z), ref) <= tol, (variant, sweeps, inner, w)
+
+
+@pytest.mark.parametrize("name", ["vardiff3d_23", "convdiff_71"])
+@pytest.mark.parametrize("lds", [g.LDS_OFF, g.LDS_ON])
+def test_dia_damping_compact_and_jr(name, lds):
+    """Inner damping gamma, the compact form and the JR entry point on the
+    diagonal layout (float64)."""
+    A, dA = mat(name)
+    v = np.random.default_rng(12).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    h = g.gs2_setup(dA, 2, 3, 0.9, g.SYMMETRIC, inner_damping=0.6, format=g.FORMAT_DIA, lds_staging=lds)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), oracle.gs2_apply(A, v, g.SYMMETRIC, 2, 3, 0.9, 0.6)) <= 4e-12
+    h = g.gs2_setup(dA, 2, 1, 0.8, g.FORWARD, compact=True, format=g.FORMAT_DIA, lds_staging=lds)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), oracle.gs2c_sweep(A, v, np.zeros(A.n), g.FORWARD, 2, 1, 0.8)) <= 4e-12
+    g.jr_apply(h, 3, 0.7, dev(v), z)
+    assert rel_inf(host(z), oracle.jr_sweep(A, v, np.zeros(A.n), 3, 0.7)) <= 3e-12
+
+
+@pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
+@pytest.mark.parametrize("lds", [g.LDS_OFF, g.LDS_ON])
+def test_dia_gmres_iterations(prec, lds):
+    """GMRES(30) with an SGS2(1,1) preconditioner on the diagonal layout: the
+    first preconditioner pass of each step also closes the previous step
+    (the fused variant of the pass)."""
+    A, dA = mat("vardiff3d_23")
+    b = np.random.default_rng(13).standard_normal(A.n)
+    _, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=1,
+                         precision=prec)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, precision=prec, format=g.FORMAT_DIA, lds_staging=lds)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 30, 1e-8, 5000, g.PREC_GS2, h)
+    assert info["converged"] and info["relres"] <= 1e-8
+    assert abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+
+
+def test_dia_eligibility():
+    """The diagonal layout is refused where it does not apply: too many
+    distinct offsets (3-dof elasticity), hybrid blocks, or a rows-per-lane
+    whose load would exceed 16 bytes; the automatic choice then keeps the
+    sliced-ELL layout."""
+    A = elasticity_q1(5, 5, 5, seed=4)
+    dA = g.DeviceCSR.from_host(A)
+    with pytest.raises(g.Gs2Error) as e:
+        g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD, format=g.FORMAT_DIA)
+    assert e.value.status == -1
+    sch = g.gs2_handle_schedule(g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD))
+    assert sch["format"] == g.FORMAT_SELL and sch["ndiag_l"] == 0
+    L, dL = mat("laplace3d_17")
+    with pytest.raises(g.Gs2Error):
+        g.gs2_setup(dL, 1, 1, 1.0, g.FORWARD, blocks=4, format=g.FORMAT_DIA)
+    with pytest.raises(g.Gs2Error):
+        g.gs2_setup(dL, 1, 1, 1.0, g.FORWARD, format=g.FORMAT_DIA, rows_per_lane=4)  # 32-byte float64 load
+    sch = g.gs2_handle_schedule(g.gs2_setup(dL, 1, 1, 1.0, g.FORWARD, format=g.FORMAT_SELL))
+    assert sch["format"] == g.FORMAT_SELL and sch["ndiag_l"] == 0
+    R = random_sparse(500, seed=3, avg_offdiag=6)
+    sch = g.gs2_handle_schedule(g.gs2_setup(g.DeviceCSR.from_host(R), 1, 1, 1.0, g.FORWARD))
+    assert sch["format"] == g.FORMAT_SELL
+
+
+@pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
+def test_tuned_schedule_matches_oracle(prec):
+    """The timed choice (automatic format, rows per lane and staging) on a
+    stencil matrix of 35,937 rows: reported as tuned, and its apply matches
+    the oracle whichever candidate won."""
+    A = laplace3d(33)
+    dA = g.DeviceCSR.from_host(A)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, precision=prec)
+    sch = g.gs2_handle_schedule(h)
+    assert sch["tuned"] == 1 and sch["ndiag_l"] == 3 and sch["ndiag_u"] == 3
+    v = np.random.default_rng(14).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), reference(A, v, prec, g.SYMMETRIC, 1, 1, 1.0)) <= (TOL[prec] or 2e-12)
+    print(f"tuned schedule ({prec}): {sch}")
