@@ -41,6 +41,8 @@ extern "C" {
 #define GS2_ERR_HIP (-6)        /* a HIP runtime call failed                */
 #define GS2_ERR_FP16_RANGE (-7) /* scaled value outside binary16 range      */
 #define GS2_ERR_NO_LEVELS (-8)  /* trisolve on a handle built without levels */
+#define GS2_ERR_SCRATCH (-9)    /* input larger than the fixed scratch of an */
+                                /* allocation-free entry point               */
 #define GS2_NOT_CONVERGED 1     /* maxit Arnoldi steps without reaching rtol */
 #define GS2_BREAKDOWN_EXACT 2   /* exact breakdown: a Givens radius of zero, */
                                 /* the Hessenberg is singular and the step   */
@@ -256,6 +258,29 @@ int cg_solve(const gs2_csr *A, const double *b, double *x, double rtol, int maxi
  * handle), GS2_ERR_NOMEM, GS2_ERR_HIP.
  */
 int gs2_inner_residuals(gs2_handle *h, const double *r, int inner, double *out, void *stream);
+
+/*
+ * Allocation-free variant of gs2_inner_residuals, for callers that cannot
+ * allocate device memory or synchronise (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same quantities, same
+ * kernels, bitwise the same values; out is a DEVICE array of inner + 1
+ * doubles, written asynchronously on `stream` (no host synchronisation).
+ * The per-workgroup partial sums live in a fixed device array of
+ * GS2_NOALLOC_SCRATCH_DOUBLES doubles (4 MiB) that the library holds on each
+ * device it runs on until the process ends; its address is resolved once
+ * per device (at the first gs2_setup there, else at the first call).  Limit:
+ * (ceil(n / 256) + 1) * (inner + 2) <= GS2_NOALLOC_SCRATCH_DOUBLES, else
+ * GS2_ERR_SCRATCH and nothing is enqueued (n up to 33.5 M rows at inner = 2,
+ * 7.4 M at inner = 16).
+ * Every call on one device shares that array (nothing in it needs to start
+ * at zero: each call writes every slot before reading it), so calls that
+ * overlap on one device -- on different streams or threads -- race and must
+ * be serialised by the caller.  Also uses the handle's work vectors, like
+ * gs2_inner_residuals.  Records nothing in the profiler.  Errors:
+ * GS2_ERR_ARG, GS2_ERR_SCRATCH, GS2_ERR_HIP.
+ */
+#define GS2_NOALLOC_SCRATCH_DOUBLES 524288
+int gs2_inner_residuals_noalloc(gs2_handle *h, const double *r, int inner, double *out, void *stream);
 
 /* Free a handle (NULL is ignored).  Synchronises the device. */
 void gs2_destroy(gs2_handle *h);

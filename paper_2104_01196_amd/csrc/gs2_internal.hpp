@@ -273,6 +273,9 @@ int apply_trisolve(Handle &h, int variant, double omega, const double *v, double
 int apply_mtgs(Handle &h, int variant, double omega, const double *v, double *z, hipStream_t s);
 int time_inner_pass(Handle &h, hipStream_t s, float *ms, bool with_resid = false);
 int inner_residuals(Handle &h, const double *r, int inner, double *out, hipStream_t s);
+// device address of the allocation-free entry point's fixed scratch on the
+// current device (resolved once per device)
+int noalloc_scratch(double **ptr);
 
 // krylov.hip, cg.hip
 void free_gmres_work(GmresWork *w);
@@ -286,6 +289,12 @@ enum ProfKid : int {
     PK_SCALE, PK_UPDATE_X, PK_BATCHED, PK_MISC
 };
 bool prof_on();
+// While one lives, the calling thread's launches are not recorded (the
+// allocation-free entry points: recording creates events).
+struct ProfPause {
+    ProfPause();
+    ~ProfPause();
+};
 void prof_begin(hipStream_t s, int kid, double bytes);
 void prof_end(hipStream_t s);
 void prof_set_step(int cycle, int step);

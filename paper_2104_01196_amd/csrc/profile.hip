@@ -44,7 +44,12 @@ static hipEvent_t get_event()
     return e;
 }
 
-bool prof_on() { return g_on; }
+// calls made under ProfPause on this thread record nothing
+static thread_local int g_paused = 0;
+ProfPause::ProfPause() { ++g_paused; }
+ProfPause::~ProfPause() { --g_paused; }
+
+bool prof_on() { return g_on && g_paused == 0; }
 
 void prof_begin(hipStream_t s, int kid, double bytes)
 {

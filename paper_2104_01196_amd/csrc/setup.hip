@@ -882,6 +882,9 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     h.local_sweeps = std::max(1, o.local_sweeps);
     h.precision = o.precision;
     hipStream_t s = (hipStream_t)stream;
+    // resolve the allocation-free entry point's scratch on this device now
+    // (cached per device; should it fail, that entry point reports it)
+    (void)noalloc_scratch(nullptr);
     int st = GS2_ERR_HIP;
     try {
         st = setup_handle(h, *A, o, s, true);
@@ -918,6 +921,7 @@ const char *gs2_status_string(int status)
     case GS2_ERR_HIP: return "HIP runtime error";
     case GS2_ERR_FP16_RANGE: return "scaled matrix value outside binary16 range";
     case GS2_ERR_NO_LEVELS: return "handle was built without level sets";
+    case GS2_ERR_SCRATCH: return "input exceeds the fixed scratch of the allocation-free entry point";
     case GS2_NOT_CONVERGED: return "not converged within maxit iterations";
     case GS2_BREAKDOWN_EXACT: return "GMRES exact breakdown (singular Hessenberg)";
     case GS2_STAGNATED: return "GMRES stagnated (true residual not halved over the stagnation window)";

@@ -592,6 +592,13 @@ __global__ __launch_bounds__(KT) void k_sum_parts(const double *__restrict__ par
     if (threadIdx.x == 0) out[blockIdx.x] = sblk;
 }
 
+// out[j] = sqrt(sums[j]) / sqrt(sums[nq - 1]) for j < nq - 1.
+__global__ void k_ratios(const double *__restrict__ sums, int nq, double *__restrict__ out)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j < nq - 1) out[j] = sqrt(sums[j]) / sqrt(sums[nq - 1]);
+}
+
 // ------------------------------------------------------------ host drivers
 
 constexpr int TB = KT; // 4 wavefronts per workgroup, one or two slices each
@@ -937,18 +944,15 @@ struct Launch {
     }
 
     // The diagnostic of Section 8 for j = 0 .. inner with the handle's L,
-    // damping and precision: out (host, inner + 1 values).  Allocates its
-    // partial sums; synchronises the stream.
-    static int inner_residuals(Handle &h, const double *r, int nj, double *out, hipStream_t s)
+    // damping and precision, enqueued on s: per-workgroup partial sums in
+    // part (nb * (inner + 2) doubles, nb = ceil(n / KT)), their totals in sums
+    // (inner + 2), the ratios in out (device, inner + 1).  Every slot of part
+    // and sums is written before it is read, so neither needs clearing.
+    static int inner_residuals_enqueue(Handle &h, const double *r, int nj, double *part, double *sums,
+                                       double *out, hipStream_t s)
     {
         const int nb = (int)((h.n + KT - 1) / KT);
         const int nq = nj + 2; // quantities: steps 0..inner, then ||r||^2
-        double *part = nullptr, *sums = nullptr;
-        GS2_TRY_HIP(hipMalloc(&part, sizeof(double) * (size_t)nb * nq));
-        if (hipMalloc(&sums, sizeof(double) * nq) != hipSuccess) {
-            (void)hipFree(part);
-            return GS2_ERR_NOMEM;
-        }
         AT *ga = (AT *)h.ga, *gb = (AT *)h.gb;
         const AT *gold = nullptr;
         for (int j = 0; j <= nj; ++j) {
@@ -959,18 +963,31 @@ struct Launch {
         }
         k_diff_sums<AT><<<nb, KT, 0, s>>>(h.n, nullptr, nullptr, r, h.sl, part + (size_t)(nj + 1) * nb);
         k_sum_parts<<<nq, KT, 0, s>>>(part, nb, sums);
-        std::vector<double> hs(nq);
-        int st = GS2_OK;
-        if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(hs.data(), sums, sizeof(double) * nq, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+        k_ratios<<<(unsigned)((nq + KT - 1) / KT), KT, 0, s>>>(sums, nq, out);
+        GS2_TRY_HIP(hipGetLastError());
+        return GS2_OK;
+    }
+
+    // The same with its own temporaries (allocated and freed here); out is a
+    // host array.  Synchronises the stream.
+    static int inner_residuals(Handle &h, const double *r, int nj, double *out, hipStream_t s)
+    {
+        const int nb = (int)((h.n + KT - 1) / KT);
+        const int nq = nj + 2;
+        double *part = nullptr, *sums = nullptr;
+        GS2_TRY_HIP(hipMalloc(&part, sizeof(double) * (size_t)nb * nq));
+        if (hipMalloc(&sums, sizeof(double) * (2 * nq - 1)) != hipSuccess) {
+            (void)hipFree(part);
+            return GS2_ERR_NOMEM;
+        }
+        int st = inner_residuals_enqueue(h, r, nj, part, sums, sums + nq, s);
+        if (st == GS2_OK && (hipMemcpyAsync(out, sums + nq, sizeof(double) * (nj + 1), hipMemcpyDeviceToHost, s) !=
+                                 hipSuccess ||
+                             hipStreamSynchronize(s) != hipSuccess))
             st = GS2_ERR_HIP;
         (void)hipFree(part);
         (void)hipFree(sums);
-        if (st != GS2_OK) return st;
-        const double rn = std::sqrt(hs[nj + 1]);
-        for (int j = 0; j <= nj; ++j) out[j] = std::sqrt(hs[j]) / rn;
-        return GS2_OK;
+        return st;
     }
 
     // Time of one inner pass over L (and, with resid, one residual pass over
@@ -1045,6 +1062,37 @@ int inner_residuals(Handle &h, const double *r, int inner, double *out, hipStrea
     return GS2_DISPATCH(h, inner_residuals(h, r, inner, out, s));
 }
 
+// --------------------------------- fixed scratch of the allocation-free entry
+//
+// The allocation-free diagnostic keeps its partial sums in this array: one
+// copy per device, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address resolved once per device by
+// noalloc_scratch().
+static __device__ __align__(256) double scratch[GS2_NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (resolved on the first
+// call per device, with that device current).
+int noalloc_scratch(double **ptr)
+{
+    int dev = 0;
+    GS2_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return GS2_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        GS2_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return GS2_ERR_HIP;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    if (ptr) *ptr = g_scratch_ptr[dev];
+    return GS2_OK;
+}
+
 int time_inner_pass(Handle &h, hipStream_t s, float *ms, bool with_resid)
 {
     int st = GS2_DISPATCH(h, time_inner(h, s, ms, with_resid));
@@ -1098,6 +1146,20 @@ int gs2_inner_residuals(gs2_handle *H, const double *r, int inner, double *out, 
     if (!H || inner < 0 || !out || (H->h.n > 0 && !r)) return GS2_ERR_ARG;
     if (H->h.n == 0 || H->h.blocks > 1) return H->h.n == 0 ? GS2_OK : GS2_ERR_ARG;
     return inner_residuals(H->h, r, inner, out, (hipStream_t)stream);
+}
+
+int gs2_inner_residuals_noalloc(gs2_handle *H, const double *r, int inner, double *out, void *stream)
+{
+    if (!H || inner < 0 || !out || (H->h.n > 0 && !r)) return GS2_ERR_ARG;
+    if (H->h.n == 0 || H->h.blocks > 1) return H->h.n == 0 ? GS2_OK : GS2_ERR_ARG;
+    const int64_t nb = (H->h.n + KT - 1) / KT, nq = (int64_t)inner + 2;
+    if (nb * nq + nq > GS2_NOALLOC_SCRATCH_DOUBLES) return GS2_ERR_SCRATCH;
+    double *part = nullptr;
+    GS2_TRY(noalloc_scratch(&part));
+    ProfPause quiet; // the profiler's event records would allocate
+    Handle &h = H->h;
+    const hipStream_t s = (hipStream_t)stream;
+    return GS2_DISPATCH(h, inner_residuals_enqueue(h, r, inner, part, part + nb * nq, out, s));
 }
 
 } // extern "C"

@@ -17,6 +17,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "gs2.h")
 
 OK, ERR_ARG, ERR_BAD_CSR, ERR_ZERO_DIAG, ERR_NONFINITE, ERR_NOMEM, ERR_HIP, ERR_FP16_RANGE, ERR_NO_LEVELS = (
     0, -1, -2, -3, -4, -5, -6, -7, -8)
+ERR_SCRATCH = -9
+NOALLOC_SCRATCH_DOUBLES = 524288  # fixed scratch of the allocation-free entry point (doubles per device)
 NOT_CONVERGED, BREAKDOWN_EXACT, STAGNATED = 1, 2, 3
 BREAKDOWN = BREAKDOWN_EXACT  # earlier name of the same code
 FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
@@ -83,6 +85,7 @@ def lib():
         L.gs2_handle_query.argtypes = [vp, i64p, i64p, i64p, i64p, ip, ip, ip]
         L.gs2_handle_schedule.argtypes = [vp, ip, ip, ip, ip, ip, ip, ip, ip]
         L.gs2_inner_residuals.argtypes = [vp, vp, i, C.POINTER(C.c_double), vp]
+        L.gs2_inner_residuals_noalloc.argtypes = [vp, vp, i, vp, vp]
         L.gs2_profile.argtypes = [i]
         L.gs2_graphs.argtypes = [i]
         L.gs2_profile_kernel_count.argtypes = []
@@ -290,6 +293,18 @@ def gs2_inner_residuals(h: Handle, r, inner: int, stream=None):
     if st != OK:
         raise Gs2Error(st, "gs2_inner_residuals")
     return np.array(out[:], dtype=np.float64)
+
+
+def gs2_inner_residuals_noalloc(h: Handle, r, inner: int, out, stream=None):
+    """The allocation-free variant: writes the inner + 1 ratios into the
+    float64 GPU tensor `out` on the stream, without allocating or
+    synchronising (partial sums in the library's fixed per-device scratch)."""
+    import torch
+
+    st = lib().gs2_inner_residuals_noalloc(h.ptr, _ptr(r, torch.float64, h.n, "r"), inner,
+                                           _ptr(out, torch.float64, inner + 1, "out"), _stream(stream))
+    if st != OK:
+        raise Gs2Error(st, "gs2_inner_residuals_noalloc")
 
 
 def gs2_profile(enable: bool):
