@@ -128,6 +128,21 @@ def oracle_reference(wname, x_true, np):
     return x_true + dx.astype(np.float64), rec
 
 
+def oracle_sampled_error(rec, xs, np):
+    """||x - x_oracle|| / ||x_oracle|| over the seeded sample of solution
+    entries the oracle record stores (its float64 values, written by the
+    oracle-only script), or None without a record."""
+    if not rec:
+        return None
+    f64 = rec["solves"]["fp64"]
+    if "sample_values" not in f64:
+        return None
+    rng = np.random.default_rng(rec["sample_seed"])
+    idx = np.sort(rng.choice(len(xs), size=min(rec["nsample"], len(xs)), replace=False))
+    xo = np.asarray(f64["sample_values"])
+    return {"value": float(np.linalg.norm(xs[idx] - xo) / np.linalg.norm(xo)), "entries": int(len(idx))}
+
+
 def oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, gpu_iterations, np):
     """The oracle (one host thread, as written) on a bounded sample of the
     same float64 solve: its first 4 and first 12 Arnoldi steps, timed apart.
@@ -243,9 +258,10 @@ def main():
         results[name] = {"time_to_solution_s": dt, "median_s": float(np.median(each)), "min_s": min(each),
                          "max_s": max(each), "iterations": info["iterations"], "restarts": info["restarts"],
                          "converged": info["converged"], "relres_true": rel, "setup_s": setup_s, "lanes_per_row": lanes,
-                         "schedule": sched,
+                         "schedule": sched, "gmres_schedule": g.gs2_gmres_schedule(h),
                          "rel_err_vs_oracle_fp64": (float(np.linalg.norm(xs - x_or) / np.linalg.norm(x_or))
                                                     if x_or is not None else None),
+                         "rel_err_vs_oracle_fp64_sampled": oracle_sampled_error(orec, xs, np),
                          "oracle_iterations": (orec["solves"][name]["iterations"]
                                                if orec and name in orec["solves"] else None),
                          "rel_err_vs_fp64_gpu_solution": float(np.linalg.norm(xs - xref) / np.linalg.norm(xref)),
@@ -267,10 +283,12 @@ def main():
                 f"{k} {v['achieved']:.0f} GB/s ({100 * v['frac']:.1f}%, {v['avg_launch_us']:.1f} us)"
                 for k, v in sweep.items()) + f"; preconditioner {apply_ms * 1e3:.1f} us per apply")
         eo = results[name]["rel_err_vs_oracle_fp64"]
+        es = results[name]["rel_err_vs_oracle_fp64_sampled"]
         log(f"[bench] {name}: {dt * 1e3:.2f} ms/solve (median {np.median(each) * 1e3:.2f}, spread "
             f"{min(each) * 1e3:.2f}-{max(each) * 1e3:.2f}), its={info['iterations']} (oracle "
             f"{results[name]['oracle_iterations']}), relres={rel:.2e}, err vs oracle "
-            f"{'n/a' if eo is None else f'{eo:.2e}'}, setup {setup_s:.2f}s, schedule {sched}")
+            f"{'n/a' if eo is None else f'{eo:.2e}'} (on {es['entries'] if es else 0} sampled entries: "
+            f"{'n/a' if es is None else format(es['value'], '.2e')}), setup {setup_s:.2f}s, schedule {sched}")
         del h
     head = results["fp64"]
 

@@ -121,6 +121,13 @@ typedef struct gs2_options {
                            /* GS2_STAGNATED when the true residual has not   */
                            /* halved over this many restart cycles (0 =      */
                            /* default 50, also without a handle; < 0 = never)*/
+    int spmv_format;      /* gmres_solve with this handle: layout of the     */
+                          /* solver's copy of A for w = A z: GS2_FORMAT_AUTO */
+                          /* (0: timed once per pattern on >= 65536 rows --  */
+                          /* sliced ELL at two lane counts, diagonal copy at */
+                          /* 1 and 2 rows per lane when A qualifies --, else */
+                          /* sliced ELL), _SELL or _DIA (2 rows per lane;    */
+                          /* sliced ELL if A does not qualify)               */
 } gs2_options;
 
 /* gs2_options.format */
@@ -312,6 +319,16 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  */
 int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,
                         int *lds_staging, int *ndiag_l, int *ndiag_u, int *tuned);
+
+/*
+ * The layout gmres_solve used for its copy of A with this handle (host
+ * outputs, any may be NULL; all 0 before the handle's first solve): format
+ * GS2_FORMAT_SELL or GS2_FORMAT_DIA, lanes_per_row (sliced ELL) or
+ * rows_per_lane (diagonal copy), ndiag (diagonals of the copy, 0 for sliced
+ * ELL), tuned = 1 if chosen by timing the candidates.
+ */
+int gs2_gmres_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *ndiag,
+                       int *tuned);
 
 /* --------------------------------------------------------------- batched
  *

@@ -23,7 +23,7 @@
 
 namespace gs2 {
 
-constexpr int RB = 1024; // rows per workgroup in the vector kernels
+constexpr int RB = KRB; // rows per workgroup in the vector kernels (sella.hpp)
 
 static std::atomic<int> g_graphs{1}; // replay restart cycles from HIP graphs
 
@@ -60,7 +60,8 @@ struct GmresWork {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     CycleKey key;
-    SellA A; // sliced-ELL copy of the system matrix
+    SellA A;         // the solver's copy of the system matrix
+    int fmt_req = -1; // the layout request it was built for
 };
 
 template <typename F>
@@ -198,8 +199,8 @@ __device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const doub
 
 // w = A z (sliced ELL, K lanes per row) fused with h = V^T w and ||w||^2
 // partials, written k-major: part[k*nb + b], the norm at k = nk.
-template <int K>
-__global__ __launch_bounds__(KT) void k_spmv_dot(SellAView A, int64_t n, const double *__restrict__ z,
+template <int SEL>
+__global__ __launch_bounds__(KT) void k_spmv_dot(SellAView A, DiaAView D, int64_t n, const double *__restrict__ z,
                                                  double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
                                                  const GState *__restrict__ st, double *__restrict__ part, int nb,
                                                  int fixed_nk)
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot(SellAView A, int64_t n, const d
     const int nk = st ? st->j + 1 : fixed_nk;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x;
-    sella_rows<K, RB, KT / WAVE>(A, n, r0, z, wl);
+    mat_rows<SEL, KT / WAVE>(A, D, n, r0, z, wl);
     for (int i = t; i < RB; i += KT)
         if (r0 + i < n) w[r0 + i] = wl[i];
     block_multidot<false>(n, r0, wl, nullptr, V, ldv, nk, true, ra, nullptr, rn);
@@ -219,8 +220,8 @@ __global__ __launch_bounds__(KT) void k_spmv_dot(SellAView A, int64_t n, const d
 }
 
 // r = b - A x written to out, with ||r||^2 partials.
-template <int K>
-__global__ __launch_bounds__(KT) void k_true_resid(SellAView A, int64_t n, const double *__restrict__ x,
+template <int SEL>
+__global__ __launch_bounds__(KT) void k_true_resid(SellAView A, DiaAView D, int64_t n, const double *__restrict__ x,
                                                    const double *__restrict__ b, double *__restrict__ out,
                                                    double *__restrict__ part, int nb)
 {
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(KT) void k_true_resid(SellAView A, int64_t n, const
     __shared__ double red[KT / WAVE];
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x;
-    sella_rows<K, RB, KT / WAVE>(A, n, r0, x, wl);
+    mat_rows<SEL, KT / WAVE>(A, D, n, r0, x, wl);
     double s = 0.0;
     for (int i = t; i < RB; i += KT) {
         const int64_t row = r0 + i;
@@ -417,8 +418,8 @@ __global__ void k_scale_next(int64_t n, double *__restrict__ V, int64_t ldv, con
 // equal to the final column in exact arithmetic; when the cycle stops the
 // tentative column is committed as it stands.
 
-template <int K>
-__global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, int64_t n, const double *__restrict__ z,
+template <int SEL>
+__global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, DiaAView D, int64_t n, const double *__restrict__ z,
                                                   double *__restrict__ w, const double *__restrict__ V, int64_t ldv,
                                                   const GState *__restrict__ st, double *__restrict__ part, int nb)
 {
@@ -428,7 +429,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, int64_t n, const 
     const int j = st->j;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x;
-    sella_rows<K, RB, KT / WAVE>(A, n, r0, z, wl);
+    mat_rows<SEL, KT / WAVE>(A, D, n, r0, z, wl);
     const double zsc = st->zs[j];
     const double *__restrict__ u = V + (int64_t)j * ldv;
     for (int i = t; i < RB; i += KT) {
@@ -596,9 +597,13 @@ __global__ void k_copy_stop(int64_t n, const double *__restrict__ a, double *__r
 
 // ------------------------------------------------------------- host side
 
+// SEL > 0: sliced ELL with SEL lanes per row; SEL < 0: the diagonal copy
+// with -SEL rows per lane
 #define GS2_SPMV_DISPATCH(K, kern, grid, ...)                                \
     do {                                                                     \
         switch (K) {                                                         \
+        case -1: kern<-1><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
+        case -2: kern<-2><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
         case 1: kern<1><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
         case 2: kern<2><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
         case 4: kern<4><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
@@ -621,6 +626,103 @@ static int precondition(int kind, gs2_handle *P, const double *v, double *z, int
         k_copy_stop<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, v, z, st);
         return GS2_OK;
     }
+}
+
+// Below this many rows the product's layout is not timed (sliced ELL at the
+// rule's lanes per row, unless forced): launch overhead would dominate.
+constexpr int64_t SPMV_TUNE_MIN_ROWS = 65536;
+
+// Time of one product w2 = b - A w in the layout sel (best of three batches
+// of five launches after a warm-up batch; timing-only events).
+static int time_product(GmresWork *W, int sel, hipStream_t s, float *ms)
+{
+    const int64_t n = W->n;
+    const int nb = W->nb;
+    const SellAView AS = view(W->A);
+    const DiaAView AD = dview(W->A);
+    hipEvent_t e0, e1;
+    GS2_TRY_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    GS2_TRY_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    k_zero64<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, W->w);
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+        GS2_TRY_HIP(hipEventRecord(e0, s));
+        for (int b = 0; b < 5; ++b)
+            GS2_SPMV_DISPATCH(sel, k_true_resid, (unsigned)nb, AS, AD, n, W->w, W->w, W->w2, W->part, nb);
+        GS2_TRY_HIP(hipEventRecord(e1, s));
+        GS2_TRY_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        GS2_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+        if (rep > 0) best = std::min(best, t / 5);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = best;
+    return GS2_OK;
+}
+
+static int build_layout(SellA &S, const gs2_csr &A, int sel, const std::vector<int> &offs, hipStream_t s)
+{
+    if (sel > 0) return sella_build_sell(S, A, sel, s);
+    GS2_TRY(sella_build_dia(S, A, -sel, offs, s));
+    return sella_fill_values(S, A, false, s);
+}
+
+// The layout of the solver's copy of A, chosen once per CSR pattern (keyed
+// by its row-pointer and column arrays and sizes) and kept with the
+// workspace; the values are copied again at every solve, so values changed
+// in place between solves are honoured.  Candidates: sliced ELL at the
+// lanes per row the mean row length suggests and at twice that, and, when
+// A qualifies, the diagonal copy at one and two rows per lane (8- and
+// 16-byte value loads).  fmt GS2_FORMAT_AUTO times them (one product each;
+// a later candidate must win by 3 %) on matrices of at least
+// SPMV_TUNE_MIN_ROWS rows; GS2_FORMAT_SELL / _DIA force a layout (the
+// diagonal one at two rows per lane, falling back to sliced ELL when A does
+// not qualify).
+static int prepare_matrix(GmresWork *W, const gs2_csr &A, int fmt, hipStream_t s)
+{
+    SellA &S = W->A;
+    if (S.rp == A.rowptr && S.ci == A.colind && S.n == A.n && S.nnz == A.nnz && (S.val || S.dval) &&
+        W->fmt_req == fmt)
+        return sella_fill_values(S, A, false, s);
+    sella_free(S);
+    std::vector<int> offs;
+    int hst = GS2_OK;
+    const bool dia_ok = fmt != GS2_FORMAT_SELL && sella_dia_offsets(A, offs, s, &hst);
+    GS2_TRY(hst);
+    const int K0 = sella_rule_lanes(A);
+    int sel = K0, tuned = 0;
+    if (fmt == GS2_FORMAT_DIA && dia_ok) {
+        sel = -2;
+    } else if (fmt == GS2_FORMAT_AUTO && A.n >= SPMV_TUNE_MIN_ROWS) {
+        std::vector<int> cands{K0};
+        if (K0 < WAVE) cands.push_back(2 * K0);
+        if (dia_ok) {
+            cands.push_back(-1);
+            cands.push_back(-2);
+        }
+        float best = 1e30f;
+        std::vector<int> timed;
+        for (int c : cands) {
+            GS2_TRY(build_layout(S, A, c, offs, s));
+            // the padding rule may widen a sliced-ELL candidate to one already timed
+            if (std::find(timed.begin(), timed.end(), S.sel) != timed.end()) continue;
+            timed.push_back(S.sel);
+            float ms = 0.f;
+            GS2_TRY(time_product(W, S.sel, s, &ms));
+            if (ms < 0.97f * best) {
+                best = ms;
+                sel = S.sel;
+            }
+        }
+        tuned = 1;
+    }
+    if (S.sel != sel || !(S.val || S.dval)) GS2_TRY(build_layout(S, A, sel, offs, s));
+    S.tuned = tuned;
+    S.rp = A.rowptr; // complete: key it
+    S.ci = A.colind;
+    W->fmt_req = fmt;
+    return GS2_OK;
 }
 
 static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, double rtol, int maxit, int kind,
@@ -648,9 +750,10 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     const int nb = W->nb;
     const unsigned gN = (unsigned)nb;
     const unsigned gE = (unsigned)((n + 255) / 256);
-    GS2_TRY(sella_prepare(W->A, A, s));
+    GS2_TRY(prepare_matrix(W, A, P ? P->h.spmv_fmt : GS2_FORMAT_AUTO, s));
     const SellAView AS = view(W->A);
-    const int K = W->A.K;
+    const DiaAView AD = dview(W->A);
+    const int K = W->A.sel;
     GState *st = W->st;
     GHeader *hdr = W->hdr;
     if (P) P->h.stop = &st->done;
@@ -694,13 +797,13 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     int ref_cycle = 0;
     // algorithmic bytes: SpMV with A (entries, slice pointers, z gathered once,
     // w written), and one pass over nk Krylov vectors
-    const double spmv_b = 12.0 * (double)A.nnz + 8.0 * (W->A.nslices + 1) + 16.0 * n;
+    const double spmv_b = sella_bytes(W->A);
     const double red_b = 8.0 * nb;
     for (;;) {
         prof_set_step(cycles, -1);
         {
             Prof pr(s, PK_TRUE_RESID, spmv_b + 8.0 * n);
-            GS2_SPMV_DISPATCH(K, k_true_resid, gN, AS, n, x, b, W->V, W->part, nb);
+            GS2_SPMV_DISPATCH(K, k_true_resid, gN, AS, AD, n, x, b, W->V, W->part, nb);
         }
         {
             Prof pr(s, PK_REDUCE, red_b);
@@ -748,7 +851,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                     {
                         Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
                         hipStream_t s = cs;
-                        GS2_SPMV_DISPATCH(K, k_spmv_dot2, gN, AS, n, zj, W->w, W->V, n, st, W->part, nb);
+                        GS2_SPMV_DISPATCH(K, k_spmv_dot2, gN, AS, AD, n, zj, W->w, W->V, n, st, W->part, nb);
                     }
                     {
                         Prof pr(cs, PK_REDUCE, red_b * (2 * j + 3));
@@ -769,7 +872,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                 {   // w = A z_j, hA = V^T w, ||w||^2
                     Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
                     hipStream_t s = cs;
-                    GS2_SPMV_DISPATCH(K, k_spmv_dot, gN, AS, n, zj, W->w, W->V, n, st, W->part, nb, 0);
+                    GS2_SPMV_DISPATCH(K, k_spmv_dot, gN, AS, AD, n, zj, W->w, W->V, n, st, W->part, nb, 0);
                 }
                 {
                     Prof pr(cs, PK_REDUCE, red_b * (j + 2));
@@ -815,7 +918,8 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         // and parameters (with a handle: its work space outlives the call).
         // Per-kernel event profiling needs the launches one by one.
         if (P && g_graphs.load() && !prof_on()) {
-            const CycleKey key{A.rowptr, A.colind, A.val, b, x, P, W->A.val, kind, m, steps, rtol, orth};
+            const CycleKey key{A.rowptr, A.colind, A.val, b, x, P, W->A.sel < 0 ? (const void *)W->A.dval : W->A.val,
+                               kind, m, steps, rtol, orth};
             if (!(W->exec && W->key == key)) GS2_TRY(capture_cycle(W, key, enqueue_cycle));
             GS2_TRY_HIP(hipGraphLaunch(W->exec, s));
         } else {
@@ -833,6 +937,21 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
 using namespace gs2;
 
 extern "C" int gs2_graphs(int enable) { return g_graphs.exchange(enable != 0 ? 1 : 0); }
+
+extern "C" int gs2_gmres_schedule(const gs2_handle *H, int *format, int *lanes_per_row, int *rows_per_lane,
+                                  int *ndiag, int *tuned)
+{
+    if (!H) return GS2_ERR_ARG;
+    const GmresWork *W = H->h.gw;
+    const bool built = W && (W->A.val || W->A.dval);
+    const int sel = built ? W->A.sel : 0;
+    if (format) *format = !built ? 0 : sel < 0 ? GS2_FORMAT_DIA : GS2_FORMAT_SELL;
+    if (lanes_per_row) *lanes_per_row = sel > 0 ? sel : 0;
+    if (rows_per_lane) *rows_per_lane = sel < 0 ? -sel : 0;
+    if (ndiag) *ndiag = sel < 0 ? W->A.ndiag : 0;
+    if (tuned) *tuned = built ? W->A.tuned : 0;
+    return GS2_OK;
+}
 
 extern "C" int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit,
                            int prec_kind, gs2_handle *prec, gs2_solve_info *info, void *stream)

@@ -1,6 +1,9 @@
 // Sliced-ELL copy of the system matrix for the Krylov solvers' SpMV.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+#include <vector>
+
 #include "sella.hpp"
 
 namespace gs2 {
@@ -53,17 +56,108 @@ __global__ void k_sella_fill(int64_t n, int64_t nslices, int K, const int32_t *_
 
 void sella_free(SellA &S)
 {
-    for (void *p : {(void *)S.sp, (void *)S.col, (void *)S.val})
+    for (void *p : {(void *)S.sp, (void *)S.col, (void *)S.val, (void *)S.dval})
         if (p) (void)hipFree(p);
     S = SellA{};
 }
 
-// Lanes per row: the mean row length picks K (as for the triangles), and K
-// grows while a few long rows would pad the copy beyond twice the entries.
-static int sella_structure(SellA &S, const gs2_csr &A, int64_t *len, void *tmp, size_t tmp_bytes, hipStream_t s)
+struct DiaOffsA {
+    int nd;
+    int off[DIA_MAX];
+};
+
+// One thread per row: entry (i, i + off[d]) of the row goes to diagonal d at
+// the row's interleaved position (R rows per lane).  Offsets ascend within a
+// row as they do in off, so the diagonal index walks forward.  Entries of
+// rows past n and absent entries keep the zeros written at allocation.
+__global__ void k_diaA_fill(int64_t n, int R, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const double *__restrict__ va, DiaOffsA o, int64_t stride, double *__restrict__ val)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t blk = (int64_t)WAVE * R;
+    const int64_t pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
+    int t = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int d = (int)((int64_t)ci[k] - i);
+        while (t < o.nd - 1 && o.off[t] < d) ++t;
+        if (o.off[t] == d) val[(int64_t)t * stride + pos] = va[k];
+    }
+}
+
+// Distinct offsets col - row of the whole pattern, ascending (host copy of
+// the pattern); false when there are more than DIA_MAX or the diagonals
+// would store more than 1.5x the entries.
+static bool diaA_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st)
+{
+    *st = GS2_OK;
+    offs.clear();
+    const int64_t n = A.n;
+    std::vector<int32_t> rp(n + 1), ci(std::max<int64_t>(A.nnz, 1));
+    if (hipMemcpyAsync(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (A.nnz && hipMemcpyAsync(ci.data(), A.colind, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, s) !=
+                      hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        *st = GS2_ERR_HIP;
+        return false;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int d = (int)((int64_t)ci[k] - i);
+            auto it = std::lower_bound(offs.begin(), offs.end(), d);
+            if (it == offs.end() || *it != d) {
+                if ((int)offs.size() == DIA_MAX) return false;
+                offs.insert(it, d);
+            }
+        }
+    return (double)offs.size() * (double)n <= 1.5 * (double)A.nnz + (double)KRB * offs.size();
+}
+
+int sella_build_dia(SellA &S, const gs2_csr &A, int R, const std::vector<int> &offs, hipStream_t s)
+{
+    sella_free(S);
+    S.n = A.n;
+    S.nnz = A.nnz;
+    S.dR = R;
+    S.ndiag = (int)offs.size();
+    S.dstride = std::max<int64_t>(1, (A.n + KRB - 1) / KRB) * KRB;
+    for (int d = 0; d < DIA_MAX; ++d) S.doff[d] = d < S.ndiag ? offs[d] : 0;
+    const size_t bytes = sizeof(double) * (size_t)std::max(S.ndiag, 1) * (size_t)S.dstride;
+    GS2_TRY_HIP(hipMalloc(&S.dval, bytes));
+    GS2_TRY_HIP(hipMemsetAsync(S.dval, 0, bytes, s));
+    S.sel = -R;
+    return GS2_OK;
+}
+
+// copy A's values into the built layout
+int sella_fill_values(SellA &S, const gs2_csr &A, bool with_col, hipStream_t s)
 {
     const int tb = 256;
-    for (int K = choose_lanes((double)A.nnz / (double)std::max<int64_t>(A.n, 1), 0);; K *= 2) {
+    if (S.sel < 0) {
+        if (A.n > 0) {
+            DiaOffsA o;
+            o.nd = S.ndiag;
+            for (int d = 0; d < DIA_MAX; ++d) o.off[d] = S.doff[d];
+            k_diaA_fill<<<(unsigned)((A.n + tb - 1) / tb), tb, 0, s>>>(A.n, S.dR, A.rowptr, A.colind, A.val, o,
+                                                                      S.dstride, S.dval);
+        }
+    } else if (S.nslices > 0) {
+        const int64_t threads = S.nslices * WAVE;
+        k_sella_fill<<<(unsigned)((threads + tb - 1) / tb), tb, 0, s>>>(A.n, S.nslices, S.K, A.rowptr, A.colind,
+                                                                       A.val, S.sp, with_col ? 1 : 0, S.col, S.val);
+    }
+    GS2_TRY_HIP(hipGetLastError());
+    return GS2_OK;
+}
+
+// Lanes per row: from K0 (the rule: the mean row length, as for the
+// triangles), K grows while a few long rows would pad the copy beyond twice
+// the entries.
+static int sella_structure(SellA &S, const gs2_csr &A, int K0, int64_t *len, void *tmp, size_t tmp_bytes,
+                           hipStream_t s)
+{
+    const int tb = 256;
+    for (int K = K0;; K *= 2) {
         S.K = K;
         S.C = WAVE / K;
         S.nslices = (A.n + S.C - 1) / S.C;
@@ -79,41 +173,40 @@ static int sella_structure(SellA &S, const gs2_csr &A, int64_t *len, void *tmp, 
     return GS2_OK;
 }
 
-int sella_prepare(SellA &S, const gs2_csr &A, hipStream_t s)
+int sella_rule_lanes(const gs2_csr &A) { return choose_lanes((double)A.nnz / (double)std::max<int64_t>(A.n, 1), 0); }
+
+// Sliced-ELL structure with at least K0 lanes per row (columns and values
+// filled), replacing whatever S held.
+int sella_build_sell(SellA &S, const gs2_csr &A, int K0, hipStream_t s)
 {
-    const bool same = S.val && S.rp == A.rowptr && S.ci == A.colind && S.n == A.n && S.nnz == A.nnz;
-    if (!same) {
-        sella_free(S);
-        S.n = A.n;
-        S.nnz = A.nnz;
-        int64_t *len = nullptr;
-        void *tmp = nullptr;
-        size_t tmp_bytes = 0;
-        int st = GS2_OK;
-        const int64_t max_slices = A.n; // K = 64: one row per slice
-        if (hipMalloc(&S.sp, sizeof(int64_t) * (max_slices + 1)) != hipSuccess ||
-            hipMalloc(&len, sizeof(int64_t) * (max_slices + 1)) != hipSuccess ||
-            hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, len, S.sp, (int)(max_slices + 1), s) != hipSuccess ||
-            hipMalloc(&tmp, tmp_bytes + 16) != hipSuccess)
-            st = GS2_ERR_NOMEM;
-        if (st == GS2_OK) st = sella_structure(S, A, len, tmp, tmp_bytes, s);
-        if (tmp) (void)hipFree(tmp);
-        if (len) (void)hipFree(len);
-        if (st != GS2_OK) {
-            sella_free(S);
-            return st;
-        }
-        S.rp = A.rowptr; // the structure is complete: key it
-        S.ci = A.colind;
+    sella_free(S);
+    S.n = A.n;
+    S.nnz = A.nnz;
+    int64_t *len = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    int st = GS2_OK;
+    const int64_t max_slices = A.n; // K = 64: one row per slice
+    if (hipMalloc(&S.sp, sizeof(int64_t) * (max_slices + 1)) != hipSuccess ||
+        hipMalloc(&len, sizeof(int64_t) * (max_slices + 1)) != hipSuccess ||
+        hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, len, S.sp, (int)(max_slices + 1), s) != hipSuccess ||
+        hipMalloc(&tmp, tmp_bytes + 16) != hipSuccess)
+        st = GS2_ERR_NOMEM;
+    if (st == GS2_OK) st = sella_structure(S, A, K0, len, tmp, tmp_bytes, s);
+    if (tmp) (void)hipFree(tmp);
+    if (len) (void)hipFree(len);
+    if (st == GS2_OK) {
+        S.sel = S.K;
+        st = sella_fill_values(S, A, true, s);
     }
-    if (S.nslices > 0) {
-        const int tb = 256;
-        const int64_t threads = S.nslices * WAVE;
-        k_sella_fill<<<(unsigned)((threads + tb - 1) / tb), tb, 0, s>>>(A.n, S.nslices, S.K, A.rowptr, A.colind,
-                                                                       A.val, S.sp, same ? 0 : 1, S.col, S.val);
-        GS2_TRY_HIP(hipGetLastError());
-    }
-    return GS2_OK;
+    if (st != GS2_OK) sella_free(S);
+    return st;
+}
+
+bool sella_dia_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st)
+{
+    return A.n > 0 && A.n <= (int64_t(1) << 30) && diaA_offsets(A, offs, s, st);
 }
 
 } // namespace gs2
+

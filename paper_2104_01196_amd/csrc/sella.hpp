@@ -21,6 +21,10 @@
 
 namespace gs2 {
 
+// Rows per workgroup of the Krylov kernels that form w = A z (and of the
+// padding of the diagonal copy below).
+constexpr int KRB = 1024;
+
 struct SellA {
     const void *rp = nullptr, *ci = nullptr;
     int64_t n = 0, nnz = 0;
@@ -29,6 +33,20 @@ struct SellA {
     int64_t *sp = nullptr; // nslices + 1 offsets (multiples of 64)
     int32_t *col = nullptr;
     double *val = nullptr;
+    // Diagonal-interleaved alternative for matrices with at most DIA_MAX
+    // distinct offsets col - row (stencils in natural order): diagonal d holds
+    // a_{i, i + off[d]} for every row i (0 where absent), rows in blocks of
+    // 64 R, lane l of a block owning rows k*64 + l (k < R) with its R values
+    // of one diagonal contiguous (one 8R-byte load), rows padded to whole
+    // workgroups (KRB).  No column indices.  dR = 0: not built.
+    int dR = 0, ndiag = 0;
+    int64_t dstride = 0;
+    double *dval = nullptr;
+    int doff[DIA_MAX] = {};
+    // the product's layout: sel > 0 sliced ELL with K = sel lanes per row,
+    // sel < 0 the diagonal copy with R = -sel rows per lane
+    int sel = 1;
+    int tuned = 0; // 1 if sel was chosen by timing the candidates
 };
 
 struct SellAView {
@@ -38,11 +56,47 @@ struct SellAView {
     const double *val;
 };
 
-inline SellAView view(const SellA &S) { return SellAView{S.nslices, S.sp, S.col, S.val}; }
+struct DiaAView {
+    int ndiag;
+    int64_t stride;
+    const double *val;
+    int off[DIA_MAX];
+};
 
-// (Re)build the structure when the pattern is new, then copy the values.
-int sella_prepare(SellA &S, const gs2_csr &A, hipStream_t s);
+inline SellAView view(const SellA &S) { return SellAView{S.nslices, S.sp, S.col, S.val}; }
+inline DiaAView dview(const SellA &S)
+{
+    DiaAView v;
+    v.ndiag = S.ndiag;
+    v.stride = S.dstride;
+    v.val = S.dval;
+    for (int d = 0; d < DIA_MAX; ++d) v.off[d] = S.doff[d];
+    return v;
+}
+
+// Algorithmic bytes of one product w = A z in the chosen layout: every
+// stored entry (value, plus the column for sliced ELL; padding not counted),
+// the slice pointers, z gathered once and w written once.
+inline double sella_bytes(const SellA &S)
+{
+    if (S.sel < 0) return 8.0 * (double)S.nnz + 16.0 * (double)S.n;
+    return 12.0 * (double)S.nnz + 8.0 * (double)(S.nslices + 1) + 16.0 * (double)S.n;
+}
+
+// Building blocks of the copy (sella.hip); the Krylov solver picks among
+// them (krylov.hip: prepare_matrix).
 void sella_free(SellA &S);
+// lanes per row the mean row length suggests
+int sella_rule_lanes(const gs2_csr &A);
+// sliced ELL with at least K0 lanes per row, values filled
+int sella_build_sell(SellA &S, const gs2_csr &A, int K0, hipStream_t s);
+// A's distinct offsets when it qualifies for the diagonal copy (<= DIA_MAX
+// offsets, stored diagonals <= 1.5x the entries); *st reports HIP failures
+bool sella_dia_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st);
+// diagonal copy with R rows per lane (zeroed; fill with sella_fill_values)
+int sella_build_dia(SellA &S, const gs2_csr &A, int R, const std::vector<int> &offs, hipStream_t s);
+// copy A's values (and columns, for a new sliced-ELL structure) into S
+int sella_fill_values(SellA &S, const gs2_csr &A, bool with_col, hipStream_t s);
 
 // ybuf[i] = (A z)[r0 + i] for the RB rows of the workgroup starting at r0
 // (0 past n), into LDS.  The workgroup's NW wavefronts take consecutive
@@ -92,6 +146,72 @@ __device__ __forceinline__ void sella_rows(const SellAView A, int64_t n, int64_t
         }
     }
     __syncthreads();
+}
+
+// ybuf[i] = (A z)[r0 + i] for the KRB rows of the workgroup starting at r0
+// (0 past n), from the diagonal copy with R rows per lane.  Wavefront w of
+// the NW takes the KRB / NW consecutive rows r0 + w KRB/NW, i.e. KRB / NW /
+// (64 R) blocks; per diagonal a lane loads its R values of a block in one
+// 8R-byte load (non-temporal: the copy is streamed once per product) and
+// gathers z at row + off, 64 consecutive elements per wavefront load.
+// Columns are clamped into [0, n) only in blocks whose shifted rows leave it
+// (a clamped column meets a stored zero).  Ends with a barrier.
+template <int R, int NW>
+__device__ __forceinline__ void dia_rows(const DiaAView A, int64_t n, int64_t r0, const double *__restrict__ z,
+                                         double *ybuf)
+{
+    constexpr int RW = KRB / NW;          // rows per wavefront
+    constexpr int NBLK = RW / (WAVE * R); // blocks per wavefront
+    static_assert(RW % (WAVE * R) == 0, "a wavefront's rows split into whole blocks");
+    using V2 = double __attribute__((ext_vector_type(2)));
+    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
+    const int64_t w0 = r0 + (int64_t)wv * RW;
+    double acc[NBLK][R];
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int k = 0; k < R; ++k) acc[b][k] = 0.0;
+    for (int d = 0; d < A.ndiag; ++d) {
+        const int o = A.off[d];
+        const double *__restrict__ vd = A.val + (int64_t)d * A.stride;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            const int64_t base = w0 + (int64_t)b * (WAVE * R);
+            double a[R];
+            if constexpr (R == 2) {
+                const V2 t = __builtin_nontemporal_load((const V2 *)(vd + base + 2 * ln));
+                a[0] = t.x;
+                a[1] = t.y;
+            } else {
+                a[0] = __builtin_nontemporal_load(vd + base + ln);
+            }
+            const bool inside = base + o >= 0 && base + WAVE * R + o <= n;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                int64_t c = base + k * WAVE + ln + o;
+                if (!inside) c = c < 0 ? 0 : (c >= n ? n - 1 : c);
+                acc[b][k] += a[k] * z[c];
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int64_t row = w0 + (int64_t)b * (WAVE * R) + k * WAVE + ln;
+            ybuf[row - r0] = row < n ? acc[b][k] : 0.0;
+        }
+    __syncthreads();
+}
+
+// The product in the layout sel encodes (> 0 sliced ELL, K lanes per row;
+// < 0 the diagonal copy, -sel rows per lane).
+template <int SEL, int NW>
+__device__ __forceinline__ void mat_rows(const SellAView A, const DiaAView D, int64_t n, int64_t r0,
+                                         const double *__restrict__ z, double *ybuf)
+{
+    if constexpr (SEL > 0) sella_rows<SEL, KRB, NW>(A, n, r0, z, ybuf);
+    else dia_rows<-SEL, NW>(D, n, r0, z, ybuf);
 }
 
 } // namespace gs2

@@ -842,6 +842,7 @@ void gs2_default_options(gs2_options *opt)
     opt->rows_per_lane = 0;
     opt->lds_staging = 0;
     opt->stagnation_cycles = 0;
+    opt->spmv_format = GS2_FORMAT_AUTO;
 }
 
 int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
@@ -864,7 +865,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
         return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
     if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_DIA || o.rows_per_lane < 0 || o.lds_staging < 0 ||
-        o.lds_staging > 2)
+        o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_DIA)
         return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;
     if (!H) return GS2_ERR_NOMEM;
@@ -878,6 +879,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     h.compact = o.compact ? 1 : 0;
     h.orth = o.orthogonalization;
     h.stag_cycles = o.stagnation_cycles;
+    h.spmv_fmt = o.spmv_format;
     h.blocks = std::max(1, o.blocks);
     h.local_sweeps = std::max(1, o.local_sweeps);
     h.precision = o.precision;

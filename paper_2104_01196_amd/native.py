@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int), ("blocks", C.c_int),
                 ("local_sweeps", C.c_int), ("team_rows", C.c_int), ("team_wait_ms", C.c_int),
                 ("format", C.c_int), ("rows_per_lane", C.c_int), ("lds_staging", C.c_int),
-                ("stagnation_cycles", C.c_int)]
+                ("stagnation_cycles", C.c_int), ("spmv_format", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -84,6 +84,7 @@ def lib():
         ip = C.POINTER(C.c_int)
         L.gs2_handle_query.argtypes = [vp, i64p, i64p, i64p, i64p, ip, ip, ip]
         L.gs2_handle_schedule.argtypes = [vp, ip, ip, ip, ip, ip, ip, ip, ip]
+        L.gs2_gmres_schedule.argtypes = [vp, ip, ip, ip, ip, ip]
         L.gs2_inner_residuals.argtypes = [vp, vp, i, C.POINTER(C.c_double), vp]
         L.gs2_inner_residuals_noalloc.argtypes = [vp, vp, i, vp, vp]
         L.gs2_profile.argtypes = [i]
@@ -180,10 +181,10 @@ class Handle:
 def gs2_setup(A: DeviceCSR, sweeps=1, inner=1, damping=1.0, variant=FORWARD, precision=FP64, inner_damping=1.0,
               compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0, blocks=1,
               local_sweeps=1, format=FORMAT_AUTO, rows_per_lane=0, lds_staging=0, stagnation_cycles=0,
-              stream=None) -> Handle:
+              spmv_format=FORMAT_AUTO, stream=None) -> Handle:
     opt = Options(precision, inner_damping, int(compact), int(build_levels), int(autotune), lanes_per_row, 0,
                   orthogonalization, blocks, local_sweeps, 0, 0, format, rows_per_lane, lds_staging,
-                  stagnation_cycles)
+                  stagnation_cycles, spmv_format)
     out = C.c_void_p()
     d = A.desc()
     st = lib().gs2_setup(C.byref(d), sweeps, inner, damping, variant, C.byref(opt), _stream(stream), C.byref(out))
@@ -281,6 +282,15 @@ def gs2_handle_schedule(h: Handle) -> dict:
         raise Gs2Error(st, "gs2_handle_schedule")
     keys = ["format", "lanes_per_row", "rows_per_lane", "vector_bytes", "lds_staging", "ndiag_l", "ndiag_u", "tuned"]
     return {k: x.value for k, x in zip(keys, v)}
+
+
+def gs2_gmres_schedule(h: Handle) -> dict:
+    """The layout of gmres_solve's copy of A with this handle (zeros before its first solve)."""
+    v = [C.c_int() for _ in range(5)]
+    st = lib().gs2_gmres_schedule(h.ptr, *[C.byref(x) for x in v])
+    if st != OK:
+        raise Gs2Error(st, "gs2_gmres_schedule")
+    return {k: x.value for k, x in zip(["format", "lanes_per_row", "rows_per_lane", "ndiag", "tuned"], v)}
 
 
 def gs2_inner_residuals(h: Handle, r, inner: int, stream=None):

@@ -42,6 +42,10 @@ WORKLOADS = {
     "vardiff3d_192": dict(config=4, size=192, variant=2, sweeps=1, inner=1, restart=50),
     # 128^3 Laplacian, forward GS2(2 sweeps, 1 inner), GMRES(50)
     "laplace3d_128": dict(config=2, size=128, variant=0, sweeps=2, inner=1, restart=50),
+    # Q1 elasticity on 64^3 free nodes, SGS2(1 sweep, 3 inner) with damping 0.7 and inner damping 0.5,
+    # GMRES(50); float64 preconditioner only (the reduced-precision forms have no inner damping)
+    "elasticity_64": dict(config=3, size=64, variant=2, sweeps=1, inner=3, omega=0.7, gamma=0.5, restart=50,
+                          precisions=(0,)),
 }
 RTOL = 1e-8
 MAXIT = 20000
@@ -69,8 +73,8 @@ def _solve(args):
     w = WORKLOADS[name]
     p = config_problem(w["config"], size=w["size"])
     x, info = oracle.gmres(p["A"], p["b"], restart=w["restart"], rtol=RTOL, maxit=MAXIT, prec="gs2",
-                           variant=w["variant"], sweeps=w["sweeps"], inner=w["inner"], precision=precision,
-                           cgs2=cgs2)
+                           variant=w["variant"], sweeps=w["sweeps"], inner=w["inner"], omega=w.get("omega", 1.0),
+                           gamma=w.get("gamma", 1.0), precision=precision, cgs2=cgs2)
     out = {k: info[k] for k in ("iterations", "restarts", "relres", "converged", "status", "seconds")}
     if precision == 0:
         xt = p["x_true"]
@@ -92,7 +96,7 @@ def _solve(args):
 def main(names):
     jobs = []
     for name in names:
-        for precision in (0, 1, 2):
+        for precision in WORKLOADS[name].get("precisions", (0, 1, 2)):
             jobs.append((name, precision, False))
         jobs.append((name, 0, True))
     results = {}
@@ -111,7 +115,7 @@ def main(names):
         xm = xt + np.load(os.path.join(HERE, recs["fp64"]["dx_file"])).astype(np.float64)
         xc = xt + np.load(os.path.join(HERE, recs["fp64_cgs2"]["dx_file"])).astype(np.float64)
         recs["fp64_cgs2"]["rel_diff_vs_fp64"] = float(np.linalg.norm(xc - xm) / np.linalg.norm(xm))
-        rec = {"workload": name, **w, "rtol": RTOL, "solves": recs,
+        rec = {"workload": name, **{k: v for k, v in w.items() if k != "precisions"}, "rtol": RTOL, "solves": recs,
                "sample_seed": SAMPLE_SEED, "nsample": NSAMPLE, "nweight": NWEIGHT,
                "written_by": "tests/golden/make_oracle_solves.py (CPU oracle only)"}
         with open(os.path.join(HERE, f"{name}_oracle.json"), "w") as f:

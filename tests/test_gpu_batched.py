@@ -2,9 +2,11 @@
 right-hand side) pair against an independent oracle solve of that system
 (the systems are independent, so this is exact parity of the method).
 
-Bar: iteration count within +-1 of the oracle (CGS2 on the GPU, MGS in the
-oracle), true relative residual <= rtol recomputed on the host, and the
-solution within 1e-5 (relative) of the oracle's.
+Bar for the small batches: iteration count within +-1 of the oracle (CGS2
+on the GPU, MGS in the oracle), true relative residual <= rtol recomputed on
+the host, and the solution within 1e-5 (relative) of the oracle's.  The full
+workload's long restarted runs are held to the oracle's own spread between
+two orthogonalisations (test_batched_full_size_all_pairs).
 """
 import numpy as np
 import pytest
@@ -198,12 +200,35 @@ def test_batched_not_converged_and_general_rows(team_rows):
 
 
 @pytest.mark.slow
-def test_batched_full_size_sampled():
-    """The full 512-system workload (sides 16..256, 4 right-hand sides):
-    every pair reaches 1e-8 (true residual recomputed on the host) and a
-    sample of pairs matches independent oracle solves."""
+def test_batched_full_size_all_pairs():
+    """The full 512-system workload (sides 16..256, 4 right-hand sides),
+    GS2(2,2) with the float32 preconditioner, GMRES(20): every one of the
+    2048 pairs reaches 1e-8 (true residual recomputed on the host) and is
+    compared with the oracle's solves of the same pair stored in
+    tests/golden/convdiff512x4_oracle.json (written by make_batched_oracle.py,
+    which calls only the oracle), with modified (MGS) and with classical,
+    twice-applied (CGS2) Gram-Schmidt.
+
+    Bars.  The oracle's two orthogonalisations build the same Krylov space in
+    exact arithmetic and agree exactly on every pair that converges in fewer
+    than 200 steps; beyond that, GMRES(20) restarted tens to hundreds of times
+    with a float32 preconditioner amplifies rounding order, and they drift
+    apart (up to 590 of 1966 steps).  The GPU orthogonalises in a third order
+    and also sums the preconditioner's rows in another order.  So: pairs under
+    200 oracle steps within one step of the MGS count; for the longer pairs,
+    per band of oracle step counts, the GPU's deviations from MGS no wider
+    than the oracle's own MGS-vs-CGS2 spread allows (pairs off by more than
+    one step at most 1.5x as many plus 5, the largest deviation at most 2.5x
+    plus 5, the total step count within twice the oracle's total difference
+    plus 1 %); and the solution's weighted sum x . w within 1e-6 of the
+    oracle's, relative to ||x_oracle||."""
+    import json
+    import os
+
     from gen import config_problem
 
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "convdiff512x4_oracle.json")
+    rec = json.load(open(path))
     p = config_problem(5)
     mats, rhs = p["mats"], p["rhs"]
     st, infos, xs, *_ = run_batch(mats, rhs, 4, sweeps=2, inner=2, precision=g.FP32, restart=20)
@@ -212,12 +237,28 @@ def test_batched_full_size_sampled():
         S = A.to_scipy()
         R = rhs[i] - S @ xs[i]
         assert np.all(np.linalg.norm(R, axis=0) / np.linalg.norm(rhs[i], axis=0) <= 1e-8)
-    for i in (0, 100, 257, 511):
-        for r in (0, 3):
-            xo, io = oracle.gmres(mats[i], rhs[i][:, r], restart=20, rtol=1e-8, prec="gs2", sweeps=2, inner=2,
-                                  precision=oracle.FP32)
-            # Long restarted runs (hundreds of steps in GMRES(20)) with a float32
-            # preconditioner: both sides round every apply to float32, in different
-            # summation orders, and the restarts amplify those differences into
-            # slightly different histories; the bar is 1% of the count (>= 1).
-            assert abs(infos[i * 4 + r]["iterations"] - io["iterations"]) <= max(1, io["iterations"] // 100)
+    gi = np.array([infos[q["system"] * 4 + q["rhs"]]["iterations"] for q in rec["pairs"]])
+    mi = np.array([q["iterations_mgs"] for q in rec["pairs"]])
+    ci = np.array([q["iterations_cgs2"] for q in rec["pairs"]])
+    d, spread = np.abs(gi - mi), np.abs(ci - mi)
+    assert np.all(d[mi < 200] <= 1), np.nonzero(d[mi < 200] > 1)
+    for lo, hi in [(0, 200), (200, 400), (400, 800), (800, 100000)]:
+        sel = (mi >= lo) & (mi < hi)
+        if not sel.any():
+            continue
+        gs, os_ = gi[sel].sum() - mi[sel].sum(), ci[sel].sum() - mi[sel].sum()
+        print(f"oracle steps [{lo},{hi}): {sel.sum()} pairs, {mi[sel].sum()} MGS steps; |GPU - MGS| max "
+              f"{d[sel].max()} median {np.median(d[sel]):.0f} p90 {np.quantile(d[sel], 0.9):.0f} >1: "
+              f"{(d[sel] > 1).sum()} total {gs:+d}; |CGS2 - MGS| max {spread[sel].max()} median "
+              f"{np.median(spread[sel]):.0f} p90 {np.quantile(spread[sel], 0.9):.0f} >1: {(spread[sel] > 1).sum()} "
+              f"total {os_:+d}")
+        if lo >= 200:
+            assert (d[sel] > 1).sum() <= 1.5 * (spread[sel] > 1).sum() + 5
+            assert d[sel].max() <= 2.5 * spread[sel].max() + 5
+            assert abs(gs) <= 2 * abs(os_) + 0.01 * mi[sel].sum()
+    xw = np.array([xs[q["system"]][:, q["rhs"]] @ np.sin(np.arange(1, mats[q["system"]].n + 1, dtype=np.float64))
+                   for q in rec["pairs"]])
+    ew = np.abs(xw - np.array([q["x_dot_w"] for q in rec["pairs"]])) / np.array([q["x_norm"] for q in rec["pairs"]])
+    print(f"|x.w - x_oracle.w| / ||x_oracle||: max {ew.max():.2e}, median {np.median(ew):.2e}; all steps: GPU "
+          f"{gi.sum()}, MGS {mi.sum()}, CGS2 {ci.sum()}")
+    assert ew.max() <= 1e-6
