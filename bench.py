@@ -50,9 +50,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=None, help="grid side (default: the configuration's)")
-    ap.add_argument("--config", type=int, default=4, choices=[2, 4, 5],
+    ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4, 5],
                     help="4: precision forms on the 192^3 variable-coefficient problem (default); 2: the 128^3 "
-                         "Laplacian; 5: batched form on 512 convection-diffusion systems x 4 right-hand sides")
+                         "Laplacian; 3: Q1 elasticity on 64^3 free nodes (damped SGS2 with inner damping, "
+                         "and Jacobi); 5: batched form on 512 convection-diffusion systems x 4 right-hand sides")
     ap.add_argument("--compare", action="store_true",
                     help="GMRES(50) on the 128^3 Laplacian with each preconditioner of the comparison (GS2, SGS2, JR, "
                          "exact level-scheduled GS, multicolor GS) instead of the default measurement")
@@ -143,7 +144,7 @@ def oracle_sampled_error(rec, xs, np):
     return {"value": float(np.linalg.norm(xs[idx] - xo) / np.linalg.norm(xo)), "entries": int(len(idx))}
 
 
-def oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, gpu_iterations, np):
+def oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, gpu_iterations, np, omega=1.0, gamma=1.0):
     """The oracle (one host thread, as written) on a bounded sample of the
     same float64 solve: its first 4 and first 12 Arnoldi steps, timed apart.
     A step's cost is modelled as c0 + c1 (j + 1) (preconditioner and product,
@@ -154,7 +155,8 @@ def oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, gpu_iterations, np):
     k1, k2 = 4, 12
     t = {}
     for k in (k1, k2):
-        _, oi = oracle.gmres(A, b, restart=restart, rtol=rtol, maxit=k, prec="gs2", variant=pv, sweeps=psw, inner=pin)
+        _, oi = oracle.gmres(A, b, restart=restart, rtol=rtol, maxit=k, prec="gs2", variant=pv, sweeps=psw, inner=pin,
+                             omega=omega, gamma=gamma)
         t[k] = oi["seconds"]
     # steps 0..k1-1 and k1..k2-1: mean (j + 1) is (k1 + 1) / 2 and (k1 + k2 + 1) / 2
     m1, m2 = (k1 + 1) / 2.0, (k1 + k2 + 1) / 2.0
@@ -187,19 +189,28 @@ def main():
     dev = torch.device("cuda:0")
     t0 = time.time()
     cfg = args.config
-    size = args.size or (128 if cfg == 2 else 192)
+    size = args.size or {2: 128, 3: 64}.get(cfg, 192)
     p = config_problem(cfg, size=size)
     A, b = p["A"], p["b"]
     log(f"[bench] generated config {cfg}, side {size}: n={A.n} nnz={A.nnz} ({time.time() - t0:.1f}s)")
     # preconditioner: forward GS2(2 sweeps, 1 inner) for the benchmark workload;
     # symmetric GS2(1, 1) for the precision forms (the paper's mixed-precision setting)
     pv, psw, pin = (g.FORWARD, 2, 1) if cfg == 2 else (g.SYMMETRIC, 1, 1)
+    # elasticity: SGS2(1 sweep, 3 inner) with damping 0.7 and inner damping 0.5 (undamped inner
+    # sweeps stagnate GMRES on this problem, in the oracle as on the GPU)
+    omega, gamma = 1.0, 1.0
+    if cfg == 3:
+        pv, psw, pin, omega, gamma = g.SYMMETRIC, 1, 3, 0.7, 0.5
     dA = g.DeviceCSR.from_host(A, dev)
     db = torch.as_tensor(b, device=dev)
     restart, rtol, maxit = 50, 1e-8, 20000
     if cfg == 2:
         wname = f"laplace3d_{size}"
         workload = f"laplace3d_7pt_{size}^3 GS2-forward(2 sweeps,1 inner) GMRES(50) rtol 1e-8"
+    elif cfg == 3:
+        wname = f"elasticity_{size}"
+        workload = (f"elasticity_q1_27pt_{size}^3nodes_3dof E logU[1,100] nu U[0.2,0.45] SGS2(1 sweep,3 inner) "
+                    f"damping 0.7 inner damping 0.5 GMRES(50) rtol 1e-8")
     else:
         wname = f"vardiff3d_{size}"
         workload = f"vardiff3d_7pt_{size}^3 kappa logU[1e-2,1e2] SGS2(1 sweep,1 inner) GMRES(50) rtol 1e-8"
@@ -217,7 +228,7 @@ def main():
     prof_solve_s = None
     for name, prec in forms:
         ts = time.time()
-        h = g.gs2_setup(dA, psw, pin, 1.0, pv, precision=prec)
+        h = g.gs2_setup(dA, psw, pin, omega, pv, precision=prec, inner_damping=gamma)
         torch.cuda.synchronize()
         setup_s = time.time() - ts
         lanes = g.gs2_handle_query(h)["lanes_per_row"]
@@ -315,9 +326,28 @@ def main():
         log(f"[bench] dominant kernel {dom}: {ach:.0f} GB/s ({100 * ach / HBM_PEAK_GBS:.1f}% of peak, "
             f"{100 * ach / ceiling:.1f}% of the measured {ceiling:.0f} GB/s copy)")
 
+    comparison = None
+    if cfg == 3:
+        # Jacobi-Richardson, one sweep, as the paper's comparison on elasticity
+        hj = g.gs2_setup(dA, 1, 0, 1.0, g.FORWARD)
+        for _ in range(args.warmup):
+            x.zero_()
+            g.gmres_solve(dA, db, x, restart, rtol, maxit, g.PREC_JR, hj)
+        torch.cuda.synchronize()
+        each = []
+        for _ in range(args.steps):
+            x.zero_()
+            te = time.perf_counter()
+            ij = g.gmres_solve(dA, db, x, restart, rtol, maxit, g.PREC_JR, hj)
+            each.append(time.perf_counter() - te)
+        comparison = {"jr1": {"time_to_solution_s": float(np.mean(each)), "median_s": float(np.median(each)),
+                              "iterations": ij["iterations"], "converged": ij["converged"], "relres": ij["relres"]}}
+        log(f"[bench] JR(1): {np.mean(each) * 1e3:.2f} ms/solve, its={ij['iterations']}, relres={ij['relres']:.2e}")
+        del hj
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, head["iterations"], np)
+        cpu = oracle_cpu_baseline(A, b, restart, rtol, pv, psw, pin, head["iterations"], np, omega, gamma)
         log(f"[bench] cpu oracle: {cpu['value']:.1f} s extrapolated ({cpu['sample']})")
 
     out = {
@@ -339,6 +369,8 @@ def main():
         "forms": results,
         "kernels": kernels,
     }
+    if comparison:
+        out["comparison"] = comparison
     print(json.dumps(out), flush=True)
 
 
@@ -486,6 +518,25 @@ def bench_batched(args, g, torch, np):
     if not args.no_sequential:
         seq = sequential_pairs(g, torch, np, mats, dm, B, nrhs, restart, rtol, maxit, check, res)
     head = res["batched_fp32"]
+    comparison = None
+    if cfg == 3:
+        # Jacobi-Richardson, one sweep, as the paper's comparison on elasticity
+        hj = g.gs2_setup(dA, 1, 0, 1.0, g.FORWARD)
+        for _ in range(args.warmup):
+            x.zero_()
+            g.gmres_solve(dA, db, x, restart, rtol, maxit, g.PREC_JR, hj)
+        torch.cuda.synchronize()
+        each = []
+        for _ in range(args.steps):
+            x.zero_()
+            te = time.perf_counter()
+            ij = g.gmres_solve(dA, db, x, restart, rtol, maxit, g.PREC_JR, hj)
+            each.append(time.perf_counter() - te)
+        comparison = {"jr1": {"time_to_solution_s": float(np.mean(each)), "median_s": float(np.median(each)),
+                              "iterations": ij["iterations"], "converged": ij["converged"], "relres": ij["relres"]}}
+        log(f"[bench] JR(1): {np.mean(each) * 1e3:.2f} ms/solve, its={ij['iterations']}, relres={ij['relres']:.2e}")
+        del hj
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = batched_cpu_baseline(mats, rhs, res["batched_fp32"]["iterations"], restart, rtol, maxit, np)

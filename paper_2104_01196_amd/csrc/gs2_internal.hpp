@@ -287,7 +287,7 @@ inline size_t prec_bytes(int precision) { return precision == GS2_FP64 ? 8 : 4; 
 // profile.hip: optional per-launch HIP-event timing with algorithmic bytes
 enum ProfKid : int {
     PK_INNER = 0, PK_RESID, PK_FIRST_JR, PK_TRI, PK_SPMV_DOT, PK_CGS, PK_TRUE_RESID, PK_REDUCE, PK_GIVENS,
-    PK_SCALE, PK_UPDATE_X, PK_BATCHED, PK_MISC
+    PK_SCALE, PK_UPDATE_X, PK_BATCHED, PK_MISC, PK_SPMV
 };
 bool prof_on();
 // While one lives, the calling thread's launches are not recorded (the

@@ -447,6 +447,75 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, DiaAView D, int64
         part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
 }
 
+// The same pass split in two for the diagonal copy of A: k_dia_spmv writes
+// w = zs[j] (A z) straight from registers (one block of 64 R rows per
+// wavefront), then k_dot2 forms the dot products from w, u and Q.  Staging
+// the product in LDS ahead of the dot products, as the fused kernel does,
+// held the product to 58 % of the peak on the 192^3 problem (111 us) against
+// 77 % written directly (82 us); the split costs one more read of w.
+template <int R>
+__global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const double *__restrict__ z,
+                                                 double *__restrict__ w, const GState *__restrict__ st)
+{
+    using V2 = double __attribute__((ext_vector_type(2)));
+    if (st && st->done) return;
+    const double zsc = st ? st->zs[st->j] : 1.0;
+    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
+    const int64_t base = ((int64_t)blockIdx.x * (KT / WAVE) + wv) * (WAVE * R);
+    double acc[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k] = 0.0;
+    const bool rows_in = base < n;
+    for (int d = 0; d < A.ndiag && rows_in; ++d) {
+        const int o = A.off[d];
+        const double *__restrict__ vd = A.val + (int64_t)d * A.stride;
+        double a[R];
+        if constexpr (R == 2) {
+            const V2 t = __builtin_nontemporal_load((const V2 *)(vd + base + 2 * ln));
+            a[0] = t.x;
+            a[1] = t.y;
+        } else {
+            a[0] = __builtin_nontemporal_load(vd + base + ln);
+        }
+        const bool inside = base + o >= 0 && base + WAVE * R + o <= n;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            int64_t c = base + k * WAVE + ln + o;
+            if (!inside) c = c < 0 ? 0 : (c >= n ? n - 1 : c);
+            acc[k] += a[k] * z[c];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int64_t row = base + k * WAVE + ln;
+        if (row < n) w[row] = zsc * acc[k];
+    }
+}
+
+__global__ __launch_bounds__(KT) void k_dot2(int64_t n, const double *__restrict__ w, const double *__restrict__ V,
+                                             int64_t ldv, const GState *__restrict__ st, double *__restrict__ part,
+                                             int nb)
+{
+    __shared__ double wl[RB], ul[RB];
+    __shared__ double ra[MAXM + 2], rc[MAXM + 2], rn[3];
+    if (st->done) return;
+    const int j = st->j;
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int t = threadIdx.x;
+    const double zsc = st->zs[j];
+    const double *__restrict__ u = V + (int64_t)j * ldv;
+    for (int i = t; i < RB; i += KT) {
+        const int64_t row = r0 + i;
+        wl[i] = row < n ? w[row] : 0.0;
+        ul[i] = row < n ? zsc * u[row] : 0.0;
+    }
+    __syncthreads();
+    block_multidot<true>(n, r0, ul, wl, V, ldv, j, true, ra, rc, rn);
+    __syncthreads();
+    for (int k = t; k < 2 * j + 3; k += KT)
+        part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
+}
+
 // Pass 2 of step j: q_j = (u - Q a)/alpha over u's slot, w' = w - Q c - e q_j
 // into V[j+1], partial ||w'||^2.  Every workgroup derives alpha and e itself
 // (identical bits) and skips the pass when u has fallen into span(Q).
@@ -504,6 +573,68 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
     s = block_sum(s, red);
     if (t == 0) part[blockIdx.x] = s;
 }
+
+// The same pass with 16-byte loads for an even n (every column then starts
+// 16-byte aligned): each thread owns NP pairs of consecutive rows, so a
+// workgroup covers 2 NP KT rows and writes one partial.  Measured on the
+// 192^3 problem's basis (24 columns): 238 us against 273 us for the
+// one-row-per-load pass over 1024-row workgroups.
+template <int NP>
+__global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__restrict__ V, int64_t ldv,
+                                                          const GState *__restrict__ st, const double *__restrict__ w,
+                                                          double *__restrict__ part)
+{
+    using D2 = double __attribute__((ext_vector_type(2)));
+    __shared__ double as[MAXM + 2], cs_[MAXM + 2], red[KT / WAVE], sc[2];
+    if (st->done) return;
+    const int j = st->j, t = threadIdx.x;
+    for (int k = t; k < j; k += KT) {
+        as[k] = st->hA[k];
+        cs_[k] = st->hB[k];
+    }
+    __syncthreads();
+    double alpha, e, a2;
+    if (!reorth_scalars(st, j, as, cs_, sc, &alpha, &e, &a2)) return; // the same in every workgroup
+    const double ia = 1.0 / alpha, zsc = st->zs[j];
+    const int64_t r0 = (int64_t)blockIdx.x * (2 * NP * KT);
+    double s = 0.0;
+    double *__restrict__ u = V + (int64_t)j * ldv;
+    double *__restrict__ wn = V + (int64_t)(j + 1) * ldv;
+    // pairs past n are clamped to the last pair for loads and skipped for stores
+    int64_t rows[NP];
+    D2 aq[NP], aw[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int64_t row = r0 + 2 * (t + q * KT);
+        rows[q] = row < n ? row : n - 2;
+        aq[q] = zsc * *(const D2 *)&u[rows[q]];
+        aw[q] = *(const D2 *)&w[rows[q]];
+    }
+    for (int k = 0; k < j; ++k) {
+        const double *__restrict__ vk = V + (int64_t)k * ldv;
+        const double a = as[k], c = cs_[k];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const D2 x = __builtin_nontemporal_load((const D2 *)&vk[rows[q]]);
+            aq[q] -= a * x;
+            aw[q] -= c * x;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int64_t row = r0 + 2 * (t + q * KT);
+        if (row >= n) continue;
+        const D2 qv = aq[q] * ia;
+        const D2 wp = aw[q] - e * qv;
+        *(D2 *)&u[row] = qv;
+        *(D2 *)&wn[row] = wp;
+        s += wp.x * wp.x;
+        s += wp.y * wp.y;
+    }
+    s = block_sum(s, red);
+    if (t == 0) part[blockIdx.x] = s;
+}
+constexpr int UPD_PAIRS = 4; // pairs of rows per thread in k_dcgs_update_pairs
 
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
@@ -837,6 +968,9 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
         // a GS2 or JR pass: it needs only step j's partial sums and the state,
         // and the pass needs neither.  The last step's runs alone.
         const bool fuse_fin = orth == 0 && P && (kind == GS2_PREC_GS2 || kind == GS2_PREC_JR);
+        // the second basis pass loads pairs of rows when every column is 16-byte aligned
+        const bool pairs = n % 2 == 0;
+        const int nbu = pairs ? (int)((n + 2 * UPD_PAIRS * KT - 1) / (2 * UPD_PAIRS * KT)) : nb;
         auto enqueue_cycle = [&](hipStream_t cs) -> int {
             k_cycle_init<<<1, 64, 0, cs>>>(st, steps, rtol);
             k_scale0<<<gE, 256, 0, cs>>>(n, W->V, st);
@@ -846,9 +980,18 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                 double *zj = Zb + (int64_t)j * n;
                 const double vb = 8.0 * n * (j + 1);
                 if (orth == 0) { // delayed CGS2
-                    if (fuse_fin && j > 0) P->h.fin = Handle::FinJob{W->part, nb, st}; // closes step j-1
+                    if (fuse_fin && j > 0) P->h.fin = Handle::FinJob{W->part, nbu, st}; // closes step j-1
                     GS2_TRY(precondition(kind, P, vj, zj, n, st, cs));
-                    {
+                    if (K < 0) { // diagonal copy: the product, then the dot products
+                        {
+                            Prof pr(cs, PK_SPMV, spmv_b);
+                            const unsigned gD = (unsigned)((n + (int64_t)KT * -K - 1) / ((int64_t)KT * -K));
+                            if (K == -2) k_dia_spmv<2><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                            else k_dia_spmv<1><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                        }
+                        Prof pr(cs, PK_SPMV_DOT, vb + 8.0 * n);
+                        k_dot2<<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
+                    } else {
                         Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
                         hipStream_t s = cs;
                         GS2_SPMV_DISPATCH(K, k_spmv_dot2, gN, AS, AD, n, zj, W->w, W->V, n, st, W->part, nb);
@@ -859,11 +1002,14 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                     }
                     {
                         Prof pr(cs, PK_CGS, 8.0 * n * (j + 4));
-                        k_dcgs_update<<<gN, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
+                        if (pairs)
+                            k_dcgs_update_pairs<UPD_PAIRS><<<(unsigned)nbu, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
+                        else
+                            k_dcgs_update<<<gN, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
                     }
                     if (!fuse_fin || j == steps - 1) {
                         Prof pr(cs, PK_GIVENS, red_b);
-                        k_dcgs_finish<<<1, KT, 0, cs>>>(W->part, nb, st);
+                        k_dcgs_finish<<<1, KT, 0, cs>>>(W->part, nbu, st);
                     }
                     GS2_TRY_HIP(hipGetLastError());
                     continue;

@@ -768,11 +768,15 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
             } else {
                 float best = 1e30f;
                 int bestK = K;
+                // each candidate is timed on one inner pass over L and one residual pass
+                // over L and U, with the cache policy its stored size implies
                 for (int cand = 1; cand <= 16; cand *= 2) {
                     if (cand > 1 && cand > 2 * std::max(1.0, avg)) break;
                     GS2_TRY(build_part(h, h.L, PART_L, cand, A, sc, s));
+                    GS2_TRY(build_part(h, h.U, PART_U, cand, A, sc, s));
+                    h.L.nt = h.U.nt = h.L.stored_bytes() + h.U.stored_bytes() > NT_TRIANGLES_BYTES ? 1 : 0;
                     float ms = 0.f;
-                    GS2_TRY(time_inner_pass(h, s, &ms));
+                    GS2_TRY(time_inner_pass(h, s, &ms, true));
                     // a wider candidate must win by more than the timing noise
                     if (ms < 0.97f * best) { best = ms; bestK = cand; }
                 }

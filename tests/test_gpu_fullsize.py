@@ -1,19 +1,23 @@
-"""Full-size parity: the GPU's GMRES solves of the two large workloads against
+"""Full-size parity: the GPU's GMRES solves of the three large workloads against
 the CPU oracle's solves of the same seeded problems, stored by
 tests/golden/make_oracle_solves.py (which calls only the oracle; a full
 float64 oracle solve takes minutes at 192^3).
 
   laplace3d_128: 128^3 Laplacian, forward GS2(2 sweeps, 1 inner), GMRES(50)
   vardiff3d_192: 192^3 variable-coefficient diffusion, SGS2(1,1), GMRES(50)
+  elasticity_64: Q1 elasticity on 64^3 free nodes (786,432 rows), SGS2(1,3)
+                 with damping 0.7 and inner damping 0.5, GMRES(50)
 
-in the float64, float32 and scaled-float16 preconditioner forms.  Bars:
+in the float64, float32 and scaled-float16 preconditioner forms (float64
+only for elasticity, whose record has no reduced-precision solves).  Bars:
 iteration count within +-1 of the oracle's count for the same form (the
 oracle's own modified vs classical Gram-Schmidt counts are recorded next to
 it), true relative residual <= 1e-8 recomputed on the host, and the float64
 form's solution within 10x the distance between the oracle's two
 orthogonalisations' solutions (both are correct solutions to 1e-8; the GPU
-orthogonalises in a third order), checked on the full vector when the stored
-difference array is present and always on 4096 sampled entries."""
+orthogonalises in a third order), checked always on 4096 sampled entries
+stored in float64, and on the full vector when the stored difference array
+(float32, whose rounding is added to the bound) is present."""
 import json
 import os
 
@@ -42,7 +46,7 @@ def sample_idx(n, seed, count):
     return np.sort(rng.choice(n, size=min(count, n), replace=False))
 
 
-@pytest.mark.parametrize("wname", ["laplace3d_128", "vardiff3d_192"])
+@pytest.mark.parametrize("wname", ["laplace3d_128", "vardiff3d_192", "elasticity_64"])
 def test_full_size_gmres_matches_oracle(wname):
     rec = load(wname)
     p = config_problem(rec["config"], size=rec["size"])
@@ -59,7 +63,10 @@ def test_full_size_gmres_matches_oracle(wname):
     xo = p["x_true"] + np.load(dx_path).astype(np.float64) if os.path.exists(dx_path) else None
     x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
     for form, prec in FORMS:
-        h = g.gs2_setup(dA, rec["sweeps"], rec["inner"], 1.0, rec["variant"], precision=prec)
+        if form not in rec["solves"]:
+            continue
+        h = g.gs2_setup(dA, rec["sweeps"], rec["inner"], rec.get("omega", 1.0), rec["variant"], precision=prec,
+                        inner_damping=rec.get("gamma", 1.0))
         x.zero_()
         info = g.gmres_solve(dA, db, x, rec["restart"], rec["rtol"], 20000, g.PREC_GS2, h)
         xs = x.cpu().numpy()
@@ -73,7 +80,11 @@ def test_full_size_gmres_matches_oracle(wname):
             es = np.linalg.norm(xs[idx] - xo_s) / np.linalg.norm(xo_s)
             assert es <= bound, (es, bound)
             if xo is not None:
+                # the stored difference x_oracle - x_true is float32: its rounding (half a unit in
+                # the last place, relative 2^-24 of the difference) adds to the bound
+                qb = bound + 2.0 ** -23 * or64["rel_err_vs_x_true"]
                 e = np.linalg.norm(xs - xo) / np.linalg.norm(xo)
-                print(f"{wname} fp64: ||x - x_oracle|| / ||x_oracle|| = {e:.3e} (bound {bound:.3e})")
-                assert e <= bound, (e, bound)
+                print(f"{wname} fp64: ||x - x_oracle|| / ||x_oracle|| = {e:.3e} (bound {qb:.3e}); on the "
+                      f"sampled float64 entries {es:.3e} (bound {bound:.3e})")
+                assert e <= qb, (e, qb)
         del h
