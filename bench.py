@@ -61,6 +61,12 @@ def parse():
     ap.add_argument("--no-sequential", action="store_true",
                     help="config 5: skip the one-solve-per-pair comparison (e.g. under a kernel tracer)")
     ap.add_argument("--no-forms", action="store_true", help="skip the float32 / float16 preconditioner solves")
+    ap.add_argument("--schedule", default=None,
+                    help="force the sweep kernels' schedule per form instead of timing it at setup, e.g. "
+                         "'fp64=1/0/0,fp32=4/0/0,fp16_scaled=8/0/1' (diagonal layout, rows per lane / LDS staging "
+                         "0 or 1 / per-XCD row ranges 0 or 1; the solver's copy of A then uses the diagonal layout "
+                         "too): for counter runs, whose "
+                         "serialised launches would time the candidates differently")
     ap.add_argument("--profile", choices=["on", "off"], default="on",
                     help="per-kernel HIP-event timing of the float64 solves (a second pass of the same solves)")
     return ap.parse_args()
@@ -127,6 +133,21 @@ def oracle_reference(wname, x_true, np):
         return None, rec
     dx = np.load(dx_path)
     return x_true + dx.astype(np.float64), rec
+
+
+def forced_schedule(args, form, g):
+    """gs2_setup keyword arguments that force the schedule --schedule names
+    for this form (none: the setup times its candidates)."""
+    if not args.schedule:
+        return {}
+    for item in args.schedule.split(","):
+        name, val = item.split("=")
+        if name == form:
+            rows, lds, *xcd = val.split("/")
+            return {"format": g.FORMAT_DIA, "rows_per_lane": int(rows), "lds_staging": g.LDS_ON if int(lds) else g.LDS_OFF,
+                    "xcd_ranges": (g.XCD_RANGES if int(xcd[0]) else g.XCD_DISPATCH_ORDER) if xcd else g.XCD_AUTO,
+                    "spmv_format": g.FORMAT_DIA}
+    return {}
 
 
 def oracle_sampled_error(rec, xs, np):
@@ -228,7 +249,7 @@ def main():
     prof_solve_s = None
     for name, prec in forms:
         ts = time.time()
-        h = g.gs2_setup(dA, psw, pin, omega, pv, precision=prec, inner_damping=gamma)
+        h = g.gs2_setup(dA, psw, pin, omega, pv, precision=prec, inner_damping=gamma, **forced_schedule(args, name, g))
         torch.cuda.synchronize()
         setup_s = time.time() - ts
         lanes = g.gs2_handle_query(h)["lanes_per_row"]

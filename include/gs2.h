@@ -117,6 +117,10 @@ typedef struct gs2_options {
     int lds_staging;      /* diagonal layout: stage the source vector in LDS */
                           /* for offsets |col - row| <= 64: 0 = timed,       */
                           /* 1 = off, 2 = on                                 */
+    int xcd_ranges;       /* diagonal layout: each of the 8 XCDs walks its   */
+                          /* own contiguous range of workgroups (rows) or    */
+                          /* they take workgroups in dispatch order:         */
+                          /* 0 = timed, 1 = dispatch order, 2 = ranges       */
     int stagnation_cycles; /* gmres_solve with this handle: stop with        */
                            /* GS2_STAGNATED when the true residual has not   */
                            /* halved over this many restart cycles (0 =      */
@@ -307,18 +311,20 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * The schedule the setup chose for the GS2 / JR passes (host outputs, any
  * may be NULL): format GS2_FORMAT_SELL or GS2_FORMAT_DIA; lanes_per_row of
  * the sliced-ELL layout; rows_per_lane and vector_bytes (rows_per_lane x
- * value bytes, the width of one value load) and lds_staging (0/1) of the
- * diagonal layout (0 when it is not used); ndiag_l / ndiag_u, the diagonals
+ * value bytes, the width of one value load), lds_staging (0/1) and
+ * xcd_ranges (1 if each XCD walks its own range of rows, 0 for dispatch
+ * order) of the diagonal layout (0 when it is not used); ndiag_l / ndiag_u, the diagonals
  * of L and U (0 if the matrix does not qualify for the diagonal layout);
  * tuned = 1 if the choice was timed (or taken from the process-wide cache of
  * timed choices), 0 if it was forced or defaulted.  Candidates and timing:
  * the sliced-ELL layout at K = 1, 2, 4, ... lanes per row, then the diagonal
  * layout at every rows_per_lane whose load is 2 to 16 bytes, with and
- * without LDS staging; each is timed on one inner pass over L plus one
- * residual pass over L and U (Section 4 passes), the fastest kept.
+ * without LDS staging, with and without per-XCD ranges; each is timed on
+ * one inner pass over L plus one residual pass over L and U (Section 4
+ * passes), the fastest kept.
  */
 int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,
-                        int *lds_staging, int *ndiag_l, int *ndiag_u, int *tuned);
+                        int *lds_staging, int *xcd_ranges, int *ndiag_l, int *ndiag_u, int *tuned);
 
 /*
  * The layout gmres_solve used for its copy of A with this handle (host

@@ -230,6 +230,9 @@ struct Handle {
     // diagonal-interleaved copies of L and U, used by the GS2 / JR passes
     // when fmt == FMT_DIA (rows per lane dl.R, LDS staging if lds)
     int fmt = FMT_SELL, lds = 0, tuned = 0;
+    // diagonal passes: walk each XCD through its own contiguous range of
+    // workgroups (1) or dispatch them in order (0); timed with the rest
+    int remap = 1;
     Dia DL, DU;
     // hybrid relaxation: `blocks` contiguous row blocks; L and U then hold the
     // block-local triangles and E the couplings between blocks, applied to

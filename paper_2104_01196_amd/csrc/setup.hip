@@ -508,7 +508,7 @@ static int64_t count_total(const int32_t *tot, int64_t n, hipStream_t s, int *st
 // Schedules of the diagonal layout chosen by timing, per (size bucket, mean
 // row length, longest-row bucket, precision, diagonal counts).
 struct DiaChoice {
-    int fmt, R, lds;
+    int fmt, R, lds, remap;
 };
 static std::map<std::string, DiaChoice> g_dia_cache;
 
@@ -548,25 +548,30 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
     if (Rs.empty()) return GS2_ERR_ARG; // a forced rows-per-lane whose load is not 2..16 bytes
     if (o.lds_staging == 0) ldss = {0, 1};
     else ldss = {o.lds_staging == 2 ? 1 : 0};
+    std::vector<int> rms;
+    if (o.xcd_ranges == 0) rms = {1, 0};
+    else rms = {o.xcd_ranges == 2 ? 1 : 0};
     auto build = [&](int R) -> int {
         GS2_TRY(build_dia(h.DL, n, h.precision, 1, R, offL, nnzL, A, sc.lcnt, h.sl, h.sr, sc.err, s));
         GS2_TRY(build_dia(h.DU, n, h.precision, 0, R, offU, nnzU, A, sc.lcnt, h.sl, h.sr, sc.err, s));
         h.DL.nt = h.DU.nt = h.DL.stored_bytes() + h.DU.stored_bytes() > NT_TRIANGLES_BYTES ? 1 : 0;
         return GS2_OK;
     };
-    const bool timed = can_time && o.autotune && (o.format == GS2_FORMAT_AUTO || Rs.size() > 1 || ldss.size() > 1);
+    const bool timed = can_time && o.autotune &&
+                       (o.format == GS2_FORMAT_AUTO || Rs.size() > 1 || ldss.size() > 1 || rms.size() > 1);
     if (!timed) {
         if (o.format != GS2_FORMAT_DIA) return GS2_OK; // untimed automatic choice: sliced ELL
         GS2_TRY(build(Rs.back()));                       // forced: the widest load allowed
         h.fmt = FMT_DIA;
         h.lds = ldss.back();
+        h.remap = rms.front();
         return GS2_OK;
     }
     char kb[48];
-    std::snprintf(kb, sizeof kb, "_d%d_%d_f%d_r%d_s%d", h.DL.ndiag, h.DU.ndiag, o.format, o.rows_per_lane,
-                  o.lds_staging);
+    std::snprintf(kb, sizeof kb, "_d%d_%d_f%d_r%d_s%d_x%d", h.DL.ndiag, h.DU.ndiag, o.format, o.rows_per_lane,
+                  o.lds_staging, o.xcd_ranges);
     const std::string key = key_base + kb;
-    DiaChoice ch{FMT_SELL, 0, 0};
+    DiaChoice ch{FMT_SELL, 0, 0, 1};
     bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -584,17 +589,19 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
         }
         for (int R : Rs) {
             GS2_TRY(build(R));
-            for (int l : ldss) {
-                h.fmt = FMT_DIA;
-                h.lds = l;
-                float ms = 0.f;
-                GS2_TRY(time_inner_pass(h, s, &ms, true));
-                // a new candidate must win by more than the timing noise
-                if (ms < 0.97f * best) {
-                    best = ms;
-                    ch = DiaChoice{FMT_DIA, R, l};
+            for (int l : ldss)
+                for (int rm : rms) { // workgroups walked per XCD, or in dispatch order
+                    h.fmt = FMT_DIA;
+                    h.lds = l;
+                    h.remap = rm;
+                    float ms = 0.f;
+                    GS2_TRY(time_inner_pass(h, s, &ms, true));
+                    // a new candidate must win by more than the timing noise
+                    if (ms < 0.97f * best) {
+                        best = ms;
+                        ch = DiaChoice{FMT_DIA, R, l, rm};
+                    }
                 }
-            }
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_dia_cache[key] = ch;
@@ -610,6 +617,7 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
     if (!h.DL.val || h.DL.R != ch.R) GS2_TRY(build(ch.R));
     h.fmt = FMT_DIA;
     h.lds = ch.lds;
+    h.remap = ch.remap;
     return GS2_OK;
 }
 
@@ -847,6 +855,7 @@ void gs2_default_options(gs2_options *opt)
     opt->lds_staging = 0;
     opt->stagnation_cycles = 0;
     opt->spmv_format = GS2_FORMAT_AUTO;
+    opt->xcd_ranges = 0;
 }
 
 int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int variant, const gs2_options *opt,
@@ -869,7 +878,8 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
         return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
     if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_DIA || o.rows_per_lane < 0 || o.lds_staging < 0 ||
-        o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_DIA)
+        o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_DIA || o.xcd_ranges < 0 ||
+        o.xcd_ranges > 2)
         return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;
     if (!H) return GS2_ERR_NOMEM;
@@ -954,7 +964,7 @@ int gs2_handle_query(const gs2_handle *H, int64_t *n, int64_t *nnz_l, int64_t *n
 }
 
 int gs2_handle_schedule(const gs2_handle *H, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,
-                        int *lds_staging, int *ndiag_l, int *ndiag_u, int *tuned)
+                        int *lds_staging, int *xcd_ranges, int *ndiag_l, int *ndiag_u, int *tuned)
 {
     if (!H) return GS2_ERR_ARG;
     const Handle &h = H->h;
@@ -964,6 +974,7 @@ int gs2_handle_schedule(const gs2_handle *H, int *format, int *lanes_per_row, in
     if (rows_per_lane) *rows_per_lane = dia ? h.DL.R : 0;
     if (vector_bytes) *vector_bytes = dia ? h.DL.R * h.DL.val_bytes : 0;
     if (lds_staging) *lds_staging = dia ? h.lds : 0;
+    if (xcd_ranges) *xcd_ranges = dia ? h.remap : 0;
     if (ndiag_l) *ndiag_l = h.DL.ndiag;
     if (ndiag_u) *ndiag_u = h.DU.ndiag;
     if (tuned) *tuned = h.tuned;

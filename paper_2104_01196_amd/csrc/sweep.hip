@@ -354,6 +354,11 @@ struct DiaView {
     int off[DIA_MAX];
 };
 
+// compile-time flags of the diagonal passes: LDS staging of the source, and
+// the non-temporal cache policy for the values
+enum : int { DIA_FL_LDS = 1, DIA_FL_NT = 2 };
+static int dia_flags(const Handle &h, const Dia &D) { return (h.lds ? DIA_FL_LDS : 0) | (D.nt ? DIA_FL_NT : 0); }
+
 static DiaView dview(const Dia &D)
 {
     DiaView v;
@@ -385,12 +390,14 @@ struct RawVec<2> {
 };
 
 // The R values a lane holds on one diagonal, in one load.
-template <typename VT, typename AT, int R>
-__device__ __forceinline__ void dia_vals(const VT *__restrict__ p, int nt, AT (&a)[R])
+template <typename VT, typename AT, int R, bool NT>
+__device__ __forceinline__ void dia_vals(const VT *__restrict__ p, AT (&a)[R])
 {
     static_assert(R * sizeof(VT) >= 2 && R * sizeof(VT) <= 16, "one load of 2 to 16 bytes per lane");
     using RV = typename RawVec<R * (int)sizeof(VT)>::T;
-    const RV raw = nt ? __builtin_nontemporal_load((const RV *)p) : *(const RV *)p;
+    RV raw;
+    if constexpr (NT) raw = __builtin_nontemporal_load((const RV *)p);
+    else raw = *(const RV *)p;
     VT t[R];
     __builtin_memcpy(t, &raw, sizeof(t));
 #pragma unroll
@@ -403,15 +410,18 @@ __device__ __forceinline__ int clamp_col(int c, int n) { return c < 0 ? 0 : (c >
 // the lane's first value of diagonal 0.  src(c) loads the source at a column
 // c in [0, n); with LDS, xs holds the source over [base, base + span).
 // Columns need clamping only in the workgroups whose rows [w0, w0 + RB),
-// shifted by the offset, leave [0, n) (a uniform test per diagonal); the
-// others load at row + off directly, R loads 64 elements apart from one
-// address.
+// shifted by the offset, leave [0, n) (a uniform test per diagonal).  The
+// clamp is a select, not a branch, and the values' cache policy (NT) is a
+// compile-time choice, so the loop body is straight-line code and the
+// compiler issues every diagonal's loads before the first wait: with a branch
+// per diagonal it waited on each diagonal in turn (24 against 64 registers,
+// the float64 residual pass 107 against 83 us on the 192^3 problem).
 //
 // ND > 0: the triangle has exactly ND diagonals and the loop over them is
 // unrolled completely, so every diagonal's loads are in flight together
 // (measured for three diagonals in scaled float16, rows-per-lane 8: 24.9
 // against 29.9 us per inner pass over the 192^3 problem); ND = 0: any count.
-template <typename VT, typename AT, int R, bool LDS, int ND, typename Src>
+template <typename VT, typename AT, int R, bool LDS, bool NT, int ND, typename Src>
 __device__ __forceinline__ void dia_dots(const DiaView &T, int64_t pos, int w0, int rb, int n, Src src, const AT *xs,
                                          int base, AT (&acc)[R])
 {
@@ -422,17 +432,19 @@ __device__ __forceinline__ void dia_dots(const DiaView &T, int64_t pos, int w0, 
 #pragma unroll UNR
     for (int d = 0; d < nd; ++d) {
         AT a[R];
-        dia_vals<VT, AT, R>(val + (int64_t)d * T.stride + pos, T.nt, a);
+        dia_vals<VT, AT, R, NT>(val + (int64_t)d * T.stride + pos, a);
         const int o = T.off[d];
         if (LDS && o >= -DIA_HALO && o <= DIA_HALO) {
 #pragma unroll
             for (int k = 0; k < R; ++k) acc[k] += a[k] * xs[rb + k * WAVE + o - base];
-        } else if (w0 + o >= 0 && w0 + RB + o <= n) {
-#pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += a[k] * src(rb + o + k * WAVE);
         } else {
+            const bool inside = w0 + o >= 0 && w0 + RB + o <= n;
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += a[k] * src(clamp_col(rb + k * WAVE + o, n));
+            for (int k = 0; k < R; ++k) {
+                int c = rb + k * WAVE + o;
+                c = inside ? c : clamp_col(c, n);
+                acc[k] += a[k] * src(c);
+            }
         }
     }
 }
@@ -454,8 +466,8 @@ __device__ __forceinline__ int dia_stage(AT *xs, int base, int n, Src src, const
 // the other workgroups may then read the stop flag while that workgroup sets
 // it, and either value is correct: a pass that runs after the cycle has
 // converged only writes vectors the cycle no longer reads.
-template <typename VT, typename AT, int R, bool LDS, bool FIN, int ND>
-__global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict__ stop, int n, DiaView T,
+template <typename VT, typename AT, int R, int FL, bool FIN, int ND>
+__global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict__ stop, int remap, int n, DiaView T,
                                                   const AT *__restrict__ rh, const AT *__restrict__ gin,
                                                   const double *__restrict__ v, const double *__restrict__ sl, int rv,
                                                   int gv, int damp, AT w, AT gamma, int dst, AT *__restrict__ gout,
@@ -463,6 +475,7 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
                                                   const double *__restrict__ sr, const double *__restrict__ fpart,
                                                   int fnb, void *fst)
 {
+    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT;
     constexpr int RB = DIA_THREADS * R; // rows per workgroup
     constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
     if constexpr (FIN) {
@@ -472,7 +485,7 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
         }
     }
     const int sh = FIN ? 1 : 0;
-    const int wg = (int)xcd_remap(blockIdx.x - sh, gridDim.x - sh);
+    const int wg = remap ? (int)xcd_remap(blockIdx.x - sh, gridDim.x - sh) : (int)(blockIdx.x - sh);
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int w0 = wg * RB;
     const int rb = w0 + wv * (WAVE * R) + lane;
@@ -488,15 +501,15 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
         const int base = w0 - DIA_HALO;
         if (gv) {
             if (dia_stage<AT, SPAN>(xs, base, n, sv, stop, &sflag)) return;
-            dia_dots<VT, AT, R, true, ND>(T, pos, w0, rb, n, sv, xs, base, acc);
+            dia_dots<VT, AT, R, true, NT, ND>(T, pos, w0, rb, n, sv, xs, base, acc);
         } else {
             if (dia_stage<AT, SPAN>(xs, base, n, sg, stop, &sflag)) return;
-            dia_dots<VT, AT, R, true, ND>(T, pos, w0, rb, n, sg, xs, base, acc);
+            dia_dots<VT, AT, R, true, NT, ND>(T, pos, w0, rb, n, sg, xs, base, acc);
         }
     } else {
         if (stop && *stop) return;
-        if (gv) dia_dots<VT, AT, R, false, ND>(T, pos, w0, rb, n, sv, nullptr, 0, acc);
-        else dia_dots<VT, AT, R, false, ND>(T, pos, w0, rb, n, sg, nullptr, 0, acc);
+        if (gv) dia_dots<VT, AT, R, false, NT, ND>(T, pos, w0, rb, n, sv, nullptr, 0, acc);
+        else dia_dots<VT, AT, R, false, NT, ND>(T, pos, w0, rb, n, sg, nullptr, 0, acc);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -513,17 +526,19 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
 }
 
 // Outer residual pass on diagonal-interleaved triangles (as k_resid without
-// the hybrid term): rh = S_l v - cdiag xh - P xh [- Q xh].
-template <typename VT, typename AT, int R, bool LDS, int ND>
-__global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict__ stop, int n, DiaView P, DiaView Q, int two,
+// the hybrid term): rh = S_l v - cdiag xh - P xh [- Q xh].  ND > 0 kernels
+// always add Q.
+template <typename VT, typename AT, int R, int FL, int ND>
+__global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict__ stop, int remap, int n, DiaView P, DiaView Q, int two,
                                                   const AT *__restrict__ xh, const double *__restrict__ v,
                                                   const double *__restrict__ sl, AT cdiag, AT w, int dst,
                                                   AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
                                                   const double *__restrict__ sr)
 {
+    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT;
     constexpr int RB = DIA_THREADS * R;
     constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
-    const int wg = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int wg = remap ? (int)xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
     const int w0 = wg * RB;
     const int rb = w0 + wv * (WAVE * R) + lane;
@@ -538,14 +553,14 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
         __shared__ int sflag;
         const int base = w0 - DIA_HALO;
         if (dia_stage<AT, SPAN>(xs, base, n, sx, stop, &sflag)) return;
-        dia_dots<VT, AT, R, true, ND>(P, pos, w0, rb, n, sx, xs, base, acc);
-        if (two) dia_dots<VT, AT, R, true, ND>(Q, pos, w0, rb, n, sx, xs, base, acc);
+        dia_dots<VT, AT, R, true, NT, ND>(P, pos, w0, rb, n, sx, xs, base, acc);
+        if (ND > 0 || two) dia_dots<VT, AT, R, true, NT, ND>(Q, pos, w0, rb, n, sx, xs, base, acc);
 #pragma unroll
         for (int k = 0; k < R; ++k) own[k] = xs[rb + k * WAVE - base];
     } else {
         if (stop && *stop) return;
-        dia_dots<VT, AT, R, false, ND>(P, pos, w0, rb, n, sx, nullptr, 0, acc);
-        if (two) dia_dots<VT, AT, R, false, ND>(Q, pos, w0, rb, n, sx, nullptr, 0, acc);
+        dia_dots<VT, AT, R, false, NT, ND>(P, pos, w0, rb, n, sx, nullptr, 0, acc);
+        if (ND > 0 || two) dia_dots<VT, AT, R, false, NT, ND>(Q, pos, w0, rb, n, sx, nullptr, 0, acc);
 #pragma unroll
         for (int k = 0; k < R; ++k) own[k] = xh[clamp_col(rb + k * WAVE, n)];
     }
@@ -628,82 +643,108 @@ struct Launch {
     static double dia_bytes(const Dia &D) { return (double)D.nnz * sizeof(VT); }
     static const Dia &dia_of(const Handle &h, const Sell &T) { return &T == &h.L ? h.DL : h.DU; }
 
-    template <int R, bool LDS>
+    template <int R, int FL>
     static void dia_inner_r(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
                             int gv, int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
     {
         const int damp = h.gamma != 1.0;
         const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R)) + (fj.st ? 1u : 0u);
+        const DiaView dv = dview(T);
+        const int n = (int)h.n;
         // three diagonals per triangle (7-point stencils): the loop over them unrolled
         if (T.ndiag == 3) {
             if (fj.st)
-                k_dia_inner<VT, AT, R, LDS, true, 3><<<grid, DIA_THREADS, 0, s>>>(
-                    h.stop, (int)h.n, dview(T), rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout,
-                    xh, z, h.sr, fj.part, fj.nb, fj.st);
+                k_dia_inner<VT, AT, R, FL, true, 3><<<grid, DIA_THREADS, 0, s>>>(
+                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
+                    h.sr, fj.part, fj.nb, fj.st);
             else
-                k_dia_inner<VT, AT, R, LDS, false, 3><<<grid, DIA_THREADS, 0, s>>>(
-                    h.stop, (int)h.n, dview(T), rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout,
-                    xh, z, h.sr, nullptr, 0, nullptr);
+                k_dia_inner<VT, AT, R, FL, false, 3><<<grid, DIA_THREADS, 0, s>>>(
+                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
+                    h.sr, nullptr, 0, nullptr);
             return;
         }
         if (fj.st)
-            k_dia_inner<VT, AT, R, LDS, true, 0><<<grid, DIA_THREADS, 0, s>>>(
-                h.stop, (int)h.n, dview(T), rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
-                z, h.sr, fj.part, fj.nb, fj.st);
+            k_dia_inner<VT, AT, R, FL, true, 0><<<grid, DIA_THREADS, 0, s>>>(
+                h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
+                h.sr, fj.part, fj.nb, fj.st);
         else
-            k_dia_inner<VT, AT, R, LDS, false, 0><<<grid, DIA_THREADS, 0, s>>>(
-                h.stop, (int)h.n, dview(T), rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
-                z, h.sr, nullptr, 0, nullptr);
+            k_dia_inner<VT, AT, R, FL, false, 0><<<grid, DIA_THREADS, 0, s>>>(
+                h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
+                h.sr, nullptr, 0, nullptr);
     }
-    template <bool LDS>
+    template <int R>
+    static void dia_inner_f(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
+                            int gv, int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
+    {
+        switch (dia_flags(h, T)) {
+        case 0: dia_inner_r<R, 0>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 1: dia_inner_r<R, 1>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 2: dia_inner_r<R, 2>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        default: dia_inner_r<R, 3>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        }
+    }
     static void dia_inner_l(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
                             int gv, int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
     {
         switch (T.R) {
         case 1:
-            if constexpr (r_ok<1>()) dia_inner_r<1, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            if constexpr (r_ok<1>()) dia_inner_f<1>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
             break;
         case 2:
-            if constexpr (r_ok<2>()) dia_inner_r<2, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            if constexpr (r_ok<2>()) dia_inner_f<2>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
             break;
         case 4:
-            if constexpr (r_ok<4>()) dia_inner_r<4, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            if constexpr (r_ok<4>()) dia_inner_f<4>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
             break;
         default:
-            if constexpr (r_ok<8>()) dia_inner_r<8, LDS>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            if constexpr (r_ok<8>()) dia_inner_f<8>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
             break;
         }
     }
-    template <int R, bool LDS>
+    template <int R, int FL>
     static void dia_resid_r(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
                             AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
     {
         const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R));
-        if (P.ndiag == 3 && (!Q || Q->ndiag == 3))
-            k_dia_resid<VT, AT, R, LDS, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, (int)h.n, dview(P),
-                                                                        Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
-                                                                        h.sl, cdiag, w, dst, rh, xout, z, h.sr);
+        const int n = (int)h.n;
+        // ND = 3 kernels always add both triangles (no branch on `two`, so the
+        // loads of all six diagonals are issued together); one triangle (the
+        // compact form's residual) takes the general kernel
+        if (P.ndiag == 3 && Q && Q->ndiag == 3)
+            k_dia_resid<VT, AT, R, FL, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
+                                                                       Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
+                                                                       h.sl, cdiag, w, dst, rh, xout, z, h.sr);
         else
-            k_dia_resid<VT, AT, R, LDS, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, (int)h.n, dview(P),
-                                                                        Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
-                                                                        h.sl, cdiag, w, dst, rh, xout, z, h.sr);
+            k_dia_resid<VT, AT, R, FL, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
+                                                                       Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
+                                                                       h.sl, cdiag, w, dst, rh, xout, z, h.sr);
     }
-    template <bool LDS>
+    template <int R>
+    static void dia_resid_f(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
+                            AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
+    {
+        switch (dia_flags(h, P)) {
+        case 0: dia_resid_r<R, 0>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
+        case 1: dia_resid_r<R, 1>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
+        case 2: dia_resid_r<R, 2>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
+        default: dia_resid_r<R, 3>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
+        }
+    }
     static void dia_resid_l(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
                             AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
     {
         switch (P.R) {
         case 1:
-            if constexpr (r_ok<1>()) dia_resid_r<1, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<1>()) dia_resid_f<1>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
             break;
         case 2:
-            if constexpr (r_ok<2>()) dia_resid_r<2, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<2>()) dia_resid_f<2>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
             break;
         case 4:
-            if constexpr (r_ok<4>()) dia_resid_r<4, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<4>()) dia_resid_f<4>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
             break;
         default:
-            if constexpr (r_ok<8>()) dia_resid_r<8, LDS>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<8>()) dia_resid_f<8>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
             break;
         }
     }
@@ -749,8 +790,7 @@ struct Launch {
         if (h.fmt == FMT_DIA) {
             const Dia &D = dia_of(h, T);
             Prof pr(s, PK_INNER, dia_bytes(D) + (double)h.n * (src + dst_bytes(dst)));
-            if (h.lds) dia_inner_l<true>(h, D, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
-            else dia_inner_l<false>(h, D, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
+            dia_inner_l(h, D, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj);
             return;
         }
         Prof pr(s, PK_INNER, tri_bytes(T) + (double)h.n * (src + dst_bytes(dst)));
@@ -781,8 +821,7 @@ struct Launch {
             const Dia &DP = dia_of(h, P);
             const Dia *DQ = Q ? &dia_of(h, *Q) : nullptr;
             Prof pr(s, PK_RESID, dia_bytes(DP) + (DQ ? dia_bytes(*DQ) : 0.0) + (double)h.n * (16.0 + sizeof(AT) + out));
-            if (h.lds) dia_resid_l<true>(h, DP, DQ, xh, v, cdiag, w, dst, rh, xout, z, s);
-            else dia_resid_l<false>(h, DP, DQ, xh, v, cdiag, w, dst, rh, xout, z, s);
+            dia_resid_l(h, DP, DQ, xh, v, cdiag, w, dst, rh, xout, z, s);
             return;
         }
         Prof pr(s, PK_RESID,

@@ -25,6 +25,7 @@ FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
 FP64, FP32, FP16_SCALED = 0, 1, 2
 FORMAT_AUTO, FORMAT_SELL, FORMAT_DIA = 0, 1, 2
 LDS_AUTO, LDS_OFF, LDS_ON = 0, 1, 2
+XCD_AUTO, XCD_DISPATCH_ORDER, XCD_RANGES = 0, 1, 2
 PREC_NONE, PREC_GS2, PREC_JR, PREC_GS_TRISOLVE, PREC_MTGS = 0, 1, 2, 3, 4
 
 
@@ -45,7 +46,7 @@ class Options(C.Structure):
                 ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int), ("blocks", C.c_int),
                 ("local_sweeps", C.c_int), ("team_rows", C.c_int), ("team_wait_ms", C.c_int),
                 ("format", C.c_int), ("rows_per_lane", C.c_int), ("lds_staging", C.c_int),
-                ("stagnation_cycles", C.c_int), ("spmv_format", C.c_int)]
+                ("xcd_ranges", C.c_int), ("stagnation_cycles", C.c_int), ("spmv_format", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -83,7 +84,7 @@ def lib():
         i64p = C.POINTER(C.c_int64)
         ip = C.POINTER(C.c_int)
         L.gs2_handle_query.argtypes = [vp, i64p, i64p, i64p, i64p, ip, ip, ip]
-        L.gs2_handle_schedule.argtypes = [vp, ip, ip, ip, ip, ip, ip, ip, ip]
+        L.gs2_handle_schedule.argtypes = [vp, ip, ip, ip, ip, ip, ip, ip, ip, ip]
         L.gs2_gmres_schedule.argtypes = [vp, ip, ip, ip, ip, ip]
         L.gs2_inner_residuals.argtypes = [vp, vp, i, C.POINTER(C.c_double), vp]
         L.gs2_inner_residuals_noalloc.argtypes = [vp, vp, i, vp, vp]
@@ -181,10 +182,12 @@ class Handle:
 def gs2_setup(A: DeviceCSR, sweeps=1, inner=1, damping=1.0, variant=FORWARD, precision=FP64, inner_damping=1.0,
               compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0, blocks=1,
               local_sweeps=1, format=FORMAT_AUTO, rows_per_lane=0, lds_staging=0, stagnation_cycles=0,
-              spmv_format=FORMAT_AUTO, stream=None) -> Handle:
-    opt = Options(precision, inner_damping, int(compact), int(build_levels), int(autotune), lanes_per_row, 0,
-                  orthogonalization, blocks, local_sweeps, 0, 0, format, rows_per_lane, lds_staging,
-                  stagnation_cycles, spmv_format)
+              spmv_format=FORMAT_AUTO, xcd_ranges=0, stream=None) -> Handle:
+    opt = Options(precision=precision, inner_damping=inner_damping, compact=int(compact),
+                  build_levels=int(build_levels), autotune=int(autotune), lanes_per_row=lanes_per_row,
+                  orthogonalization=orthogonalization, blocks=blocks, local_sweeps=local_sweeps, format=format,
+                  rows_per_lane=rows_per_lane, lds_staging=lds_staging, xcd_ranges=xcd_ranges,
+                  stagnation_cycles=stagnation_cycles, spmv_format=spmv_format)
     out = C.c_void_p()
     d = A.desc()
     st = lib().gs2_setup(C.byref(d), sweeps, inner, damping, variant, C.byref(opt), _stream(stream), C.byref(out))
@@ -276,11 +279,12 @@ def gs2_handle_query(h: Handle) -> dict:
 
 
 def gs2_handle_schedule(h: Handle) -> dict:
-    v = [C.c_int() for _ in range(8)]
+    v = [C.c_int() for _ in range(9)]
     st = lib().gs2_handle_schedule(h.ptr, *[C.byref(x) for x in v])
     if st != OK:
         raise Gs2Error(st, "gs2_handle_schedule")
-    keys = ["format", "lanes_per_row", "rows_per_lane", "vector_bytes", "lds_staging", "ndiag_l", "ndiag_u", "tuned"]
+    keys = ["format", "lanes_per_row", "rows_per_lane", "vector_bytes", "lds_staging", "xcd_ranges", "ndiag_l",
+            "ndiag_u", "tuned"]
     return {k: x.value for k, x in zip(keys, v)}
 
 

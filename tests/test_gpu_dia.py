@@ -1,5 +1,6 @@
 """GPU parity of the diagonal-interleaved layout of the triangles (every rows-
-per-lane candidate, with and without LDS staging of the source vector)
+per-lane candidate, with and without LDS staging of the source vector, with
+workgroups walked in per-XCD ranges and in dispatch order)
 against the CPU oracle, through the C ABI.  Same bars as the sliced-ELL
 applies (tests/test_gpu_parity.py): 1e-12 per half sweep in float64 (the
 scaled-space kernels and the textbook oracle differ only in rounding
@@ -64,23 +65,25 @@ def schedules():
     for prec, Rs in R_OF.items():
         for R in Rs:
             for lds in (g.LDS_OFF, g.LDS_ON):
-                yield prec, R, lds
+                for xcd in (g.XCD_RANGES, g.XCD_DISPATCH_ORDER):
+                    yield prec, R, lds, xcd
 
 
 CASES = [(g.FORWARD, 2, 1, 1.0), (g.SYMMETRIC, 1, 2, 0.9), (g.BACKWARD, 1, 3, 0.8), (g.FORWARD, 3, 0, 0.7)]
 
 
 @pytest.mark.parametrize("name", list(MATS))
-@pytest.mark.parametrize("prec,R,lds", list(schedules()))
-def test_dia_apply_every_schedule(name, prec, R, lds):
+@pytest.mark.parametrize("prec,R,lds,xcd", list(schedules()))
+def test_dia_apply_every_schedule(name, prec, R, lds, xcd):
     A, dA = mat(name)
     v = np.random.default_rng(11).standard_normal(A.n)
     z = torch.empty(A.n, dtype=torch.float64, device=DEV)
     for variant, sweeps, inner, w in CASES:
         h = g.gs2_setup(dA, sweeps, inner, w, variant, precision=prec, format=g.FORMAT_DIA, rows_per_lane=R,
-                        lds_staging=lds)
+                        lds_staging=lds, xcd_ranges=xcd)
         sch = g.gs2_handle_schedule(h)
-        assert (sch["format"], sch["rows_per_lane"], sch["lds_staging"]) == (g.FORMAT_DIA, R, lds == g.LDS_ON)
+        assert (sch["format"], sch["rows_per_lane"], sch["lds_staging"], sch["xcd_ranges"]) == \
+            (g.FORMAT_DIA, R, lds == g.LDS_ON, xcd == g.XCD_RANGES)
         assert sch["vector_bytes"] == R * {g.FP64: 8, g.FP32: 4, g.FP16_SCALED: 2}[prec]
         g.gs2_apply(h, dev(v), z)
         ref = reference(A, v, prec, variant, sweeps, inner, w)
@@ -108,8 +111,9 @@ def test_dia_damping_compact_and_jr(name, lds):
 
 
 @pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
-@pytest.mark.parametrize("lds", [g.LDS_OFF, g.LDS_ON])
-def test_dia_gmres_iterations(prec, lds):
+@pytest.mark.parametrize("lds,xcd", [(g.LDS_OFF, g.XCD_RANGES), (g.LDS_ON, g.XCD_RANGES),
+                                     (g.LDS_OFF, g.XCD_DISPATCH_ORDER)])
+def test_dia_gmres_iterations(prec, lds, xcd):
     """GMRES(30) with an SGS2(1,1) preconditioner on the diagonal layout: the
     first preconditioner pass of each step also closes the previous step
     (the fused variant of the pass)."""
@@ -117,7 +121,8 @@ def test_dia_gmres_iterations(prec, lds):
     b = np.random.default_rng(13).standard_normal(A.n)
     _, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=1,
                          precision=prec)
-    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, precision=prec, format=g.FORMAT_DIA, lds_staging=lds)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, precision=prec, format=g.FORMAT_DIA, lds_staging=lds,
+                    xcd_ranges=xcd)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
     info = g.gmres_solve(dA, dev(b), x, 30, 1e-8, 5000, g.PREC_GS2, h)
     assert info["converged"] and info["relres"] <= 1e-8

@@ -10,10 +10,11 @@ oracle result):
     2e-5 / 1e-4 (tens of float32 unit roundoffs; FP16 allows a rare
     one-ulp difference in a stored value).
   GMRES: iteration count within +-1 of the oracle (MGS vs the GPU's CGS2
-    with delayed reorthogonalisation); for runs of hundreds of steps over
-    many restarts, where rounding differences between the two
-    orthogonalisations accumulate, 1% of the count; true residual <= rtol,
-    solutions agree to what the tolerance allows.
+    with delayed reorthogonalisation); true residual <= rtol, solutions
+    agree to what the tolerance allows.
+  CG without a preconditioner on the four-decade variable-coefficient
+    problem: twice the oracle's own spread under reorderings of the
+    summation (measured in the test).
 """
 import numpy as np
 import pytest
@@ -421,8 +422,8 @@ def test_gmres_elasticity_damping_study(prec, kind, inner, w, sweeps):
     """The elasticity study of Section 8 (tab:ela3d-omega) on a reduced
     config-3 problem (6^3 free nodes x 3 dof): symmetric GS2 with damping
     0.7 and several inner sweeps, and JR with 1 or 3 sweeps, against the
-    oracle's iteration counts (runs of 80-300 steps over several restarts:
-    bar 1% of the count, at least 1)."""
+    oracle's iteration counts (runs of 80-300 steps over several restarts,
+    where the oracle's own MGS and CGS2 counts agree exactly: bar +-1)."""
     p = config_problem(3, size=6)
     A, b = p["A"], p["b"]
     okw = dict(variant=g.SYMMETRIC, sweeps=sweeps, inner=inner, omega=w) if prec == "gs2" else \
@@ -433,8 +434,7 @@ def test_gmres_elasticity_damping_study(prec, kind, inner, w, sweeps):
     h = g.gs2_setup(dA, sweeps, max(inner, 1), w, g.SYMMETRIC)
     x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
     info = g.gmres_solve(dA, dev(b), x, 50, 1e-8, 1500, kind, h)
-    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= max(1, io["iterations"] // 100), \
-        (info, io)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
     xh = host(x)
     assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
 
@@ -600,8 +600,25 @@ def test_pcg_matches_oracle(prec, kind, kw, cfg, size):
     assert info["converged"] and io["converged"]
     # Unpreconditioned CG on the variable-coefficient problem (kappa spans four
     # decades) loses orthogonality early, and the resulting convergence delay
-    # depends on rounding order; there the bar is 2% of the count, elsewhere +-1.
-    slack = max(1, int(0.02 * io["iterations"])) if kind == g.PREC_NONE else 1
+    # depends on rounding order.  The oracle's own spread under a change of
+    # summation order is measured here: CG on P A P^T x' = P b for a few
+    # permutations P (the same iterates in exact arithmetic, every dot product
+    # and row sum in another order; 430..433 steps against 432 at 14^3).  The
+    # GPU is held to twice that spread; the preconditioned runs, whose oracle
+    # counts do not move, to +-1.
+    slack = 1
+    if kind == g.PREC_NONE:
+        counts = [io["iterations"]]
+        rng = np.random.default_rng(3)
+        S = A.to_scipy().tocsr()
+        for t in range(3):
+            perm = rng.permutation(A.n) if t else np.arange(A.n)[::-1].copy()
+            P = S[perm][:, perm].tocsr()
+            P.sort_indices()
+            Ap = CSR(A.n, P.indptr.astype(np.int32), P.indices.astype(np.int32), P.data.astype(np.float64))
+            counts.append(oracle.pcg(Ap, b[perm], rtol=1e-8, prec="none")[1]["iterations"])
+        slack = max(1, 2 * (max(counts) - min(counts)))
+        print(f"CG, no preconditioner: oracle counts under reordering {counts}, GPU {info['iterations']}")
     assert abs(info["iterations"] - io["iterations"]) <= slack, (info, io)
     xh = host(x)
     assert np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b) <= 1e-8
