@@ -453,7 +453,13 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, DiaAView D, int64
 // the product in LDS ahead of the dot products, as the fused kernel does,
 // held the product to 58 % of the peak on the 192^3 problem (111 us) against
 // 77 % written directly (82 us); the split costs one more read of w.
-template <int R>
+//
+// ND > 0: exactly ND diagonals (7 for 7-point stencils), the loop unrolled
+// completely so that every diagonal's loads are issued before the first
+// wait.  Every launched wavefront loads in bounds (the copy is padded to
+// 1024-row workgroups and a clamped column only meets a stored zero); rows
+// past n are not written.
+template <int R, int ND>
 __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const double *__restrict__ z,
                                                  double *__restrict__ w, const GState *__restrict__ st)
 {
@@ -465,8 +471,10 @@ __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const do
     double acc[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) acc[k] = 0.0;
-    const bool rows_in = base < n;
-    for (int d = 0; d < A.ndiag && rows_in; ++d) {
+    const int nd = ND > 0 ? ND : A.ndiag;
+    constexpr int UNR = ND > 0 ? ND : 1;
+#pragma unroll UNR
+    for (int d = 0; d < nd; ++d) {
         const int o = A.off[d];
         const double *__restrict__ vd = A.val + (int64_t)d * A.stride;
         double a[R];
@@ -481,7 +489,8 @@ __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const do
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             int64_t c = base + k * WAVE + ln + o;
-            if (!inside) c = c < 0 ? 0 : (c >= n ? n - 1 : c);
+            const int64_t cc = c < 0 ? 0 : (c >= n ? n - 1 : c);
+            c = inside ? c : cc;
             acc[k] += a[k] * z[c];
         }
     }
@@ -986,8 +995,13 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                         {
                             Prof pr(cs, PK_SPMV, spmv_b);
                             const unsigned gD = (unsigned)((n + (int64_t)KT * -K - 1) / ((int64_t)KT * -K));
-                            if (K == -2) k_dia_spmv<2><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
-                            else k_dia_spmv<1><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                            if (AD.ndiag == 7) {
+                                if (K == -2) k_dia_spmv<2, 7><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                                else k_dia_spmv<1, 7><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                            } else {
+                                if (K == -2) k_dia_spmv<2, 0><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                                else k_dia_spmv<1, 0><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                            }
                         }
                         Prof pr(cs, PK_SPMV_DOT, vb + 8.0 * n);
                         k_dot2<<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
