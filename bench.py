@@ -530,7 +530,8 @@ def bench_batched(args, g, torch, np):
         res[name] = {"time_s": float(np.mean(each)), "median_s": float(np.median(each)), "min_s": min(each),
                      "max_s": max(each), "setup_s": setup_s, "status": st, "iterations": its,
                      "iterations_max": max(its),
-                     "iterations_mean": float(np.mean(its)), "worst_relres_true": check(X.cpu().numpy())}
+                     "iterations_mean": float(np.mean(its)), "worst_relres_true": check(X.cpu().numpy()),
+                     "schedule": g.gs2_batched_schedule(bh)}
         log(f"[bench] {name}: {res[name]['time_s'] * 1e3:.1f} ms for all {len(its)} pairs, its mean "
             f"{res[name]['iterations_mean']:.0f} max {max(its)}, worst relres {res[name]['worst_relres_true']:.2e}")
         del bh
@@ -539,25 +540,6 @@ def bench_batched(args, g, torch, np):
     if not args.no_sequential:
         seq = sequential_pairs(g, torch, np, mats, dm, B, nrhs, restart, rtol, maxit, check, res)
     head = res["batched_fp32"]
-    comparison = None
-    if cfg == 3:
-        # Jacobi-Richardson, one sweep, as the paper's comparison on elasticity
-        hj = g.gs2_setup(dA, 1, 0, 1.0, g.FORWARD)
-        for _ in range(args.warmup):
-            x.zero_()
-            g.gmres_solve(dA, db, x, restart, rtol, maxit, g.PREC_JR, hj)
-        torch.cuda.synchronize()
-        each = []
-        for _ in range(args.steps):
-            x.zero_()
-            te = time.perf_counter()
-            ij = g.gmres_solve(dA, db, x, restart, rtol, maxit, g.PREC_JR, hj)
-            each.append(time.perf_counter() - te)
-        comparison = {"jr1": {"time_to_solution_s": float(np.mean(each)), "median_s": float(np.median(each)),
-                              "iterations": ij["iterations"], "converged": ij["converged"], "relres": ij["relres"]}}
-        log(f"[bench] JR(1): {np.mean(each) * 1e3:.2f} ms/solve, its={ij['iterations']}, relres={ij['relres']:.2e}")
-        del hj
-
     cpu = None
     if not args.no_cpu_baseline:
         cpu = batched_cpu_baseline(mats, rhs, res["batched_fp32"]["iterations"], restart, rtol, maxit, np)

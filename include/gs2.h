@@ -371,6 +371,15 @@ int gs2_setup_batched(const gs2_csr *As, int nsys, int sweeps, int inner, double
 int gmres_solve_batched(gs2_batch *bh, int nrhs, const double *B, double *X, double rtol, int maxit,
                         gs2_solve_info *infos, void *stream);
 
+/*
+ * The schedule gs2_setup_batched chose (host outputs, any may be NULL): the
+ * lanes per row of the systems' triangles (1 or 4; timed against each other
+ * when opt->lanes_per_row is 0, autotune is on and 4 is at most twice the
+ * longest mean row of a triangle), right-hand sides per work item, and
+ * tuned = 1 if they were chosen by timing one restart cycle of every item.
+ */
+int gs2_batched_schedule(const gs2_batch *bh, int *lanes_per_row, int *rhs_per_item, int *tuned);
+
 void gs2_destroy_batched(gs2_batch *bh);
 
 /* ----------------------------------------------------------- measurement

@@ -1093,6 +1093,7 @@ static BatchedKernel pick_kernel(int prec, int R, int K)
 
 struct Batch {
     int nsys = 0, m = 0, nrhs = 0, R = 1, K = 1, precision = GS2_FP32;
+    int tuned = 0; // lanes per row and right-hand sides per item chosen by timing
     std::vector<Handle *> hs;
     std::vector<int64_t> sizes;
     int32_t *rp = nullptr, *ci = nullptr;
@@ -1246,54 +1247,81 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
         maxslices_rows = std::max<int64_t>(maxslices_rows, As[i].n);
         if (As[i].n) maxavg = std::max(maxavg, (double)(As[i].nnz - As[i].n) / (2.0 * As[i].n));
     }
-    b.K = (o.lanes_per_row == 4 || (o.lanes_per_row == 0 && maxavg > 12.0)) ? 4 : 1;
-    gs2_options so = o;
-    so.autotune = 0;
-    so.build_levels = 0;
-    so.lanes_per_row = b.K;
+    // lanes per row of the systems' triangles: 1 or 4 (timed below unless forced)
+    std::vector<int> kcands;
+    if (o.lanes_per_row == 1 || o.lanes_per_row == 4) kcands = {o.lanes_per_row};
+    else if (o.lanes_per_row != 0) return GS2_ERR_ARG;
+    else if (!o.autotune) kcands = {maxavg > 12.0 ? 4 : 1};
+    else {
+        kcands = {1};
+        if (4 <= 2.0 * std::max(1.0, maxavg)) kcands.push_back(4); // as the single-system tuner: K <= 2 x mean row
+    }
     GS2_TRY_HIP(hipMalloc(&b.rp, sizeof(int32_t) * (rows + nsys)));
     GS2_TRY_HIP(hipMalloc(&b.ci, sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
     GS2_TRY_HIP(hipMalloc(&b.va, sizeof(double) * std::max<int64_t>(nnz, 1)));
-    std::vector<BSys> sys(nsys);
-    int64_t roff = 0, noff = 0, row0 = 0;
-    for (int i = 0; i < nsys; ++i) {
-        Handle *h = new (std::nothrow) Handle;
-        if (!h) return GS2_ERR_NOMEM;
-        b.hs.push_back(h);
-        h->n = As[i].n;
-        h->sweeps = sweeps;
-        h->inner = inner;
-        h->variant = variant;
-        h->omega = damping;
-        h->gamma = o.inner_damping;
-        h->precision = o.precision;
-        GS2_TRY(setup_handle(*h, As[i], so, s, false));
-        b.sizes.push_back(As[i].n);
-        GS2_TRY_HIP(hipMemcpyAsync(b.rp + roff, As[i].rowptr, sizeof(int32_t) * (As[i].n + 1), hipMemcpyDeviceToDevice, s));
-        GS2_TRY_HIP(hipMemcpyAsync(b.ci + noff, As[i].colind, sizeof(int32_t) * As[i].nnz, hipMemcpyDeviceToDevice, s));
-        GS2_TRY_HIP(hipMemcpyAsync(b.va + noff, As[i].val, sizeof(double) * As[i].nnz, hipMemcpyDeviceToDevice, s));
-        BSys &d = sys[i];
-        d.n = h->n;
-        d.nslices = h->L.nslices;
-        d.Lsp = h->L.slice_ptr;
-        d.Usp = h->U.slice_ptr;
-        d.Lcol = h->L.col;
-        d.Ucol = h->U.col;
-        d.Lval = h->L.val;
-        d.Uval = h->U.val;
-        d.sl = h->sl;
-        d.sr = h->sr;
-        d.rp = b.rp + roff;
-        d.ci = b.ci + noff;
-        d.va = b.va + noff;
-        d.row0 = row0;
-        roff += As[i].n + 1;
-        noff += As[i].nnz;
-        row0 += As[i].n;
+    {
+        int64_t roff = 0, noff = 0;
+        for (int i = 0; i < nsys; ++i) {
+            GS2_TRY_HIP(hipMemcpyAsync(b.rp + roff, As[i].rowptr, sizeof(int32_t) * (As[i].n + 1),
+                                       hipMemcpyDeviceToDevice, s));
+            GS2_TRY_HIP(hipMemcpyAsync(b.ci + noff, As[i].colind, sizeof(int32_t) * As[i].nnz, hipMemcpyDeviceToDevice,
+                                       s));
+            GS2_TRY_HIP(hipMemcpyAsync(b.va + noff, As[i].val, sizeof(double) * As[i].nnz, hipMemcpyDeviceToDevice, s));
+            b.sizes.push_back(As[i].n);
+            roff += As[i].n + 1;
+            noff += As[i].nnz;
+        }
     }
+    // the systems' triangles with K lanes per row (replacing any built before)
+    auto build_systems = [&](int K) -> int {
+        b.K = K;
+        for (Handle *h : b.hs) delete h;
+        b.hs.clear();
+        gs2_options so = o;
+        so.autotune = 0;
+        so.build_levels = 0;
+        so.lanes_per_row = K;
+        so.format = GS2_FORMAT_SELL;
+        std::vector<BSys> sys(nsys);
+        int64_t roff = 0, noff = 0, row0 = 0;
+        for (int i = 0; i < nsys; ++i) {
+            Handle *h = new (std::nothrow) Handle;
+            if (!h) return GS2_ERR_NOMEM;
+            b.hs.push_back(h);
+            h->n = As[i].n;
+            h->sweeps = sweeps;
+            h->inner = inner;
+            h->variant = variant;
+            h->omega = damping;
+            h->gamma = o.inner_damping;
+            h->precision = o.precision;
+            GS2_TRY(setup_handle(*h, As[i], so, s, false));
+            BSys &d = sys[i];
+            d.n = h->n;
+            d.nslices = h->L.nslices;
+            d.Lsp = h->L.slice_ptr;
+            d.Usp = h->U.slice_ptr;
+            d.Lcol = h->L.col;
+            d.Ucol = h->U.col;
+            d.Lval = h->L.val;
+            d.Uval = h->U.val;
+            d.sl = h->sl;
+            d.sr = h->sr;
+            d.rp = b.rp + roff;
+            d.ci = b.ci + noff;
+            d.va = b.va + noff;
+            d.row0 = row0;
+            roff += As[i].n + 1;
+            noff += As[i].nnz;
+            row0 += As[i].n;
+        }
+        if (!b.d_sys) GS2_TRY_HIP(hipMalloc(&b.d_sys, sizeof(BSys) * nsys));
+        GS2_TRY_HIP(hipMemcpyAsync(b.d_sys, sys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
+        GS2_TRY_HIP(hipStreamSynchronize(s));
+        return GS2_OK;
+    };
+    GS2_TRY(build_systems(kcands.front()));
     // the copied row pointers index the copied arrays from 0: rowptr is relative per system, as given
-    GS2_TRY_HIP(hipMalloc(&b.d_sys, sizeof(BSys) * nsys));
-    GS2_TRY_HIP(hipMemcpyAsync(b.d_sys, sys.data(), sizeof(BSys) * nsys, hipMemcpyHostToDevice, s));
     const size_t tot = (size_t)std::max<int64_t>(rows, 1) * nrhs;
     GS2_TRY_HIP(hipMalloc(&b.V, sizeof(double) * tot * (restart + 1)));
     GS2_TRY_HIP(hipMalloc(&b.Z, sizeof(double) * tot * restart));
@@ -1343,8 +1371,9 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
         for (int R : {4, 2, 1})
             if (nrhs % R == 0) cands.push_back(R);
     }
-    int bestR = cands.front();
-    if (o.autotune && cands.size() > 1) {
+    int bestR = cands.front(), bestK = kcands.front();
+    b.tuned = o.autotune && (cands.size() > 1 || kcands.size() > 1);
+    if (b.tuned) {
         double *Bt = nullptr, *Xt = nullptr;
         GS2_TRY_HIP(hipMalloc(&Bt, sizeof(double) * tot));
         GS2_TRY_HIP(hipMalloc(&Xt, sizeof(double) * tot));
@@ -1359,27 +1388,39 @@ static int setup_batched_impl(Batch &b, const gs2_csr *As, int nsys, int sweeps,
         // its slowest one has.  With one workgroup per item the largest items
         // form the critical path, so the smallest R within 25% of the best
         // tuning time is taken; with teams the largest items are split and the
-        // fastest R is taken.
-        std::vector<float> ms_of(cands.size(), 0.f);
-        float best = 1e30f;
-        for (size_t c = 0; c < cands.size(); ++c) {
-            GS2_TRY(configure(b, cands[c]));
-            GS2_TRY_HIP(hipMemsetAsync(Xt, 0, sizeof(double) * tot, s));
-            GS2_TRY_HIP(hipEventRecord(e0, s));
-            GS2_TRY(run(b, Bt, Xt, 0.0, restart, s));
-            GS2_TRY_HIP(hipEventRecord(e1, s));
-            GS2_TRY_HIP(hipEventSynchronize(e1));
-            GS2_TRY_HIP(hipEventElapsedTime(&ms_of[c], e0, e1));
-            best = std::min(best, ms_of[c]);
+        // fastest R is taken.  Each lanes-per-row candidate is timed with its
+        // own choice of R; a wider one must win by 3 % (the timing noise).
+        float bestAll = 1e30f;
+        for (size_t kc = 0; kc < kcands.size(); ++kc) {
+            if (kcands[kc] != b.K) GS2_TRY(build_systems(kcands[kc]));
+            std::vector<float> ms_of(cands.size(), 0.f);
+            float best = 1e30f;
+            for (size_t c = 0; c < cands.size(); ++c) {
+                GS2_TRY(configure(b, cands[c]));
+                GS2_TRY_HIP(hipMemsetAsync(Xt, 0, sizeof(double) * tot, s));
+                GS2_TRY_HIP(hipEventRecord(e0, s));
+                GS2_TRY(run(b, Bt, Xt, 0.0, restart, s));
+                GS2_TRY_HIP(hipEventRecord(e1, s));
+                GS2_TRY_HIP(hipEventSynchronize(e1));
+                GS2_TRY_HIP(hipEventElapsedTime(&ms_of[c], e0, e1));
+                best = std::min(best, ms_of[c]);
+            }
+            const float slack = b.team_rows < 0 ? 1.25f : 1.0f;
+            size_t pick = 0;
+            for (size_t c = 0; c < cands.size(); ++c) // cands is in decreasing R
+                if (ms_of[c] <= slack * best) pick = c;
+            if (ms_of[pick] < (kc == 0 ? 1.0f : 0.97f) * bestAll) {
+                bestAll = ms_of[pick];
+                bestK = kcands[kc];
+                bestR = cands[pick];
+            }
         }
-        const float slack = b.team_rows < 0 ? 1.25f : 1.0f;
-        for (size_t c = 0; c < cands.size(); ++c) // cands is in decreasing R
-            if (ms_of[c] <= slack * best) bestR = cands[c];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(Bt);
         (void)hipFree(Xt);
     }
+    if (b.K != bestK) GS2_TRY(build_systems(bestK));
     GS2_TRY(configure(b, bestR));
     GS2_TRY_HIP(hipStreamSynchronize(s));
     return GS2_OK;
@@ -1450,6 +1491,15 @@ int gmres_solve_batched(gs2_batch *B, int nrhs, const double *Bv, double *X, dou
     }
     if (infos) std::memcpy(infos, h.data(), sizeof(gs2_solve_info) * h.size());
     return st;
+}
+
+int gs2_batched_schedule(const gs2_batch *B, int *lanes_per_row, int *rhs_per_item, int *tuned)
+{
+    if (!B) return GS2_ERR_ARG;
+    if (lanes_per_row) *lanes_per_row = B->b.K;
+    if (rhs_per_item) *rhs_per_item = B->b.R;
+    if (tuned) *tuned = B->b.tuned;
+    return GS2_OK;
 }
 
 void gs2_destroy_batched(gs2_batch *B)

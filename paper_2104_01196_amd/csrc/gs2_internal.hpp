@@ -269,6 +269,8 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
 void free_sell(Sell &S);
 void free_dia(Dia &D);
 int choose_lanes(double avg_len, int max_len);
+// out[i] = in[0] + ... + in[i-1] for i < m (device arrays; synchronises s)
+int exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t m, hipStream_t s);
 
 // sweep.hip
 int apply_gs2(Handle &h, const double *v, double *z, hipStream_t s);

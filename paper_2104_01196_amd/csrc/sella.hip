@@ -1,6 +1,4 @@
 // Sliced-ELL copy of the system matrix for the Krylov solvers' SpMV.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <vector>
 
@@ -153,8 +151,7 @@ int sella_fill_values(SellA &S, const gs2_csr &A, bool with_col, hipStream_t s)
 // Lanes per row: from K0 (the rule: the mean row length, as for the
 // triangles), K grows while a few long rows would pad the copy beyond twice
 // the entries.
-static int sella_structure(SellA &S, const gs2_csr &A, int K0, int64_t *len, void *tmp, size_t tmp_bytes,
-                           hipStream_t s)
+static int sella_structure(SellA &S, const gs2_csr &A, int K0, int64_t *len, hipStream_t s)
 {
     const int tb = 256;
     for (int K = K0;; K *= 2) {
@@ -162,7 +159,7 @@ static int sella_structure(SellA &S, const gs2_csr &A, int K0, int64_t *len, voi
         S.C = WAVE / K;
         S.nslices = (A.n + S.C - 1) / S.C;
         k_sella_len<<<(unsigned)((S.nslices + 1 + tb - 1) / tb), tb, 0, s>>>(A.n, S.nslices, K, A.rowptr, len);
-        GS2_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, len, S.sp, (int)(S.nslices + 1), s));
+        GS2_TRY(exclusive_scan_i64(len, S.sp, S.nslices + 1, s));
         GS2_TRY_HIP(hipMemcpyAsync(&S.padded, S.sp + S.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         GS2_TRY_HIP(hipStreamSynchronize(s));
         if (K == WAVE || S.padded <= 2 * A.nnz + WAVE * S.nslices) break;
@@ -183,17 +180,12 @@ int sella_build_sell(SellA &S, const gs2_csr &A, int K0, hipStream_t s)
     S.n = A.n;
     S.nnz = A.nnz;
     int64_t *len = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
     int st = GS2_OK;
     const int64_t max_slices = A.n; // K = 64: one row per slice
     if (hipMalloc(&S.sp, sizeof(int64_t) * (max_slices + 1)) != hipSuccess ||
-        hipMalloc(&len, sizeof(int64_t) * (max_slices + 1)) != hipSuccess ||
-        hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, len, S.sp, (int)(max_slices + 1), s) != hipSuccess ||
-        hipMalloc(&tmp, tmp_bytes + 16) != hipSuccess)
+        hipMalloc(&len, sizeof(int64_t) * (max_slices + 1)) != hipSuccess)
         st = GS2_ERR_NOMEM;
-    if (st == GS2_OK) st = sella_structure(S, A, K0, len, tmp, tmp_bytes, s);
-    if (tmp) (void)hipFree(tmp);
+    if (st == GS2_OK) st = sella_structure(S, A, K0, len, s);
     if (len) (void)hipFree(len);
     if (st == GS2_OK) {
         S.sel = S.K;

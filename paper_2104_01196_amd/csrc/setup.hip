@@ -3,7 +3,6 @@
 // triangles in sliced-ELL layout and the requested precision, optionally
 // build level sets, and pick a lane-per-row schedule.  The paper notes that
 // GS2 needs no eigenvalue estimate and only this cheap setup (Section 12).
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -401,6 +400,89 @@ static int build_dia(Dia &D, int64_t n, int precision, int lower, int R, const s
     return GS2_OK;
 }
 
+// ------------------------------------------------------- exclusive scan
+//
+// out[i] = sum of in[0..i), for the slice pointers of the sliced-ELL arrays.
+// Three passes: each workgroup scans its 1024 elements (four per thread, the
+// thread totals combined by a Hillis-Steele scan in LDS) and writes its
+// total; one workgroup scans the totals in chunks of 256 with a running
+// carry; every element then adds its workgroup's offset.  Integer sums, so
+// the result is exact whatever the order.
+constexpr int SCAN_TB = 256, SCAN_PER = 4, SCAN_BLOCK = SCAN_TB * SCAN_PER;
+
+__device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < SCAN_TB; off <<= 1) {
+        const int64_t x = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += x;
+        __syncthreads();
+    }
+    return sh[t];
+}
+
+__global__ __launch_bounds__(SCAN_TB) void k_scan_local(const int64_t *__restrict__ in, int64_t *__restrict__ out,
+                                                        int64_t m, int64_t *__restrict__ bsum)
+{
+    __shared__ int64_t sh[SCAN_TB];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_BLOCK + (int64_t)threadIdx.x * SCAN_PER;
+    int64_t v[SCAN_PER], run = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+        v[q] = base + q < m ? in[base + q] : 0;
+        run += v[q];
+    }
+    const int64_t incl = block_incl_scan(run, sh);
+    int64_t e = incl - run;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+        if (base + q < m) out[base + q] = e;
+        e += v[q];
+    }
+    if (threadIdx.x == SCAN_TB - 1) bsum[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(SCAN_TB) void k_scan_sums(int64_t *__restrict__ bsum, int64_t nb)
+{
+    __shared__ int64_t sh[SCAN_TB];
+    int64_t carry = 0; // the same in every thread
+    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_TB) {
+        const int64_t i = c0 + threadIdx.x;
+        const int64_t v = i < nb ? bsum[i] : 0;
+        const int64_t incl = block_incl_scan(v, sh);
+        if (i < nb) bsum[i] = carry + incl - v;
+        carry += sh[SCAN_TB - 1];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SCAN_TB) void k_scan_add(int64_t *__restrict__ out, int64_t m,
+                                                      const int64_t *__restrict__ bsum)
+{
+    const int64_t i = (int64_t)blockIdx.x * SCAN_TB + threadIdx.x;
+    if (i < m) out[i] += bsum[i / SCAN_BLOCK];
+}
+
+int exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t m, hipStream_t s)
+{
+    if (m <= 0) return GS2_OK;
+    const int64_t nb = (m + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    int64_t *bsum = nullptr;
+    GS2_TRY_HIP(hipMalloc(&bsum, sizeof(int64_t) * nb));
+    k_scan_local<<<(unsigned)nb, SCAN_TB, 0, s>>>(in, out, m, bsum);
+    k_scan_sums<<<1, SCAN_TB, 0, s>>>(bsum, nb);
+    k_scan_add<<<(unsigned)((m + SCAN_TB - 1) / SCAN_TB), SCAN_TB, 0, s>>>(out, m, bsum);
+    const hipError_t e = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(bsum);
+    GS2_TRY_HIP(e);
+    GS2_TRY_HIP(e2);
+    return GS2_OK;
+}
+
 int choose_lanes(double avg_len, int max_len)
 {
     (void)max_len;
@@ -426,14 +508,9 @@ static int build_one(Sell &S, int64_t n, int K, int precision, const gs2_csr &A,
     GS2_TRY_HIP(hipMalloc(&len, sizeof(int64_t) * (S.nslices + 1)));
     const int tb = 256;
     k_slice_len<<<(unsigned)((S.nslices + 1 + tb - 1) / tb), tb, 0, s>>>(n, S.nslices, K, cnt, len);
-    size_t tmp_bytes = 0;
-    GS2_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, len, S.slice_ptr, (int)(S.nslices + 1), s));
-    void *tmp = nullptr;
-    GS2_TRY_HIP(hipMalloc(&tmp, tmp_bytes + 16));
-    GS2_TRY_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, len, S.slice_ptr, (int)(S.nslices + 1), s));
+    GS2_TRY(exclusive_scan_i64(len, S.slice_ptr, S.nslices + 1, s));
     GS2_TRY_HIP(hipMemcpyAsync(&S.padded, S.slice_ptr + S.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     GS2_TRY_HIP(hipStreamSynchronize(s));
-    (void)hipFree(tmp);
     (void)hipFree(len);
     const int64_t alloc = std::max<int64_t>(S.padded, WAVE);
     GS2_TRY_HIP(hipMalloc(&S.col, sizeof(int32_t) * alloc));

@@ -97,6 +97,7 @@ def lib():
                                             C.POINTER(vp)]
             L.gmres_solve_batched.argtypes = [vp, i, vp, vp, d, i, C.POINTER(SolveInfo), vp]
             L.gs2_destroy_batched.argtypes = [vp]
+            L.gs2_batched_schedule.argtypes = [vp, ip, ip, ip]
             L.gs2_destroy_batched.restype = None
         _lib = L
     return _lib
@@ -374,6 +375,15 @@ def gs2_setup_batched(mats, sweeps=2, inner=2, damping=1.0, variant=FORWARD, pre
     if st != OK:
         raise Gs2Error(st, "gs2_setup_batched")
     return BatchHandle(out, [m.n for m in mats], nrhs, keep=mats)
+
+
+def gs2_batched_schedule(bh: BatchHandle) -> dict:
+    """Lanes per row, right-hand sides per work item and whether they were timed."""
+    v = [C.c_int() for _ in range(3)]
+    st = lib().gs2_batched_schedule(bh.ptr, *[C.byref(x) for x in v])
+    if st != OK:
+        raise Gs2Error(st, "gs2_batched_schedule")
+    return {k: x.value for k, x in zip(["lanes_per_row", "rhs_per_item", "tuned"], v)}
 
 
 def gmres_solve_batched(bh: BatchHandle, nrhs, B, X, rtol=1e-8, maxit=10000, stream=None, raise_on_error=True):

@@ -199,6 +199,26 @@ def test_batched_not_converged_and_general_rows(team_rows):
         assert np.linalg.norm(Xh[:A.n * 2].reshape(A.n, 2)[:, r] - xo) / np.linalg.norm(xo) <= 1e-6
 
 
+@pytest.mark.parametrize("lanes", [0, 1, 4])
+def test_batched_lanes_per_row(lanes):
+    """The systems' triangles at one and four lanes per row (forced), and the
+    timed choice between them: each matches the oracle, and the schedule
+    query reports the lanes, the right-hand sides per item and whether they
+    were timed."""
+    mats, rhs = make_batch([12, 40, 23, 64], 2, seed=31)
+    st, infos, xs, bh, *_ = run_batch(mats, rhs, 2, sweeps=1, inner=2, precision=g.FP32, restart=15,
+                                      lanes_per_row=lanes)
+    assert st == 0
+    sch = g.gs2_batched_schedule(bh)
+    assert sch["lanes_per_row"] in (1, 4) and sch["rhs_per_item"] in (1, 2)
+    if lanes:
+        assert sch["lanes_per_row"] == lanes
+    else:
+        assert sch["tuned"] == 1
+    print(f"lanes {lanes}: schedule {sch}")
+    check_against_oracle(mats, rhs, 2, infos, xs, oracle.FP32, 1, 2, 15)
+
+
 @pytest.mark.slow
 def test_batched_full_size_all_pairs():
     """The full 512-system workload (sides 16..256, 4 right-hand sides),

@@ -6,9 +6,9 @@ oracle result):
   FP64 preconditioner applies: 1e-12 per sweep (the scaled-space kernels and
     the textbook oracle differ only in rounding order, O(nnz_row * eps)).
   FP32 / FP16-scaled applies vs the oracle's reduced-precision form (same
-    stored values and rounding points, different summation order):
-    2e-5 / 1e-4 (tens of float32 unit roundoffs; FP16 allows a rare
-    one-ulp difference in a stored value).
+    stored values -- bit for bit, tests/test_gpu_fp16_bits.py -- and
+    rounding points, different summation order): 2e-5 / 1e-4 (tens of
+    float32 unit roundoffs, amplified over the inner sweeps).
   GMRES: iteration count within +-1 of the oracle (MGS vs the GPU's CGS2
     with delayed reorthogonalisation); true residual <= rtol, solutions
     agree to what the tolerance allows.
