@@ -586,8 +586,9 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
 // The same pass with 16-byte loads for an even n (every column then starts
 // 16-byte aligned): each thread owns NP pairs of consecutive rows, so a
 // workgroup covers 2 NP KT rows and writes one partial.  Measured on the
-// 192^3 problem's basis (24 columns): 238 us against 273 us for the
-// one-row-per-load pass over 1024-row workgroups.
+// 192^3 problem's basis: 238 us against 273 us for the one-row-per-load
+// pass over 1024-row workgroups (microbenchmark, 24 columns); in the solve,
+// four pairs per thread and two measured alike (261 / 262 us per launch).
 template <int NP>
 __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__restrict__ V, int64_t ldv,
                                                           const GState *__restrict__ st, const double *__restrict__ w,
@@ -643,7 +644,7 @@ __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__r
     s = block_sum(s, red);
     if (t == 0) part[blockIdx.x] = s;
 }
-constexpr int UPD_PAIRS = 4; // pairs of rows per thread in k_dcgs_update_pairs
+constexpr int UPD_PAIRS = 4; // pairs of rows per thread in k_dcgs_update_pairs (2048-row workgroups)
 
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
