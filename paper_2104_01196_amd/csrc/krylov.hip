@@ -146,9 +146,19 @@ static int alloc_work(GmresWork **out, int64_t n, int m)
 // zero).  Results go to LDS: ra[k] = V_k.a, rb[k] = V_k.b.  The wavefront
 // with the fewest vectors (the last) also forms a.a, a.b and b.b into
 // rn[0..2] when with_norms.
+//
+// G: loads a wavefront keeps in flight over one vector.  The loads are
+// issued in groups of G, and the next group waits for the last (an empty
+// asm statement that takes the group's values as operands makes the
+// compiler wait for them there).  With all RL = 16 in flight the pass runs
+// at 84 % of 8 TB/s over 24 basis columns of the 192^3 problem and at
+// 82 % over 48; with two at a time, 88 % and 87 % (fewer requests in
+// flight, each wavefront's range of rows more compact in time).  Over the
+// first few columns of a cycle the wider groups are faster (1-4 columns:
+// 72-87 % against 62-86 %).  The sums run in the same order for every G.
 constexpr int RL = RB / WAVE;
 
-template <bool TWO>
+template <bool TWO, int G = RL>
 __device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const double *al, const double *bl,
                                                const double *__restrict__ V, int64_t ldv, int nk, bool with_norms,
                                                double *ra, double *rb, double *rn)
@@ -159,12 +169,25 @@ __device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const doub
         asm volatile("" ::: "memory"); // keep the LDS operands in LDS (no hoisting into registers)
         const double *__restrict__ vk = V + (int64_t)k * ldv + r0;
         double sa = 0.0, sb = 0.0;
+        static_assert(RL % G == 0, "groups of loads divide the rows per lane");
 #pragma unroll
-        for (int s = 0; s < RL; ++s) {
-            const int i = ln + s * WAVE;
-            const double x = __builtin_nontemporal_load(&vk[i < last ? i : last]);
-            sa += x * al[i];
-            if (TWO) sb += x * bl[i];
+        for (int s0 = 0; s0 < RL; s0 += G) {
+            double x[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int i = ln + (s0 + g) * WAVE;
+                x[g] = __builtin_nontemporal_load(&vk[i < last ? i : last]);
+            }
+            if constexpr (G < RL) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) asm volatile("" : "+v"(x[g])::"memory");
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int i = ln + (s0 + g) * WAVE;
+                sa += x[g] * al[i];
+                if (TWO) sb += x[g] * bl[i];
+            }
         }
         sa = wave_sum(sa);
         if (TWO) sb = wave_sum(sb);
@@ -501,6 +524,7 @@ __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const do
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(KT) void k_dot2(int64_t n, const double *__restrict__ w, const double *__restrict__ V,
                                              int64_t ldv, const GState *__restrict__ st, double *__restrict__ part,
                                              int nb)
@@ -519,7 +543,7 @@ __global__ __launch_bounds__(KT) void k_dot2(int64_t n, const double *__restrict
         ul[i] = row < n ? zsc * u[row] : 0.0;
     }
     __syncthreads();
-    block_multidot<true>(n, r0, ul, wl, V, ldv, j, true, ra, rc, rn);
+    block_multidot<true, G>(n, r0, ul, wl, V, ldv, j, true, ra, rc, rn);
     __syncthreads();
     for (int k = t; k < 2 * j + 3; k += KT)
         part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
@@ -589,7 +613,13 @@ __global__ __launch_bounds__(KT) void k_dcgs_update(int64_t n, double *__restric
 // 192^3 problem's basis: 238 us against 273 us for the one-row-per-load
 // pass over 1024-row workgroups (microbenchmark, 24 columns); in the solve,
 // four pairs per thread and two measured alike (261 / 262 us per launch).
-template <int NP>
+// G: loads in flight per thread over one column, issued in groups as in
+// block_multidot; the loop over the columns is not unrolled (unrolled, the
+// pass took 118 registers and 4 wavefronts per SIMD).  Over 24 and 48
+// columns one load at a time runs at 84 % and 86 % of 8 TB/s against 79 %
+// for all four; over 1-8 columns all four are faster (81-84 % against
+// 77-80 %).  The updates run in the same order for every G.
+template <int NP, int G>
 __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__restrict__ V, int64_t ldv,
                                                           const GState *__restrict__ st, const double *__restrict__ w,
                                                           double *__restrict__ part)
@@ -620,14 +650,27 @@ __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__r
         aq[q] = zsc * *(const D2 *)&u[rows[q]];
         aw[q] = *(const D2 *)&w[rows[q]];
     }
+    static_assert(NP % G == 0, "groups of loads divide the pairs per thread");
+#pragma unroll 1
     for (int k = 0; k < j; ++k) {
         const double *__restrict__ vk = V + (int64_t)k * ldv;
         const double a = as[k], c = cs_[k];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const D2 x = __builtin_nontemporal_load((const D2 *)&vk[rows[q]]);
-            aq[q] -= a * x;
-            aw[q] -= c * x;
+        for (int q0 = 0; q0 < NP; q0 += G) {
+            D2 x[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) x[g] = __builtin_nontemporal_load((const D2 *)&vk[rows[q0 + g]]);
+            if constexpr (G < NP) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) asm volatile("" : "+v"(x[g])::"memory");
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                aq[q0 + g] -= a * x[g];
+                aw[q0 + g] -= c * x[g];
+                // the group's updates before the next group's wait: its loaded values die here
+                if constexpr (G < NP) asm volatile("" : "+v"(aq[q0 + g]), "+v"(aw[q0 + g]));
+            }
         }
     }
 #pragma unroll
@@ -645,6 +688,9 @@ __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__r
     if (t == 0) part[blockIdx.x] = s;
 }
 constexpr int UPD_PAIRS = 4; // pairs of rows per thread in k_dcgs_update_pairs (2048-row workgroups)
+// Arnoldi steps from which the basis passes keep fewer loads in flight
+// (the crossovers measured on the 192^3 problem's basis)
+constexpr int UPD_NARROW_FROM = 12, DOT_NARROW_FROM = 8;
 
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
@@ -1005,7 +1051,8 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                             }
                         }
                         Prof pr(cs, PK_SPMV_DOT, vb + 8.0 * n);
-                        k_dot2<<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
+                        if (j < DOT_NARROW_FROM) k_dot2<8><<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
+                        else k_dot2<2><<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
                     } else {
                         Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
                         hipStream_t s = cs;
@@ -1017,10 +1064,13 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                     }
                     {
                         Prof pr(cs, PK_CGS, 8.0 * n * (j + 4));
-                        if (pairs)
-                            k_dcgs_update_pairs<UPD_PAIRS><<<(unsigned)nbu, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
-                        else
+                        if (!pairs)
                             k_dcgs_update<<<gN, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
+                        else if (j < UPD_NARROW_FROM)
+                            k_dcgs_update_pairs<UPD_PAIRS, UPD_PAIRS>
+                                <<<(unsigned)nbu, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
+                        else
+                            k_dcgs_update_pairs<UPD_PAIRS, 1><<<(unsigned)nbu, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
                     }
                     if (!fuse_fin || j == steps - 1) {
                         Prof pr(cs, PK_GIVENS, red_b);
