@@ -479,7 +479,9 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, DiaAView D, int64
 //
 // ND > 0: exactly ND diagonals (7 for 7-point stencils), the loop unrolled
 // completely so that every diagonal's loads are issued before the first
-// wait.  Every launched wavefront loads in bounds (the copy is padded to
+// wait (issuing them 1, 2 or 4 diagonals at a time measured no faster in the
+// solve).  w is stored non-temporally, as are the second basis pass's
+// outputs (196.3 against 197.3 ms per 192^3 solve).  Every launched wavefront loads in bounds (the copy is padded to
 // 1024-row workgroups and a clamped column only meets a stored zero); rows
 // past n are not written.
 template <int R, int ND>
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const do
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int64_t row = base + k * WAVE + ln;
-        if (row < n) w[row] = zsc * acc[k];
+        if (row < n) __builtin_nontemporal_store(zsc * acc[k], &w[row]);
     }
 }
 
@@ -679,8 +681,8 @@ __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__r
         if (row >= n) continue;
         const D2 qv = aq[q] * ia;
         const D2 wp = aw[q] - e * qv;
-        *(D2 *)&u[row] = qv;
-        *(D2 *)&wn[row] = wp;
+        __builtin_nontemporal_store(qv, (D2 *)&u[row]);
+        __builtin_nontemporal_store(wp, (D2 *)&wn[row]);
         s += wp.x * wp.x;
         s += wp.y * wp.y;
     }
@@ -766,6 +768,58 @@ __global__ __launch_bounds__(KT) void k_update_x(int64_t n, const double *__rest
     double acc = x[i];
     for (int k = 0; k < kk; ++k) acc += ys[k] * Z[(int64_t)k * ldz + i];
     x[i] = acc;
+}
+
+// The same update over pairs of rows for an even n and a 16-byte aligned x
+// (16-byte loads), NP pairs per thread, G loads in flight per thread (as in
+// the second basis pass); the sums run in the same order.  Over the 50
+// columns of a cycle on the 192^3 problem: 439 us with one load in flight
+// (84 % of 8 TB/s), 465 us with four, 536 us for the one-row kernel.
+constexpr int UPDX_G = 1;
+template <int NP, int G>
+__global__ __launch_bounds__(KT) void k_update_x_pairs(int64_t n, const double *__restrict__ Z, int64_t ldz,
+                                                       const GState *__restrict__ st, double *__restrict__ x)
+{
+    using D2 = double __attribute__((ext_vector_type(2)));
+    __shared__ double ys[MAXM];
+    const int kk = st->kk, t = threadIdx.x;
+    for (int k = t; k < kk; k += KT) ys[k] = st->y[k] * st->zs[k];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * (2 * NP * KT);
+    int64_t rows[NP];
+    D2 acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int64_t row = r0 + 2 * (t + q * KT);
+        rows[q] = row < n ? row : n - 2;
+        acc[q] = *(const D2 *)&x[rows[q]];
+    }
+    static_assert(NP % G == 0, "groups of loads divide the pairs per thread");
+#pragma unroll 1
+    for (int k = 0; k < kk; ++k) {
+        const double *__restrict__ zk = Z + (int64_t)k * ldz;
+        const double y = ys[k];
+#pragma unroll
+        for (int q0 = 0; q0 < NP; q0 += G) {
+            D2 v[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) v[g] = __builtin_nontemporal_load((const D2 *)&zk[rows[q0 + g]]);
+            if constexpr (G < NP) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) asm volatile("" : "+v"(v[g])::"memory");
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                acc[q0 + g] += y * v[g];
+                if constexpr (G < NP) asm volatile("" : "+v"(acc[q0 + g]));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int64_t row = r0 + 2 * (t + q * KT);
+        if (row < n) *(D2 *)&x[row] = acc[q];
+    }
 }
 
 __global__ void k_zero64(int64_t n, double *__restrict__ x)
@@ -1120,7 +1174,11 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
             k_backsolve<<<1, WAVE, 0, cs>>>(st);
             {
                 Prof pr(cs, PK_UPDATE_X, 8.0 * n * steps + 16.0 * n);
-                k_update_x<<<gE, KT, 0, cs>>>(n, Zb, n, st, x);
+                if (n % 2 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0)
+                    k_update_x_pairs<4, UPDX_G>
+                        <<<(unsigned)((n + 8 * KT - 1) / (8 * KT)), KT, 0, cs>>>(n, Zb, n, st, x);
+                else
+                    k_update_x<<<gE, KT, 0, cs>>>(n, Zb, n, st, x);
             }
             GS2_TRY_HIP(hipGetLastError());
             return GS2_OK;
