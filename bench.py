@@ -301,7 +301,7 @@ def main():
         if form_prof:  # the sweep kernels' roofline in this form
             sweep = {}
             for k, r in form_prof.items():
-                if k not in ("gs2_inner", "gs2_resid", "gs2_first_jr") or not r["bytes"]:
+                if k not in ("gs2_prep", "gs2_inner", "gs2_resid", "gs2_first_jr") or not r["bytes"]:
                     continue
                 ach = (r["bytes"] / r["launches"]) / ((r["ms"] / r["launches"]) * 1e-3) / 1e9
                 sweep[k] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -449,7 +449,7 @@ def bench_compare(args, g, torch, np):
              ("SGS(1) exact, level-scheduled", g.PREC_GS_TRISOLVE, (1, 1, 1.0, g.SYMMETRIC, True)),
              ("MT-GS-FWD(2) multicolor", g.PREC_MTGS, (2, 1, 1.0, g.FORWARD, True)),
              ("none", g.PREC_NONE, None)]
-    pre_kinds = ("gs2_inner", "gs2_resid", "gs2_first_jr", "trisolve_level")
+    pre_kinds = ("gs2_prep", "gs2_inner", "gs2_resid", "gs2_first_jr", "trisolve_level")
     res = {}
     for name, kind, cfg in cases:
         h = None

@@ -243,6 +243,9 @@ struct Handle {
     double *sl = nullptr, *sr = nullptr; // scaling vectors (float64)
     // persistent temporaries (Section 6: allocated once, live with the handle)
     void *xh = nullptr, *xh2 = nullptr, *rh = nullptr, *ga = nullptr, *gb = nullptr;
+    // S_l v rounded to the working precision, formed once per apply by the
+    // 32- and 16-bit forms on the diagonal layout (null in float64)
+    void *sv = nullptr;
     // level sets (optional)
     int nlev_l = 0, nlev_u = 0;
     int32_t *lev_rows_l = nullptr, *lev_rows_u = nullptr; // rows grouped by level
@@ -292,7 +295,7 @@ inline size_t prec_bytes(int precision) { return precision == GS2_FP64 ? 8 : 4; 
 // profile.hip: optional per-launch HIP-event timing with algorithmic bytes
 enum ProfKid : int {
     PK_INNER = 0, PK_RESID, PK_FIRST_JR, PK_TRI, PK_SPMV_DOT, PK_CGS, PK_TRUE_RESID, PK_REDUCE, PK_GIVENS,
-    PK_SCALE, PK_UPDATE_X, PK_BATCHED, PK_MISC, PK_SPMV
+    PK_SCALE, PK_UPDATE_X, PK_BATCHED, PK_MISC, PK_SPMV, PK_PREP
 };
 bool prof_on();
 // While one lives, the calling thread's launches are not recorded (the

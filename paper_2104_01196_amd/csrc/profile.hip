@@ -17,7 +17,7 @@ namespace gs2 {
 
 static const char *const KNAMES[] = {"gs2_inner", "gs2_resid", "gs2_first_jr", "trisolve_level", "spmv_dot",
                                      "cgs_update_dot", "true_resid", "reduce", "givens", "scale", "update_x",
-                                     "batched_gmres", "misc", "spmv"};
+                                     "batched_gmres", "misc", "spmv", "gs2_prep"};
 constexpr int NKID = sizeof(KNAMES) / sizeof(KNAMES[0]);
 
 struct ProfRec {

@@ -799,6 +799,7 @@ static int alloc_vectors(Handle &h)
     GS2_TRY_HIP(hipMalloc(&h.rh, vb));
     GS2_TRY_HIP(hipMalloc(&h.ga, vb));
     GS2_TRY_HIP(hipMalloc(&h.gb, vb));
+    if (h.precision != GS2_FP64) GS2_TRY_HIP(hipMalloc(&h.sv, vb));
     return GS2_OK;
 }
 
@@ -903,7 +904,7 @@ Handle::~Handle()
     free_sell(E);
     free_dia(DL);
     free_dia(DU);
-    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, yh, (void *)lev_rows_l, (void *)lev_rows_u,
+    for (void *p : {(void *)sl, (void *)sr, xh, xh2, rh, ga, gb, sv, yh, (void *)lev_rows_l, (void *)lev_rows_u,
                     (void *)color_rows})
         if (p) (void)hipFree(p);
     if (gw) free_gmres_work(gw);

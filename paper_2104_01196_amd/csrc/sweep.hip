@@ -527,11 +527,51 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
 
 // Outer residual pass on diagonal-interleaved triangles (as k_resid without
 // the hybrid term): rh = S_l v - cdiag xh - P xh [- Q xh].  ND > 0 kernels
-// always add Q.
+// always add Q.  svp, when given, holds S_l v already rounded to AT (the
+// same value this pass would form from v and s_l).
+
+// S_l v rounded to the working precision, formed once per apply by the 32-
+// and 16-bit forms on the diagonal layout: the first inner pass then gathers
+// one AT value per neighbour instead of two float64 values (v and s_l), and
+// every residual pass reads 2 or 4 bytes per row instead of 16.  FIN: the
+// first workgroup closes the previous GMRES step instead (as in k_dia_inner).
+// Q: rows per thread, consecutive, for 16-byte loads of v and s_l (Q = 4
+// needs n % 4 == 0 and v, s_l, sv aligned to 16 and 4 sizeof(AT) bytes);
+// Q = 1 any.
+template <typename AT, bool FIN, int Q>
+__global__ __launch_bounds__(KT) void k_dia_prep(const int *__restrict__ stop, int n, const double *__restrict__ v,
+                                                 const double *__restrict__ sl, AT *__restrict__ sv,
+                                                 const double *__restrict__ fpart, int fnb, void *fst)
+{
+    if constexpr (FIN) {
+        if (blockIdx.x == 0) {
+            dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+            return;
+        }
+    }
+    if (stop && *stop) return;
+    const int i = ((int)(blockIdx.x - (FIN ? 1 : 0)) * KT + (int)threadIdx.x) * Q;
+    if (i >= n) return;
+    if constexpr (Q == 1) {
+        sv[i] = (AT)(v[i] * sl[i]);
+    } else {
+        static_assert(Q == 4, "one or four rows per thread");
+        using D2 = double __attribute__((ext_vector_type(2)));
+        using A4 = AT __attribute__((ext_vector_type(4)));
+        const D2 v0 = __builtin_nontemporal_load((const D2 *)&v[i]), v1 = __builtin_nontemporal_load((const D2 *)&v[i + 2]);
+        const D2 s0 = *(const D2 *)&sl[i], s1 = *(const D2 *)&sl[i + 2];
+        A4 o;
+        o.x = (AT)(v0.x * s0.x);
+        o.y = (AT)(v0.y * s0.y);
+        o.z = (AT)(v1.x * s1.x);
+        o.w = (AT)(v1.y * s1.y);
+        *(A4 *)&sv[i] = o;
+    }
+}
 template <typename VT, typename AT, int R, int FL, int ND>
 __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict__ stop, int remap, int n, DiaView P, DiaView Q, int two,
                                                   const AT *__restrict__ xh, const double *__restrict__ v,
-                                                  const double *__restrict__ sl, AT cdiag, AT w, int dst,
+                                                  const double *__restrict__ sl, const AT *__restrict__ svp, AT cdiag, AT w, int dst,
                                                   AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
                                                   const double *__restrict__ sr)
 {
@@ -568,7 +608,8 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
     for (int k = 0; k < R; ++k) {
         const int row = rb + k * WAVE;
         if (row >= n) break;
-        const AT r = ((AT)(v[row] * sl[row]) - cdiag * own[k]) - acc[k];
+        const AT s0 = svp ? svp[row] : (AT)(v[row] * sl[row]);
+        const AT r = (s0 - cdiag * own[k]) - acc[k];
         finish<AT>(dst, row, r, w, rh, const_cast<AT *>(xh), xout, z, sr);
     }
 }
@@ -702,7 +743,7 @@ struct Launch {
         }
     }
     template <int R, int FL>
-    static void dia_resid_r(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
+    static void dia_resid_r(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,
                             AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
     {
         const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R));
@@ -713,38 +754,38 @@ struct Launch {
         if (P.ndiag == 3 && Q && Q->ndiag == 3)
             k_dia_resid<VT, AT, R, FL, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
                                                                        Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
-                                                                       h.sl, cdiag, w, dst, rh, xout, z, h.sr);
+                                                                       h.sl, svp, cdiag, w, dst, rh, xout, z, h.sr);
         else
             k_dia_resid<VT, AT, R, FL, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
                                                                        Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
-                                                                       h.sl, cdiag, w, dst, rh, xout, z, h.sr);
+                                                                       h.sl, svp, cdiag, w, dst, rh, xout, z, h.sr);
     }
     template <int R>
-    static void dia_resid_f(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
+    static void dia_resid_f(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,
                             AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
     {
         switch (dia_flags(h, P)) {
-        case 0: dia_resid_r<R, 0>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 1: dia_resid_r<R, 1>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        case 2: dia_resid_r<R, 2>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
-        default: dia_resid_r<R, 3>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s); break;
+        case 0: dia_resid_r<R, 0>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
+        case 1: dia_resid_r<R, 1>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
+        case 2: dia_resid_r<R, 2>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
+        default: dia_resid_r<R, 3>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
         }
     }
-    static void dia_resid_l(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, AT cdiag,
+    static void dia_resid_l(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,
                             AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
     {
         switch (P.R) {
         case 1:
-            if constexpr (r_ok<1>()) dia_resid_f<1>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<1>()) dia_resid_f<1>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s);
             break;
         case 2:
-            if constexpr (r_ok<2>()) dia_resid_f<2>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<2>()) dia_resid_f<2>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s);
             break;
         case 4:
-            if constexpr (r_ok<4>()) dia_resid_f<4>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<4>()) dia_resid_f<4>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s);
             break;
         default:
-            if constexpr (r_ok<8>()) dia_resid_f<8>(h, P, Q, xh, v, cdiag, w, dst, rh, xout, z, s);
+            if constexpr (r_ok<8>()) dia_resid_f<8>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s);
             break;
         }
     }
@@ -812,16 +853,19 @@ struct Launch {
                                                               Q ? 1 : 0, xh, v, h.sl, cdiag, w, dst, rh, xout, z, h.sr,
                                                               ye ? view(h.E) : view(P), ye);
     }
-    // ye: values the off-block part E multiplies (NULL: no E term)
+    // ye: values the off-block part E multiplies (NULL: no E term); svp:
+    // S_l v in AT from this apply's prep pass (diagonal layout only), or NULL
     static void resid(const Handle &h, const Sell &P, const Sell *Q, const AT *xh, const double *v, AT cdiag, AT w,
-                      int dst, AT *rh, AT *xout, double *z, hipStream_t s, const AT *ye = nullptr)
+                      int dst, AT *rh, AT *xout, double *z, hipStream_t s, const AT *ye = nullptr,
+                      const AT *svp = nullptr)
     {
         const double out = (dst == DST_ZADD || dst == DST_ZSET) ? 16.0 : (double)sizeof(AT);
         if (h.fmt == FMT_DIA && !ye) {
             const Dia &DP = dia_of(h, P);
             const Dia *DQ = Q ? &dia_of(h, *Q) : nullptr;
-            Prof pr(s, PK_RESID, dia_bytes(DP) + (DQ ? dia_bytes(*DQ) : 0.0) + (double)h.n * (16.0 + sizeof(AT) + out));
-            dia_resid_l(h, DP, DQ, xh, v, cdiag, w, dst, rh, xout, z, s);
+            const double src = svp ? (double)sizeof(AT) : 16.0;
+            Prof pr(s, PK_RESID, dia_bytes(DP) + (DQ ? dia_bytes(*DQ) : 0.0) + (double)h.n * (src + sizeof(AT) + out));
+            dia_resid_l(h, DP, DQ, xh, v, svp, cdiag, w, dst, rh, xout, z, s);
             return;
         }
         Prof pr(s, PK_RESID,
@@ -840,6 +884,22 @@ struct Launch {
 
     // z = Mhat^{-1} v (Fig. code:two-stage on one process: `sweeps` outer
     // sweeps, each a forward and/or backward half with n_j inner sweeps).
+    // sv = AT(S_l v), carrying the previous GMRES step's closing work when fj is set
+    static void prep(const Handle &h, const double *v, AT *sv, hipStream_t s, const Handle::FinJob &fj)
+    {
+        Prof pr(s, PK_PREP, (double)h.n * (16.0 + sizeof(AT)));
+        const bool q4 = h.n % 4 == 0 && reinterpret_cast<uintptr_t>(v) % 16 == 0 &&
+                        reinterpret_cast<uintptr_t>(h.sl) % 16 == 0 && reinterpret_cast<uintptr_t>(sv) % (4 * sizeof(AT)) == 0;
+        const unsigned grid = q4 ? (unsigned)((h.n / 4 + KT - 1) / KT) : grid_rows(h.n);
+        const int n = (int)h.n;
+        if (q4) {
+            if (fj.st) k_dia_prep<AT, true, 4><<<grid + 1u, KT, 0, s>>>(h.stop, n, v, h.sl, sv, fj.part, fj.nb, fj.st);
+            else k_dia_prep<AT, false, 4><<<grid, KT, 0, s>>>(h.stop, n, v, h.sl, sv, nullptr, 0, nullptr);
+        } else {
+            if (fj.st) k_dia_prep<AT, true, 1><<<grid + 1u, KT, 0, s>>>(h.stop, n, v, h.sl, sv, fj.part, fj.nb, fj.st);
+            else k_dia_prep<AT, false, 1><<<grid, KT, 0, s>>>(h.stop, n, v, h.sl, sv, nullptr, 0, nullptr);
+        }
+    }
     static int gs2(Handle &h, const double *v, double *z, hipStream_t s)
     {
         AT *xc = (AT *)h.xh, *xo = (AT *)h.xh2, *rh = (AT *)h.rh, *ga = (AT *)h.ga, *gb = (AT *)h.gb;
@@ -857,6 +917,10 @@ struct Launch {
         // the interface is exchanged once per global sweep (Fig. code:two-stage), so every
         // half of it sees the same off-block values; with a single half that is the live iterate
         const bool freeze = hyb && nk * per > 1;
+        // 32- and 16-bit forms on the diagonal layout: S_l v formed once in AT
+        // (prep), read by the first inner pass and every residual pass
+        AT *svb = (sizeof(AT) < sizeof(double) && h.fmt == FMT_DIA && h.sv && h.inner >= 1 && !hyb) ? (AT *)h.sv
+                                                                                                     : nullptr;
         int t = 0;
         for (int ts = 0; ts < h.sweeps; ++ts) {
             if (freeze) { // exchange: freeze the off-block values for this global sweep
@@ -890,19 +954,25 @@ struct Launch {
                         }
                     } else {
                         int rv = 1;
+                        const AT *rsrc = rh; // this half's r (scaled), when not formed from v
                         if (!xzero) {
-                            if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s);
-                            else resid(h, T, &O, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s, ye);
+                            if (h.compact) resid(h, O, nullptr, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s, nullptr, svb);
+                            else resid(h, T, &O, xc, v, cdiag, w, DST_G, rh, nullptr, nullptr, s, ye, svb);
+                            rv = 0;
+                        } else if (svb) { // r = S_l v and g_0 = r, both read from sv
+                            prep(h, v, svb, s, fj);
+                            fj = Handle::FinJob{};
+                            rsrc = svb;
                             rv = 0;
                         }
-                        const AT *gin = rh;
+                        const AT *gin = rsrc;
                         for (int j = 1; j <= h.inner; ++j) {
                             const bool last = j == h.inner;
-                            const int gv = (j == 1 && xzero) ? 1 : 0;
+                            const int gv = (j == 1 && xzero && !svb) ? 1 : 0;
                             AT *gout = (j & 1) ? ga : gb;
                             const int dst =
                                 !last ? DST_G : fin ? (set ? DST_ZSET : DST_ZADD) : (set ? DST_XSET : DST_XADD);
-                            inner(h, T, rh, gin, v, rv, gv, dst, gout, xc, z, s, fj);
+                            inner(h, T, rsrc, gin, v, rv, gv, dst, gout, xc, z, s, fj);
                             fj = Handle::FinJob{};
                             gin = gout;
                         }

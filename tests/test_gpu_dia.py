@@ -110,6 +110,67 @@ def test_dia_damping_compact_and_jr(name, lds):
     assert rel_inf(host(z), oracle.jr_sweep(A, v, np.zeros(A.n), 3, 0.7)) <= 3e-12
 
 
+@pytest.mark.parametrize("prec", [g.FP32, g.FP16_SCALED])
+def test_dia_prep_four_rows_per_thread(prec):
+    """A row count divisible by 4 (24^3 = 13,824) takes the pass that forms
+    S_l v four rows per thread (16-byte loads); the other matrices here have
+    odd row counts and take the one-row pass.  Apply against the oracle's
+    reduced-precision apply, and GMRES(30) within one iteration of the
+    oracle (its first preconditioner pass then also closes the previous
+    Arnoldi step)."""
+    A = vardiff3d(24, seed=6)
+    assert A.n % 4 == 0
+    dA = g.DeviceCSR.from_host(A)
+    v = np.random.default_rng(15).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    for variant, sweeps, inner, w in ((g.SYMMETRIC, 2, 2, 0.9), (g.FORWARD, 1, 1, 1.0)):
+        h = g.gs2_setup(dA, sweeps, inner, w, variant, precision=prec, format=g.FORMAT_DIA)
+        g.gs2_apply(h, dev(v), z)
+        ref = oracle.gs2_apply_lp(A, v, prec, variant, sweeps, inner, w)
+        assert rel_inf(host(z), ref) <= TOL[prec], (variant, sweeps, inner, w)
+    b = np.random.default_rng(16).standard_normal(A.n)
+    _, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=1,
+                         precision=prec)
+    h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, precision=prec, format=g.FORMAT_DIA)
+    x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+    info = g.gmres_solve(dA, dev(b), x, 30, 1e-8, 5000, g.PREC_GS2, h)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
+
+
+@pytest.mark.parametrize("prec", [g.FP32, g.FP16_SCALED])
+@pytest.mark.parametrize("lds", [g.LDS_OFF, g.LDS_ON])
+def test_dia_reduced_precision_damping_and_compact(prec, lds):
+    """Inner damping gamma and the compact form in the 32- and 16-bit forms on
+    the diagonal layout, where S_l v is formed once per apply in the working
+    precision and read by the first inner pass and every residual pass.  The
+    oracle's reduced-precision apply has no gamma or compact form, so the
+    bars are against its float64 apply with the rounding of the form
+    (float32: 1e-5; scaled float16, whose stored entries carry 2^-11
+    relative error: 3e-3), and against the sliced-ELL layout of the same
+    form (same stored values and arithmetic, another summation order: 2e-5 /
+    1e-4)."""
+    A, dA = mat("vardiff3d_23")
+    v = np.random.default_rng(14).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    zs = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    bar_or = {g.FP32: 1e-5, g.FP16_SCALED: 3e-3}[prec]
+    bar_sell = TOL[prec]
+    for kw, ref in ((dict(sweeps=2, inner=3, w=0.9, var=g.SYMMETRIC, inner_damping=0.6),
+                     oracle.gs2_apply(A, v, g.SYMMETRIC, 2, 3, 0.9, 0.6)),
+                    (dict(sweeps=2, inner=1, w=0.8, var=g.FORWARD, compact=True),
+                     oracle.gs2c_sweep(A, v, np.zeros(A.n), g.FORWARD, 2, 1, 0.8))):
+        extra = {k: kw[k] for k in ("inner_damping", "compact") if k in kw}
+        h = g.gs2_setup(dA, kw["sweeps"], kw["inner"], kw["w"], kw["var"], precision=prec, format=g.FORMAT_DIA,
+                        lds_staging=lds, **extra)
+        g.gs2_apply(h, dev(v), z)
+        hs = g.gs2_setup(dA, kw["sweeps"], kw["inner"], kw["w"], kw["var"], precision=prec, format=g.FORMAT_SELL,
+                         **extra)
+        g.gs2_apply(hs, dev(v), zs)
+        zd = host(z)
+        assert rel_inf(zd, ref) <= bar_or, (kw, rel_inf(zd, ref))
+        assert rel_inf(zd, host(zs)) <= bar_sell, (kw, rel_inf(zd, host(zs)))
+
+
 @pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
 @pytest.mark.parametrize("lds,xcd", [(g.LDS_OFF, g.XCD_RANGES), (g.LDS_ON, g.XCD_RANGES),
                                      (g.LDS_OFF, g.XCD_DISPATCH_ORDER)])
