@@ -143,9 +143,11 @@ static int alloc_work(GmresWork **out, int64_t n, int m)
 // 120 -> 98 us for the fused SpMV + first pass, 44.7 -> 41.5 ms per solve
 // with the same hint in the second pass and the residual kernel).
 // Rows past n are clamped to the last row for loading (their factor is
-// zero).  Results go to LDS: ra[k] = V_k.a, rb[k] = V_k.b.  The wavefront
-// with the fewest vectors (the last) also forms a.a, a.b and b.b into
-// rn[0..2] when with_norms.
+// zero).  Results go to LDS: ra[k] = V_k.a, rb[k] = V_k.b.  With
+// with_norms each wavefront first forms a.a, a.b and b.b over its quarter of
+// the rows into rn[3 w + 0..2] (norm_part sums them in a fixed order); left
+// to one wavefront after its vectors, they held the workgroup about 6 %
+// longer (microbenchmark, 24 and 48 columns).
 //
 // G: loads a wavefront keeps in flight over one vector.  The loads are
 // issued in groups of G, and the next group waits for the last (an empty
@@ -157,6 +159,15 @@ static int alloc_work(GmresWork **out, int64_t n, int m)
 // first few columns of a cycle the wider groups are faster (1-4 columns:
 // 72-87 % against 62-86 %).  The sums run in the same order for every G.
 constexpr int RL = RB / WAVE;
+constexpr int NWV = KT / WAVE; // wavefronts per workgroup
+
+// norm c (0: a.a, 1: a.b, 2: b.b) of the workgroup from the wavefronts' parts
+__device__ __forceinline__ double norm_part(const double *rn, int c)
+{
+    double o = 0.0;
+    for (int q = 0; q < NWV; ++q) o += rn[3 * q + c];
+    return o;
+}
 
 template <bool TWO, int G = RL>
 __device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const double *al, const double *bl,
@@ -165,6 +176,30 @@ __device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const doub
 {
     const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
     const int last = (int)(n - 1 - r0 < RB - 1 ? n - 1 - r0 : RB - 1);
+    if (with_norms) {
+        constexpr int QR = RL / NWV;
+        double aa = 0.0, ab = 0.0, bb = 0.0;
+#pragma unroll
+        for (int s = 0; s < QR; ++s) {
+            const int i = ln + (wv * QR + s) * WAVE;
+            const double a = al[i], b = TWO ? bl[i] : 0.0;
+            aa += a * a;
+            if (TWO) {
+                ab += a * b;
+                bb += b * b;
+            }
+        }
+        aa = wave_sum(aa);
+        if (TWO) {
+            ab = wave_sum(ab);
+            bb = wave_sum(bb);
+        }
+        if (ln == 0) {
+            rn[3 * wv] = aa;
+            rn[3 * wv + 1] = ab;
+            rn[3 * wv + 2] = bb;
+        }
+    }
     for (int k = wv; k < nk; k += KT / WAVE) {
         asm volatile("" ::: "memory"); // keep the LDS operands in LDS (no hoisting into registers)
         const double *__restrict__ vk = V + (int64_t)k * ldv + r0;
@@ -196,28 +231,6 @@ __device__ __forceinline__ void block_multidot(int64_t n, int64_t r0, const doub
             if (TWO) rb[k] = sb;
         }
     }
-    if (with_norms && wv == KT / WAVE - 1) {
-        double aa = 0.0, ab = 0.0, bb = 0.0;
-#pragma unroll
-        for (int s = 0; s < RL; ++s) {
-            const double a = al[ln + s * WAVE], b = TWO ? bl[ln + s * WAVE] : 0.0;
-            aa += a * a;
-            if (TWO) {
-                ab += a * b;
-                bb += b * b;
-            }
-        }
-        aa = wave_sum(aa);
-        if (TWO) {
-            ab = wave_sum(ab);
-            bb = wave_sum(bb);
-        }
-        if (ln == 0) {
-            rn[0] = aa;
-            rn[1] = ab;
-            rn[2] = bb;
-        }
-    }
 }
 
 // w = A z (sliced ELL, K lanes per row) fused with h = V^T w and ||w||^2
@@ -229,7 +242,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot(SellAView A, DiaAView D, int64_
                                                  int fixed_nk)
 {
     __shared__ double wl[RB];
-    __shared__ double ra[MAXM + 2], rn[3];
+    __shared__ double ra[MAXM + 2], rn[3 * NWV];
     if (st && st->done) return;
     const int nk = st ? st->j + 1 : fixed_nk;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
@@ -239,7 +252,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot(SellAView A, DiaAView D, int64_
         if (r0 + i < n) w[r0 + i] = wl[i];
     block_multidot<false>(n, r0, wl, nullptr, V, ldv, nk, true, ra, nullptr, rn);
     __syncthreads();
-    for (int k = t; k <= nk; k += KT) part[(int64_t)k * nb + blockIdx.x] = k < nk ? ra[k] : rn[0];
+    for (int k = t; k <= nk; k += KT) part[(int64_t)k * nb + blockIdx.x] = k < nk ? ra[k] : norm_part(rn, 0);
 }
 
 // r = b - A x written to out, with ||r||^2 partials.
@@ -289,7 +302,7 @@ __global__ __launch_bounds__(KT) void k_update_dot(int64_t n, const double *__re
                                                    int do_dot, int with_norm, double *__restrict__ part, int nb)
 {
     __shared__ double wl[RB];
-    __shared__ double ra[MAXM + 2], rn[3], hs[MAXM + 2];
+    __shared__ double ra[MAXM + 2], rn[3 * NWV], hs[MAXM + 2];
     if (st->done) return;
     const int nk = st->j + 1;
     const double *hsrc = which_h == 0 ? st->hA : st->hB;
@@ -327,7 +340,7 @@ __global__ __launch_bounds__(KT) void k_update_dot(int64_t n, const double *__re
     block_multidot<false>(n, r0, wl, nullptr, V, ldv, cnt, with_norm != 0, ra, nullptr, rn);
     __syncthreads();
     for (int k = t; k < cnt + (with_norm ? 1 : 0); k += KT)
-        part[(int64_t)k * nb + blockIdx.x] = k < cnt ? ra[k] : rn[0];
+        part[(int64_t)k * nb + blockIdx.x] = k < cnt ? ra[k] : norm_part(rn, 0);
 }
 
 // out[k] = sum_b part[k*nb + b] for k < cnt (one workgroup per k).  dst
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, DiaAView D, int64
                                                   const GState *__restrict__ st, double *__restrict__ part, int nb)
 {
     __shared__ double wl[RB], ul[RB];
-    __shared__ double ra[MAXM + 2], rc[MAXM + 2], rn[3];
+    __shared__ double ra[MAXM + 2], rc[MAXM + 2], rn[3 * NWV];
     if (st->done) return;
     const int j = st->j;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(KT) void k_spmv_dot2(SellAView A, DiaAView D, int64
     block_multidot<true>(n, r0, ul, wl, V, ldv, j, true, ra, rc, rn);
     __syncthreads();
     for (int k = t; k < 2 * j + 3; k += KT)
-        part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
+        part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : norm_part(rn, k - 2 * j);
 }
 
 // The same pass split in two for the diagonal copy of A: k_dia_spmv writes
@@ -532,23 +545,39 @@ __global__ __launch_bounds__(KT) void k_dot2(int64_t n, const double *__restrict
                                              int nb)
 {
     __shared__ double wl[RB], ul[RB];
-    __shared__ double ra[MAXM + 2], rc[MAXM + 2], rn[3];
+    __shared__ double ra[MAXM + 2], rc[MAXM + 2], rn[3 * NWV];
     if (st->done) return;
     const int j = st->j;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int t = threadIdx.x;
     const double zsc = st->zs[j];
     const double *__restrict__ u = V + (int64_t)j * ldv;
+    // u.u, u.w and w.w from the values as they are staged (every wavefront
+    // its own rows; 237.6 -> 225.7 us per launch in the 192^3 solve against
+    // the norms formed by one wavefront after its vectors)
+    double aa = 0.0, ab = 0.0, bb = 0.0;
     for (int i = t; i < RB; i += KT) {
         const int64_t row = r0 + i;
-        wl[i] = row < n ? w[row] : 0.0;
-        ul[i] = row < n ? zsc * u[row] : 0.0;
+        const double wv = row < n ? w[row] : 0.0, uv = row < n ? zsc * u[row] : 0.0;
+        wl[i] = wv;
+        ul[i] = uv;
+        aa += uv * uv;
+        ab += uv * wv;
+        bb += wv * wv;
+    }
+    aa = wave_sum(aa);
+    ab = wave_sum(ab);
+    bb = wave_sum(bb);
+    if ((t & (WAVE - 1)) == 0) {
+        rn[3 * (t / WAVE)] = aa;
+        rn[3 * (t / WAVE) + 1] = ab;
+        rn[3 * (t / WAVE) + 2] = bb;
     }
     __syncthreads();
-    block_multidot<true, G>(n, r0, ul, wl, V, ldv, j, true, ra, rc, rn);
+    block_multidot<true, G>(n, r0, ul, wl, V, ldv, j, false, ra, rc, nullptr);
     __syncthreads();
     for (int k = t; k < 2 * j + 3; k += KT)
-        part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : rn[k - 2 * j];
+        part[(int64_t)k * nb + blockIdx.x] = k < j ? ra[k] : k < 2 * j ? rc[k - j] : norm_part(rn, k - 2 * j);
 }
 
 // Pass 2 of step j: q_j = (u - Q a)/alpha over u's slot, w' = w - Q c - e q_j
