@@ -130,14 +130,21 @@ typedef struct gs2_options {
                           /* (0: timed once per pattern on >= 65536 rows --  */
                           /* sliced ELL at two lane counts, diagonal copy at */
                           /* 1 and 2 rows per lane when A qualifies --, else */
-                          /* sliced ELL), _SELL or _DIA (2 rows per lane;    */
-                          /* sliced ELL if A does not qualify)               */
+                          /* or, for n = 3 x nodes with <= 32 node offsets  */
+                          /* c/3 - r/3, the 3-row block copy at 1 and 2 rows */
+                          /* per lane; else sliced ELL), _SELL, _DIA (2 rows */
+                          /* per lane) or _BLOCK3 (2 rows per lane), each    */
+                          /* falling back to sliced ELL if A does not        */
+                          /* qualify                                         */
 } gs2_options;
 
 /* gs2_options.format */
 #define GS2_FORMAT_AUTO 0
 #define GS2_FORMAT_SELL 1 /* sliced ELL, K lanes per row, column indices   */
 #define GS2_FORMAT_DIA 2  /* diagonal-interleaved, no column indices       */
+#define GS2_FORMAT_BLOCK3 3 /* spmv_format only: 3-row blocks along node   */
+                            /* offsets (3 unknowns per node, node-major),  */
+                            /* no column indices                           */
 
 typedef struct gs2_solve_info {
     int iterations; /* Arnoldi steps (preconditioner applications)          */
@@ -329,9 +336,10 @@ int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, in
 /*
  * The layout gmres_solve used for its copy of A with this handle (host
  * outputs, any may be NULL; all 0 before the handle's first solve): format
- * GS2_FORMAT_SELL or GS2_FORMAT_DIA, lanes_per_row (sliced ELL) or
- * rows_per_lane (diagonal copy), ndiag (diagonals of the copy, 0 for sliced
- * ELL), tuned = 1 if chosen by timing the candidates.
+ * GS2_FORMAT_SELL, GS2_FORMAT_DIA or GS2_FORMAT_BLOCK3, lanes_per_row
+ * (sliced ELL) or rows_per_lane (diagonal or block copy), ndiag (diagonals,
+ * or node offsets of the block copy; 0 for sliced ELL), tuned = 1 if chosen
+ * by timing the candidates.
  */
 int gs2_gmres_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *ndiag,
                        int *tuned);

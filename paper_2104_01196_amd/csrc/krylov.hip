@@ -539,6 +539,49 @@ __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const do
     }
 }
 
+// w = zs[j] (A z) from the 3-row block copy (b3_rows' scheme, written
+// straight from registers): a lane owns NB rows 64 apart.  The copy is
+// padded to whole 1024-row workgroups, so every load is in bounds; rows past
+// n are not written.
+template <int NB>
+__global__ __launch_bounds__(KT) void k_b3_spmv(DiaAView A, int64_t n, const double *__restrict__ z,
+                                                double *__restrict__ w, const GState *__restrict__ st)
+{
+    if (st && st->done) return;
+    const double zsc = st ? st->zs[st->j] : 1.0;
+    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
+    const int64_t w0 = ((int64_t)blockIdx.x * (KT / WAVE) + wv) * (WAVE * NB), nn = n / 3;
+    double acc[NB];
+    int64_t nd[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int64_t row = w0 + b * WAVE + ln;
+        acc[b] = 0.0;
+        nd[b] = (row < n ? row : n - 1) / 3;
+    }
+    const int64_t f0 = w0 / 3, f1 = ((w0 + WAVE * NB < n ? w0 + WAVE * NB : n) - 1) / 3;
+    for (int d = 0; d < A.ndiag; ++d) {
+        const int64_t o = A.off[d];
+        const bool inside = f0 + o >= 0 && f1 + o < nn;
+        const double *__restrict__ p0 = A.val + (int64_t)(3 * d) * A.stride;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int64_t row = w0 + b * WAVE + ln;
+            int64_t c = nd[b] + o;
+            c = inside ? c : (c < 0 ? 0 : (c >= nn ? nn - 1 : c));
+            c *= 3;
+            acc[b] += __builtin_nontemporal_load(p0 + row) * z[c];
+            acc[b] += __builtin_nontemporal_load(p0 + A.stride + row) * z[c + 1];
+            acc[b] += __builtin_nontemporal_load(p0 + 2 * A.stride + row) * z[c + 2];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int64_t row = w0 + b * WAVE + ln;
+        if (row < n) __builtin_nontemporal_store(zsc * acc[b], &w[row]);
+    }
+}
+
 template <int G>
 __global__ __launch_bounds__(KT) void k_dot2(int64_t n, const double *__restrict__ w, const double *__restrict__ V,
                                              int64_t ldv, const GState *__restrict__ st, double *__restrict__ part,
@@ -874,6 +917,8 @@ __global__ void k_copy_stop(int64_t n, const double *__restrict__ a, double *__r
         switch (K) {                                                         \
         case -1: kern<-1><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
         case -2: kern<-2><<<grid, KT, 0, s>>>(__VA_ARGS__); break;           \
+        case -11: kern<-11><<<grid, KT, 0, s>>>(__VA_ARGS__); break;         \
+        case -12: kern<-12><<<grid, KT, 0, s>>>(__VA_ARGS__); break;         \
         case 1: kern<1><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
         case 2: kern<2><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
         case 4: kern<4><<<grid, KT, 0, s>>>(__VA_ARGS__); break;             \
@@ -934,7 +979,8 @@ static int time_product(GmresWork *W, int sel, hipStream_t s, float *ms)
 static int build_layout(SellA &S, const gs2_csr &A, int sel, const std::vector<int> &offs, hipStream_t s)
 {
     if (sel > 0) return sella_build_sell(S, A, sel, s);
-    GS2_TRY(sella_build_dia(S, A, -sel, offs, s));
+    if (sel <= -10) GS2_TRY(sella_build_b3(S, A, -sel - 10, offs, s));
+    else GS2_TRY(sella_build_dia(S, A, -sel, offs, s));
     return sella_fill_values(S, A, false, s);
 }
 
@@ -958,18 +1004,26 @@ static int prepare_matrix(GmresWork *W, const gs2_csr &A, int fmt, hipStream_t s
     sella_free(S);
     std::vector<int> offs;
     int hst = GS2_OK;
-    const bool dia_ok = fmt != GS2_FORMAT_SELL && sella_dia_offsets(A, offs, s, &hst);
+    const bool dia_ok = fmt != GS2_FORMAT_SELL && fmt != GS2_FORMAT_BLOCK3 && sella_dia_offsets(A, offs, s, &hst);
+    GS2_TRY(hst);
+    const bool b3_ok = !dia_ok && fmt != GS2_FORMAT_SELL && fmt != GS2_FORMAT_DIA && sella_b3_offsets(A, offs, s, &hst);
     GS2_TRY(hst);
     const int K0 = sella_rule_lanes(A);
     int sel = K0, tuned = 0;
     if (fmt == GS2_FORMAT_DIA && dia_ok) {
         sel = -2;
+    } else if (fmt == GS2_FORMAT_BLOCK3 && b3_ok) {
+        sel = -12;
     } else if (fmt == GS2_FORMAT_AUTO && A.n >= SPMV_TUNE_MIN_ROWS) {
         std::vector<int> cands{K0};
         if (K0 < WAVE) cands.push_back(2 * K0);
         if (dia_ok) {
             cands.push_back(-1);
             cands.push_back(-2);
+        }
+        if (b3_ok) {
+            cands.push_back(-11);
+            cands.push_back(-12);
         }
         float best = 1e30f;
         std::vector<int> timed;
@@ -1121,11 +1175,15 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                 if (orth == 0) { // delayed CGS2
                     if (fuse_fin && j > 0) P->h.fin = Handle::FinJob{W->part, nbu, st}; // closes step j-1
                     GS2_TRY(precondition(kind, P, vj, zj, n, st, cs));
-                    if (K < 0) { // diagonal copy: the product, then the dot products
+                    if (K < 0) { // diagonal or block copy: the product, then the dot products
                         {
                             Prof pr(cs, PK_SPMV, spmv_b);
-                            const unsigned gD = (unsigned)((n + (int64_t)KT * -K - 1) / ((int64_t)KT * -K));
-                            if (AD.ndiag == 7) {
+                            const int R = K <= -10 ? -K - 10 : -K;
+                            const unsigned gD = (unsigned)((n + (int64_t)KT * R - 1) / ((int64_t)KT * R));
+                            if (K <= -10) {
+                                if (K == -12) k_b3_spmv<2><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                                else k_b3_spmv<1><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
+                            } else if (AD.ndiag == 7) {
                                 if (K == -2) k_dia_spmv<2, 7><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
                                 else k_dia_spmv<1, 7><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
                             } else {
@@ -1243,9 +1301,9 @@ extern "C" int gs2_gmres_schedule(const gs2_handle *H, int *format, int *lanes_p
     const GmresWork *W = H->h.gw;
     const bool built = W && (W->A.val || W->A.dval);
     const int sel = built ? W->A.sel : 0;
-    if (format) *format = !built ? 0 : sel < 0 ? GS2_FORMAT_DIA : GS2_FORMAT_SELL;
+    if (format) *format = !built ? 0 : sel <= -10 ? GS2_FORMAT_BLOCK3 : sel < 0 ? GS2_FORMAT_DIA : GS2_FORMAT_SELL;
     if (lanes_per_row) *lanes_per_row = sel > 0 ? sel : 0;
-    if (rows_per_lane) *rows_per_lane = sel < 0 ? -sel : 0;
+    if (rows_per_lane) *rows_per_lane = sel <= -10 ? -sel - 10 : sel < 0 ? -sel : 0;
     if (ndiag) *ndiag = sel < 0 ? W->A.ndiag : 0;
     if (tuned) *tuned = built ? W->A.tuned : 0;
     return GS2_OK;

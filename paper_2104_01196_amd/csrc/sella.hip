@@ -83,6 +83,53 @@ __global__ void k_diaA_fill(int64_t n, int R, const int32_t *__restrict__ rp, co
     }
 }
 
+// 3-row block copy: plane 3 t + (c mod 3) at row r for the entry (r, c) whose
+// node offset c/3 - r/3 is o.off[t] (a row's entries are column-sorted, so
+// its node offsets ascend).
+__global__ void k_b3A_fill(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ va, DiaOffsA o, int64_t stride, double *__restrict__ val)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t node = i / 3;
+    int t = 0;
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int64_t c = ci[k], cn = c / 3;
+        const int d = (int)(cn - node);
+        while (t < o.nd - 1 && o.off[t] < d) ++t;
+        if (o.off[t] == d) val[(int64_t)(3 * t + (int)(c - 3 * cn)) * stride + i] = va[k];
+    }
+}
+
+// Distinct node offsets c/3 - r/3, ascending (host copy of the pattern);
+// false unless n is a multiple of 3, there are at most DIA_MAX of them and
+// the blocks store at most 1.5x the entries.
+static bool b3A_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st)
+{
+    *st = GS2_OK;
+    offs.clear();
+    const int64_t n = A.n;
+    if (n % 3 != 0) return false;
+    std::vector<int32_t> rp(n + 1), ci(std::max<int64_t>(A.nnz, 1));
+    if (hipMemcpyAsync(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (A.nnz && hipMemcpyAsync(ci.data(), A.colind, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, s) !=
+                      hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        *st = GS2_ERR_HIP;
+        return false;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int d = (int)((int64_t)ci[k] / 3 - i / 3);
+            auto it = std::lower_bound(offs.begin(), offs.end(), d);
+            if (it == offs.end() || *it != d) {
+                if ((int)offs.size() == DIA_MAX) return false;
+                offs.insert(it, d);
+            }
+        }
+    return 3.0 * (double)offs.size() * (double)n <= 1.5 * (double)A.nnz + 3.0 * (double)KRB * offs.size();
+}
+
 // Distinct offsets col - row of the whole pattern, ascending (host copy of
 // the pattern); false when there are more than DIA_MAX or the diagonals
 // would store more than 1.5x the entries.
@@ -127,11 +174,35 @@ int sella_build_dia(SellA &S, const gs2_csr &A, int R, const std::vector<int> &o
     return GS2_OK;
 }
 
+int sella_build_b3(SellA &S, const gs2_csr &A, int R, const std::vector<int> &offs, hipStream_t s)
+{
+    sella_free(S);
+    S.n = A.n;
+    S.nnz = A.nnz;
+    S.dR = R;
+    S.ndiag = (int)offs.size();
+    S.dstride = std::max<int64_t>(1, (A.n + KRB - 1) / KRB) * KRB;
+    for (int d = 0; d < DIA_MAX; ++d) S.doff[d] = d < S.ndiag ? offs[d] : 0;
+    const size_t bytes = sizeof(double) * 3 * (size_t)std::max(S.ndiag, 1) * (size_t)S.dstride;
+    GS2_TRY_HIP(hipMalloc(&S.dval, bytes));
+    GS2_TRY_HIP(hipMemsetAsync(S.dval, 0, bytes, s));
+    S.sel = -10 - R;
+    return GS2_OK;
+}
+
 // copy A's values into the built layout
 int sella_fill_values(SellA &S, const gs2_csr &A, bool with_col, hipStream_t s)
 {
     const int tb = 256;
-    if (S.sel < 0) {
+    if (S.sel <= -10) {
+        if (A.n > 0) {
+            DiaOffsA o;
+            o.nd = S.ndiag;
+            for (int d = 0; d < DIA_MAX; ++d) o.off[d] = S.doff[d];
+            k_b3A_fill<<<(unsigned)((A.n + tb - 1) / tb), tb, 0, s>>>(A.n, A.rowptr, A.colind, A.val, o, S.dstride,
+                                                                     S.dval);
+        }
+    } else if (S.sel < 0) {
         if (A.n > 0) {
             DiaOffsA o;
             o.nd = S.ndiag;
@@ -198,6 +269,11 @@ int sella_build_sell(SellA &S, const gs2_csr &A, int K0, hipStream_t s)
 bool sella_dia_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st)
 {
     return A.n > 0 && A.n <= (int64_t(1) << 30) && diaA_offsets(A, offs, s, st);
+}
+
+bool sella_b3_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st)
+{
+    return A.n > 0 && A.n <= (int64_t(1) << 30) && b3A_offsets(A, offs, s, st);
 }
 
 } // namespace gs2

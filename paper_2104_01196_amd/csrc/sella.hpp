@@ -43,8 +43,17 @@ struct SellA {
     int64_t dstride = 0;
     double *dval = nullptr;
     int doff[DIA_MAX] = {};
+    // Block-diagonal alternative for matrices of 3-row blocks (3 unknowns
+    // per grid node, node-major, e.g. elasticity) with at most DIA_MAX
+    // distinct node offsets c/3 - r/3: the same arrays (ndiag node offsets
+    // in doff, dval, dstride), where plane 3 d + b holds a_{r, 3(r/3 +
+    // off[d]) + b} for every row r (0 where absent), rows contiguous.  A
+    // row's three values of one block sit in three planes at the same
+    // position, and its x operands are the three consecutive entries of one
+    // node.  No column indices.
     // the product's layout: sel > 0 sliced ELL with K = sel lanes per row,
-    // sel < 0 the diagonal copy with R = -sel rows per lane
+    // -9 <= sel < 0 the diagonal copy with R = -sel rows per lane, sel <= -10
+    // the 3-row block copy with -sel - 10 rows per lane
     int sel = 1;
     int tuned = 0; // 1 if sel was chosen by timing the candidates
 };
@@ -95,6 +104,13 @@ int sella_build_sell(SellA &S, const gs2_csr &A, int K0, hipStream_t s);
 bool sella_dia_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st);
 // diagonal copy with R rows per lane (zeroed; fill with sella_fill_values)
 int sella_build_dia(SellA &S, const gs2_csr &A, int R, const std::vector<int> &offs, hipStream_t s);
+// A's distinct node offsets c/3 - r/3 when it qualifies for the 3-row
+// block copy (n divisible by 3, <= DIA_MAX offsets, the blocks storing <=
+// 1.5x the entries); *st reports HIP failures
+bool sella_b3_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st);
+// 3-row block copy for the product kernel with R rows per lane (zeroed;
+// fill with sella_fill_values)
+int sella_build_b3(SellA &S, const gs2_csr &A, int R, const std::vector<int> &offs, hipStream_t s);
 // copy A's values (and columns, for a new sliced-ELL structure) into S
 int sella_fill_values(SellA &S, const gs2_csr &A, bool with_col, hipStream_t s);
 
@@ -204,13 +220,60 @@ __device__ __forceinline__ void dia_rows(const DiaAView A, int64_t n, int64_t r0
     __syncthreads();
 }
 
+// ybuf[i] = (A z)[r0 + i] from the 3-row block copy (layout in SellA): a
+// lane owns rows 64 apart, and per block it loads its row's three values
+// (three coalesced loads from three planes) and the three z entries of the
+// neighbour node.  Node indices are clamped into [0, n/3) only where the
+// wavefront's nodes shifted by the offset leave it (a clamped node meets
+// stored zeros).  Ends with a barrier.
+template <int NW>
+__device__ __forceinline__ void b3_rows(const DiaAView A, int64_t n, int64_t r0, const double *__restrict__ z,
+                                        double *ybuf)
+{
+    constexpr int RW = KRB / NW;   // rows per wavefront
+    constexpr int NBLK = RW / WAVE; // rows per lane
+    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
+    const int64_t w0 = r0 + (int64_t)wv * RW, nn = n / 3;
+    double acc[NBLK];
+    int64_t nd[NBLK];
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        const int64_t row = w0 + b * WAVE + ln;
+        acc[b] = 0.0;
+        nd[b] = (row < n ? row : n - 1) / 3;
+    }
+    const int64_t f0 = w0 / 3, f1 = ((w0 + RW < n ? w0 + RW : n) - 1) / 3; // the wavefront's nodes
+    for (int d = 0; d < A.ndiag; ++d) {
+        const int64_t o = A.off[d];
+        const bool inside = f0 + o >= 0 && f1 + o < nn;
+        const double *__restrict__ p0 = A.val + (int64_t)(3 * d) * A.stride;
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            const int64_t row = w0 + b * WAVE + ln;
+            int64_t c = nd[b] + o;
+            if (!inside) c = c < 0 ? 0 : (c >= nn ? nn - 1 : c);
+            c *= 3;
+            acc[b] += __builtin_nontemporal_load(p0 + row) * z[c];
+            acc[b] += __builtin_nontemporal_load(p0 + A.stride + row) * z[c + 1];
+            acc[b] += __builtin_nontemporal_load(p0 + 2 * A.stride + row) * z[c + 2];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        const int64_t row = w0 + b * WAVE + ln;
+        ybuf[row - r0] = row < n ? acc[b] : 0.0;
+    }
+    __syncthreads();
+}
+
 // The product in the layout sel encodes (> 0 sliced ELL, K lanes per row;
-// < 0 the diagonal copy, -sel rows per lane).
+// -9..-1 the diagonal copy, -sel rows per lane; <= -10 the 3-row block copy).
 template <int SEL, int NW>
 __device__ __forceinline__ void mat_rows(const SellAView A, const DiaAView D, int64_t n, int64_t r0,
                                          const double *__restrict__ z, double *ybuf)
 {
     if constexpr (SEL > 0) sella_rows<SEL, KRB, NW>(A, n, r0, z, ybuf);
+    else if constexpr (SEL <= -10) b3_rows<NW>(D, n, r0, z, ybuf);
     else dia_rows<-SEL, NW>(D, n, r0, z, ybuf);
 }
 

@@ -956,7 +956,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
         return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
     if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_DIA || o.rows_per_lane < 0 || o.lds_staging < 0 ||
-        o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_DIA || o.xcd_ranges < 0 ||
+        o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_BLOCK3 || o.xcd_ranges < 0 ||
         o.xcd_ranges > 2)
         return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;

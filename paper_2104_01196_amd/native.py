@@ -23,7 +23,7 @@ NOT_CONVERGED, BREAKDOWN_EXACT, STAGNATED = 1, 2, 3
 BREAKDOWN = BREAKDOWN_EXACT  # earlier name of the same code
 FORWARD, BACKWARD, SYMMETRIC = 0, 1, 2
 FP64, FP32, FP16_SCALED = 0, 1, 2
-FORMAT_AUTO, FORMAT_SELL, FORMAT_DIA = 0, 1, 2
+FORMAT_AUTO, FORMAT_SELL, FORMAT_DIA, FORMAT_BLOCK3 = 0, 1, 2, 3
 LDS_AUTO, LDS_OFF, LDS_ON = 0, 1, 2
 XCD_AUTO, XCD_DISPATCH_ORDER, XCD_RANGES = 0, 1, 2
 PREC_NONE, PREC_GS2, PREC_JR, PREC_GS_TRISOLVE, PREC_MTGS = 0, 1, 2, 3, 4

@@ -1,6 +1,7 @@
 """GPU parity of the layouts of the GMRES solver's copy of A (the product
-w = A z of every Arnoldi step and the true residual): sliced ELL and the
-diagonal-interleaved copy (no column indices, two rows per lane), forced
+w = A z of every Arnoldi step and the true residual): sliced ELL, the
+diagonal-interleaved copy (no column indices, two rows per lane) and the
+3-row block copy (3 unknowns per node, blocks along node offsets), forced
 through the handle's spmv_format, and the timed automatic choice.  Each
 GS2-preconditioned GMRES solve is compared with the CPU oracle's solve of
 the same system: iteration count within one step (the two orthogonalise in
@@ -18,7 +19,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import paper_2104_01196_amd as g  # noqa: E402
-from gen import convdiff2d, laplace3d, make_rhs, poisson2d, random_sparse, vardiff3d  # noqa: E402
+from gen import convdiff2d, elasticity_q1, laplace3d, make_rhs, poisson2d, random_sparse, vardiff3d  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -91,6 +92,78 @@ def test_timed_layout_choice_matches_oracle():
     print(f"laplace3d_48 automatic: {sched}")
     assert sched["tuned"] == 1 and sched["format"] in (g.FORMAT_SELL, g.FORMAT_DIA)
     xo, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.FORWARD, sweeps=1, inner=1)
+    assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+ELA = {"elasticity_12x11x10": lambda: elasticity_q1(12, 11, 10, seed=3),   # 3960 rows: 4 workgroups, ragged
+       "elasticity_7x6x5": lambda: elasticity_q1(7, 6, 5, seed=4)}       # 630 rows: one partial workgroup
+
+
+@pytest.mark.parametrize("name", list(ELA))
+@pytest.mark.parametrize("fmt", [g.FORMAT_SELL, g.FORMAT_BLOCK3])
+def test_block3_copy_matches_oracle(name, fmt):
+    """The 3-row block copy on 3-dof elasticity (27 node offsets, 81 scalar
+    offsets: too many for the diagonal copy), against the oracle's GMRES(30)
+    with the damped SGS2(1,3) of the elasticity study (omega 0.7, inner
+    damping 0.5): iterations within one, true residual, solution within
+    1e-6."""
+    A = ELA[name]()
+    dA = g.DeviceCSR.from_host(A)
+    b = make_rhs(A, "normal", seed=21)[1]
+    h = g.gs2_setup(dA, 1, 3, 0.7, g.SYMMETRIC, inner_damping=0.5, spmv_format=fmt)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    info = g.gmres_solve(dA, torch.as_tensor(b, device="cuda"), x, 30, 1e-8, 5000, g.PREC_GS2, h)
+    sched = g.gs2_gmres_schedule(h)
+    assert sched["format"] == fmt and sched["tuned"] == 0, sched
+    if fmt == g.FORMAT_BLOCK3:
+        nodes = A.n // 3
+        rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+        assert sched["rows_per_lane"] == 2
+        assert sched["ndiag"] == len(np.unique(A.colind // 3 - rows // 3)) == 27 and nodes * 3 == A.n
+    xo, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=3,
+                          omega=0.7, gamma=0.5)
+    xs = x.cpu().numpy()
+    rel = np.linalg.norm(b - A.to_scipy() @ xs) / np.linalg.norm(b)
+    print(f"{name} fmt {fmt}: {sched}, GPU {info['iterations']} its, oracle {io['iterations']}, relres {rel:.2e}")
+    assert info["converged"] and rel <= 1e-8
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_block3_refused_where_it_does_not_apply():
+    """Forced block copy on matrices that do not qualify falls back to sliced
+    ELL: a row count not divisible by 3, and scattered columns with far more
+    than 32 node offsets (3000 rows)."""
+    for A in (laplace3d(10), random_sparse(3000, seed=5, avg_offdiag=6)):
+        dA = g.DeviceCSR.from_host(A)
+        b = make_rhs(A, "normal", seed=22)[1]
+        h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, spmv_format=g.FORMAT_BLOCK3)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        info = g.gmres_solve(dA, torch.as_tensor(b, device="cuda"), x, 30, 1e-8, 5000, g.PREC_GS2, h)
+        assert g.gs2_gmres_schedule(h)["format"] == g.FORMAT_SELL
+        xo, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=1)
+        assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1
+
+
+@pytest.mark.slow
+def test_block3_timed_choice_on_elasticity():
+    """Automatic choice on an elasticity matrix large enough to be timed
+    (98,304 rows): every candidate (sliced ELL at two lane counts, the block
+    copy at one and two rows per lane) builds and runs; the solve matches the
+    oracle."""
+    A = elasticity_q1(32, 32, 32, seed=5)
+    dA = g.DeviceCSR.from_host(A)
+    b = make_rhs(A, "normal", seed=23)[1]
+    h = g.gs2_setup(dA, 1, 3, 0.7, g.SYMMETRIC, inner_damping=0.5)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    info = g.gmres_solve(dA, torch.as_tensor(b, device="cuda"), x, 50, 1e-8, 20000, g.PREC_GS2, h)
+    sched = g.gs2_gmres_schedule(h)
+    print(f"elasticity 32^3 automatic: {sched}, {info['iterations']} its")
+    assert sched["tuned"] == 1
+    xo, io = oracle.gmres(A, b, restart=50, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=3,
+                          omega=0.7, gamma=0.5)
     assert info["converged"] and abs(info["iterations"] - io["iterations"]) <= 1
     xs = x.cpu().numpy()
     assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-6
