@@ -110,8 +110,8 @@ typedef struct gs2_options {
                           /* at all, which forces that path, for tests)      */
     int format;           /* storage of L and U for the GS2 / JR passes:     */
                           /* GS2_FORMAT_AUTO (0, timed at setup), _SELL (1), */
-                          /* _DIA (2; GS2_ERR_ARG if the matrix does not     */
-                          /* qualify, see gs2_setup)                         */
+                          /* _DIA (2) or _BLOCK3 (3; these two GS2_ERR_ARG   */
+                          /* if the matrix does not qualify, see gs2_setup)  */
     int rows_per_lane;    /* diagonal layout: rows per lane R (vector width  */
                           /* R x value bytes, 2..16): 0 = timed, else forced */
     int lds_staging;      /* diagonal layout: stage the source vector in LDS */
@@ -142,9 +142,10 @@ typedef struct gs2_options {
 #define GS2_FORMAT_AUTO 0
 #define GS2_FORMAT_SELL 1 /* sliced ELL, K lanes per row, column indices   */
 #define GS2_FORMAT_DIA 2  /* diagonal-interleaved, no column indices       */
-#define GS2_FORMAT_BLOCK3 3 /* spmv_format only: 3-row blocks along node   */
-                            /* offsets (3 unknowns per node, node-major),  */
-                            /* no column indices                           */
+#define GS2_FORMAT_BLOCK3 3 /* 3-row blocks along node offsets c/3 - r/3  */
+                            /* (3 unknowns per node, node-major; <= 32     */
+                            /* node offsets per triangle), no column       */
+                            /* indices                                     */
 
 typedef struct gs2_solve_info {
     int iterations; /* Arnoldi steps (preconditioner applications)          */
@@ -171,7 +172,10 @@ void gs2_default_options(gs2_options *opt);
  * (stencil matrices in natural order), their stored diagonals hold at most
  * 1.5x the entries, n <= 2^30 and blocks <= 1, a second, diagonal-
  * interleaved copy is built and the passes use whichever layout the timing
- * picks (gs2_handle_schedule).  sweeps >= 1 outer sweeps (n_t n_k of Fig. code:two-stage on one
+ * picks (gs2_handle_schedule); failing that, when n is a multiple of 3 and
+ * each triangle has at most 32 node offsets c/3 - r/3 (3 unknowns per grid
+ * node, node-major, e.g. elasticity) whose 3-row blocks hold at most 1.5x
+ * the entries, the second copy is the 3-row block layout.  sweeps >= 1 outer sweeps (n_t n_k of Fig. code:two-stage on one
  * GPU), inner >= 0 inner JR sweeps (inner = 0 is Jacobi-Richardson), damping
  * w in (0, 2) (Section 4, damping factor), variant GS2_FORWARD/BACKWARD/
  * SYMMETRIC, opt may be NULL.  A's arrays are only read during the call; the
@@ -316,16 +320,19 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
 
 /*
  * The schedule the setup chose for the GS2 / JR passes (host outputs, any
- * may be NULL): format GS2_FORMAT_SELL or GS2_FORMAT_DIA; lanes_per_row of
- * the sliced-ELL layout; rows_per_lane and vector_bytes (rows_per_lane x
- * value bytes, the width of one value load), lds_staging (0/1) and
- * xcd_ranges (1 if each XCD walks its own range of rows, 0 for dispatch
- * order) of the diagonal layout (0 when it is not used); ndiag_l / ndiag_u, the diagonals
- * of L and U (0 if the matrix does not qualify for the diagonal layout);
+ * may be NULL): format GS2_FORMAT_SELL, GS2_FORMAT_DIA or
+ * GS2_FORMAT_BLOCK3; lanes_per_row of the sliced-ELL layout; rows_per_lane
+ * and vector_bytes (rows_per_lane x value bytes, the width of one value
+ * load), lds_staging (0/1) and xcd_ranges (1 if each XCD walks its own range
+ * of rows, 0 for dispatch order) of the diagonal or block layout (0 when it
+ * is not used); ndiag_l / ndiag_u, the diagonals (block layout: node
+ * offsets) of L and U (0 if the matrix qualifies for neither);
  * tuned = 1 if the choice was timed (or taken from the process-wide cache of
  * timed choices), 0 if it was forced or defaulted.  Candidates and timing:
  * the sliced-ELL layout at K = 1, 2, 4, ... lanes per row, then the diagonal
- * layout at every rows_per_lane whose load is 2 to 16 bytes, with and
+ * layout (<= 32 offsets per triangle) or, failing that, the 3-row block
+ * layout (n a multiple of 3, <= 32 node offsets per triangle, no LDS
+ * staging) at every rows_per_lane whose load is 2 to 16 bytes, with and
  * without LDS staging, with and without per-XCD ranges; each is timed on
  * one inner pass over L plus one residual pass over L and U (Section 4
  * passes), the fastest kept.

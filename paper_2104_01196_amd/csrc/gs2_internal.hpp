@@ -208,7 +208,11 @@ struct Dia {
     void *val = nullptr;
     int val_bytes = 8;
     int nt = 0; // stream the values with the non-temporal policy
-    double stored_bytes() const { return (double)ndiag * (double)stride * val_bytes; }
+    // 3-row blocks (3 unknowns per node, node-major): off[] holds node
+    // offsets c/3 - r/3, and plane 3 d + b (b < 3) holds a_{r, 3(r/3 +
+    // off[d]) + b} at row r's interleaved position
+    int b3 = 0;
+    double stored_bytes() const { return (double)ndiag * (b3 ? 3.0 : 1.0) * (double)stride * val_bytes; }
 };
 
 // The schedule the setup picked for the sweep kernels.

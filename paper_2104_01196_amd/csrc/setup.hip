@@ -332,6 +332,31 @@ static bool dia_offsets(const std::vector<int32_t> &rp, const std::vector<int32_
     return true;
 }
 
+// The same for 3-row blocks (n a multiple of 3): distinct node offsets c/3 -
+// r/3 of the strictly lower entries (c < r, node offsets <= 0) and of the
+// strictly upper ones (node offsets >= 0).  False when n is not a multiple
+// of 3 or either part has more than DIA_MAX node offsets.
+static bool b3_offsets(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci, int64_t n,
+                       std::vector<int> &offL, std::vector<int> &offU)
+{
+    offL.clear();
+    offU.clear();
+    if (n % 3 != 0) return false;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            if ((int64_t)ci[k] == i) continue;
+            const int d = (int)((int64_t)ci[k] / 3 - i / 3);
+            std::vector<int> &o = (int64_t)ci[k] < i ? offL : offU;
+            auto it = std::lower_bound(o.begin(), o.end(), d);
+            if (it == o.end() || *it != d) {
+                if ((int)o.size() == DIA_MAX) return false;
+                o.insert(it, d);
+            }
+        }
+    }
+    return true;
+}
+
 // One thread per row: the row's entries of one part go to their diagonal at
 // the row's interleaved position, value (s_l[i] * a_ij) * s_r[j] rounded once
 // to VT.  The array is zeroed beforehand (rows past n and absent entries).
@@ -361,17 +386,49 @@ __global__ void k_dia_fill(int64_t n, int R, const int32_t *__restrict__ rp, con
     if (ovf) atomicOr(err, ERRF_FP16);
 }
 
+// The 3-row block layout: entry (i, c) of the part goes to plane
+// 3 t + (c mod 3), t the index of its node offset c/3 - i/3, at row i's
+// interleaved position; scaled and rounded as in k_dia_fill.
+template <typename VT>
+__global__ void k_b3_fill(int64_t n, int R, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                          const double *__restrict__ va, const int32_t *__restrict__ lcnt, int lower, DiaOffs o,
+                          const double *__restrict__ sl, const double *__restrict__ sr, int64_t stride,
+                          VT *__restrict__ val, int *__restrict__ err)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t blk = (int64_t)WAVE * R;
+    const int64_t pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
+    const int64_t b = lower ? rp[i] : rp[i] + lcnt[i] + 1, e = lower ? rp[i] + lcnt[i] : rp[i + 1];
+    const double srow = sl[i];
+    const int64_t node = i / 3;
+    int t = 0, ovf = 0;
+    for (int64_t k = b; k < e; ++k) {
+        const int c = ci[k];
+        const int cn = c / 3;
+        const int d = (int)((int64_t)cn - node);
+        while (t < o.nd - 1 && o.off[t] < d) ++t; // node offsets ascend within a row
+        if (o.off[t] != d) {
+            atomicOr(err, ERRF_BAD_CSR); // cannot happen for a pattern the offsets came from
+            return;
+        }
+        val[(int64_t)(3 * t + (c - 3 * cn)) * stride + pos] = convert_scaled<VT>((srow * va[k]) * sr[c], &ovf);
+    }
+    if (ovf) atomicOr(err, ERRF_FP16);
+}
+
 // Build one triangle (lower or upper) in the diagonal-interleaved layout
 // with R rows per lane; rows are padded to whole workgroups of the sweep
 // kernels (DIA_THREADS * R rows) so that every launched lane has a slot.
 static int build_dia(Dia &D, int64_t n, int precision, int lower, int R, const std::vector<int> &offs, int64_t nnz,
                      const gs2_csr &A, const int32_t *lcnt, const double *sl, const double *sr, int *err,
-                     hipStream_t s)
+                     hipStream_t s, int b3 = 0)
 {
     free_dia(D);
     D.ndiag = (int)offs.size();
     D.R = R;
     D.nnz = nnz;
+    D.b3 = b3;
     D.val_bytes = precision == GS2_FP64 ? 8 : precision == GS2_FP32 ? 4 : 2;
     const int64_t wg = (int64_t)DIA_THREADS * R;
     D.stride = std::max<int64_t>(1, (n + wg - 1) / wg) * wg;
@@ -381,13 +438,23 @@ static int build_dia(Dia &D, int64_t n, int precision, int lower, int R, const s
         D.off[d] = d < D.ndiag ? offs[d] : 0;
         o.off[d] = D.off[d];
     }
-    const size_t bytes = (size_t)std::max(1, D.ndiag) * (size_t)D.stride * D.val_bytes;
+    const size_t bytes = (size_t)std::max(1, D.ndiag) * (b3 ? 3 : 1) * (size_t)D.stride * D.val_bytes;
     GS2_TRY_HIP(hipMalloc(&D.val, bytes));
     GS2_TRY_HIP(hipMemsetAsync(D.val, 0, bytes, s));
     if (D.ndiag == 0 || n == 0) return GS2_OK;
     const int tb = 256;
     const unsigned g = (unsigned)((n + tb - 1) / tb);
-    if (precision == GS2_FP64)
+    if (b3) {
+        if (precision == GS2_FP64)
+            k_b3_fill<double><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
+                                               (double *)D.val, err);
+        else if (precision == GS2_FP32)
+            k_b3_fill<float><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
+                                              (float *)D.val, err);
+        else
+            k_b3_fill<_Float16><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
+                                                 (_Float16 *)D.val, err);
+    } else if (precision == GS2_FP64)
         k_dia_fill<double><<<g, tb, 0, s>>>(n, R, A.rowptr, A.colind, A.val, lcnt, lower, o, sl, sr, D.stride,
                                             (double *)D.val, err);
     else if (precision == GS2_FP32)
@@ -585,12 +652,13 @@ static int64_t count_total(const int32_t *tot, int64_t n, hipStream_t s, int *st
 // Schedules of the diagonal layout chosen by timing, per (size bucket, mean
 // row length, longest-row bucket, precision, diagonal counts).
 struct DiaChoice {
-    int fmt, R, lds, remap;
+    int fmt, R, lds, remap, b3;
 };
 static std::map<std::string, DiaChoice> g_dia_cache;
 
 // Decide the layout of the GS2 / JR passes: keep the sliced-ELL triangles, or
-// build diagonal-interleaved copies (Dia) and time them against sliced ELL.
+// build diagonal-interleaved copies (Dia: scalar diagonals, or 3-row blocks
+// along node offsets) and time them against sliced ELL.
 static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, SetupScratch &sc, hipStream_t s,
                          bool can_time, const std::string &key_base)
 {
@@ -601,54 +669,68 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
     // the automatic choice is made by timing only; without it sliced ELL stays
     if (o.format == GS2_FORMAT_AUTO && !(can_time && o.autotune)) return GS2_OK;
     const int64_t n = h.n;
-    bool ok = h.blocks == 1 && n > 0 && n <= (int64_t(1) << 30);
-    std::vector<int> offL, offU;
+    const bool any = h.blocks == 1 && n > 0 && n <= (int64_t(1) << 30);
+    std::vector<int> offL, offU, boffL, boffU;
     int64_t nnzL = 0, nnzU = 0;
-    if (ok) {
+    bool dia_ok = false, b3_ok = false;
+    if (any) {
         std::vector<int32_t> rp(n + 1), ci(std::max<int64_t>(A.nnz, 1));
         GS2_TRY_HIP(hipMemcpyAsync(rp.data(), A.rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
         if (A.nnz)
             GS2_TRY_HIP(hipMemcpyAsync(ci.data(), A.colind, sizeof(int32_t) * A.nnz, hipMemcpyDeviceToHost, s));
         GS2_TRY_HIP(hipStreamSynchronize(s));
-        ok = dia_offsets(rp, ci, n, offL, offU, nnzL, nnzU);
-        // stored diagonal entries (padding included) at most 1.5x the real ones
-        ok = ok && (double)offL.size() * n <= 1.5 * nnzL + 64.0 * offL.size() &&
-             (double)offU.size() * n <= 1.5 * nnzU + 64.0 * offU.size();
+        if (o.format != GS2_FORMAT_BLOCK3) {
+            dia_ok = dia_offsets(rp, ci, n, offL, offU, nnzL, nnzU);
+            // stored diagonal entries (padding included) at most 1.5x the real ones
+            dia_ok = dia_ok && (double)offL.size() * n <= 1.5 * nnzL + 64.0 * offL.size() &&
+                     (double)offU.size() * n <= 1.5 * nnzU + 64.0 * offU.size();
+        }
+        if (!dia_ok && o.format != GS2_FORMAT_DIA) {
+            nnzL = nnzU = 0; // dia_offsets may have stopped part way
+            for (int64_t i = 0; i < n; ++i)
+                for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                    if ((int64_t)ci[k] != i) ((int64_t)ci[k] < i ? nnzL : nnzU)++;
+            b3_ok = b3_offsets(rp, ci, n, boffL, boffU) &&
+                    3.0 * boffL.size() * n <= 1.5 * nnzL + 192.0 * boffL.size() &&
+                    3.0 * boffU.size() * n <= 1.5 * nnzU + 192.0 * boffU.size();
+        }
     }
-    h.DL.ndiag = ok ? (int)offL.size() : 0;
-    h.DU.ndiag = ok ? (int)offU.size() : 0;
-    if (!ok) return o.format == GS2_FORMAT_DIA ? GS2_ERR_ARG : GS2_OK;
+    h.DL.ndiag = dia_ok ? (int)offL.size() : b3_ok ? (int)boffL.size() : 0;
+    h.DU.ndiag = dia_ok ? (int)offU.size() : b3_ok ? (int)boffU.size() : 0;
+    if (!dia_ok && !b3_ok) return o.format == GS2_FORMAT_AUTO ? GS2_OK : GS2_ERR_ARG;
+    const int b3 = dia_ok ? 0 : 1; // the one diagonal kind this pattern admits
     const int vb = h.precision == GS2_FP64 ? 8 : h.precision == GS2_FP32 ? 4 : 2;
     std::vector<int> Rs, ldss;
     for (int R = 1; R <= 8; R *= 2)
         if (R * vb >= 2 && R * vb <= 16 && (o.rows_per_lane == 0 || o.rows_per_lane == R)) Rs.push_back(R);
     if (Rs.empty()) return GS2_ERR_ARG; // a forced rows-per-lane whose load is not 2..16 bytes
-    if (o.lds_staging == 0) ldss = {0, 1};
+    if (b3) ldss = {0}; // block passes read their source directly
+    else if (o.lds_staging == 0) ldss = {0, 1};
     else ldss = {o.lds_staging == 2 ? 1 : 0};
     std::vector<int> rms;
     if (o.xcd_ranges == 0) rms = {1, 0};
     else rms = {o.xcd_ranges == 2 ? 1 : 0};
     auto build = [&](int R) -> int {
-        GS2_TRY(build_dia(h.DL, n, h.precision, 1, R, offL, nnzL, A, sc.lcnt, h.sl, h.sr, sc.err, s));
-        GS2_TRY(build_dia(h.DU, n, h.precision, 0, R, offU, nnzU, A, sc.lcnt, h.sl, h.sr, sc.err, s));
+        GS2_TRY(build_dia(h.DL, n, h.precision, 1, R, b3 ? boffL : offL, nnzL, A, sc.lcnt, h.sl, h.sr, sc.err, s, b3));
+        GS2_TRY(build_dia(h.DU, n, h.precision, 0, R, b3 ? boffU : offU, nnzU, A, sc.lcnt, h.sl, h.sr, sc.err, s, b3));
         h.DL.nt = h.DU.nt = h.DL.stored_bytes() + h.DU.stored_bytes() > NT_TRIANGLES_BYTES ? 1 : 0;
         return GS2_OK;
     };
     const bool timed = can_time && o.autotune &&
                        (o.format == GS2_FORMAT_AUTO || Rs.size() > 1 || ldss.size() > 1 || rms.size() > 1);
     if (!timed) {
-        if (o.format != GS2_FORMAT_DIA) return GS2_OK; // untimed automatic choice: sliced ELL
+        if (o.format == GS2_FORMAT_AUTO) return GS2_OK; // untimed automatic choice: sliced ELL
         GS2_TRY(build(Rs.back()));                       // forced: the widest load allowed
         h.fmt = FMT_DIA;
         h.lds = ldss.back();
         h.remap = rms.front();
         return GS2_OK;
     }
-    char kb[48];
-    std::snprintf(kb, sizeof kb, "_d%d_%d_f%d_r%d_s%d_x%d", h.DL.ndiag, h.DU.ndiag, o.format, o.rows_per_lane,
+    char kb[56];
+    std::snprintf(kb, sizeof kb, "_d%d_%d_b%d_f%d_r%d_s%d_x%d", h.DL.ndiag, h.DU.ndiag, b3, o.format, o.rows_per_lane,
                   o.lds_staging, o.xcd_ranges);
     const std::string key = key_base + kb;
-    DiaChoice ch{FMT_SELL, 0, 0, 1};
+    DiaChoice ch{FMT_SELL, 0, 0, 1, 0};
     bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -676,7 +758,7 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
                     // a new candidate must win by more than the timing noise
                     if (ms < 0.97f * best) {
                         best = ms;
-                        ch = DiaChoice{FMT_DIA, R, l, rm};
+                        ch = DiaChoice{FMT_DIA, R, l, rm, b3};
                     }
                 }
         }
@@ -955,7 +1037,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
         (int64_t)o.blocks > std::max<int64_t>(A->n, 1))
         return GS2_ERR_ARG;
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
-    if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_DIA || o.rows_per_lane < 0 || o.lds_staging < 0 ||
+    if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_BLOCK3 || o.rows_per_lane < 0 || o.lds_staging < 0 ||
         o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_BLOCK3 || o.xcd_ranges < 0 ||
         o.xcd_ranges > 2)
         return GS2_ERR_ARG;
@@ -1047,7 +1129,7 @@ int gs2_handle_schedule(const gs2_handle *H, int *format, int *lanes_per_row, in
     if (!H) return GS2_ERR_ARG;
     const Handle &h = H->h;
     const bool dia = h.fmt == FMT_DIA;
-    if (format) *format = dia ? GS2_FORMAT_DIA : GS2_FORMAT_SELL;
+    if (format) *format = !dia ? GS2_FORMAT_SELL : h.DL.b3 ? GS2_FORMAT_BLOCK3 : GS2_FORMAT_DIA;
     if (lanes_per_row) *lanes_per_row = h.L.K;
     if (rows_per_lane) *rows_per_lane = dia ? h.DL.R : 0;
     if (vector_bytes) *vector_bytes = dia ? h.DL.R * h.DL.val_bytes : 0;

@@ -349,6 +349,7 @@ static_assert(DIA_THREADS == KT, "one workgroup size for the diagonal passes and
 struct DiaView {
     int ndiag;
     int nt;
+    int b3;
     int64_t stride;
     const void *val;
     int off[DIA_MAX];
@@ -356,14 +357,20 @@ struct DiaView {
 
 // compile-time flags of the diagonal passes: LDS staging of the source, and
 // the non-temporal cache policy for the values
-enum : int { DIA_FL_LDS = 1, DIA_FL_NT = 2 };
-static int dia_flags(const Handle &h, const Dia &D) { return (h.lds ? DIA_FL_LDS : 0) | (D.nt ? DIA_FL_NT : 0); }
+// and 3-row blocks (never staged in LDS)
+enum : int { DIA_FL_LDS = 1, DIA_FL_NT = 2, DIA_FL_B3 = 4 };
+static int dia_flags(const Handle &h, const Dia &D)
+{
+    if (D.b3) return DIA_FL_B3 | (D.nt ? DIA_FL_NT : 0);
+    return (h.lds ? DIA_FL_LDS : 0) | (D.nt ? DIA_FL_NT : 0);
+}
 
 static DiaView dview(const Dia &D)
 {
     DiaView v;
     v.ndiag = D.ndiag;
     v.nt = D.nt;
+    v.b3 = D.b3;
     v.stride = D.stride;
     v.val = D.val;
     for (int d = 0; d < DIA_MAX; ++d) v.off[d] = D.off[d];
@@ -449,6 +456,45 @@ __device__ __forceinline__ void dia_dots(const DiaView &T, int64_t pos, int w0, 
     }
 }
 
+// The same sums on a 3-row block triangle: per node offset o, the three
+// planes' values of the lane's R rows (one load each) and the source at the
+// three unknowns 3(node + o) .. 3(node + o) + 2 of the neighbour node, node =
+// row / 3.  Node indices are clamped into [0, n/3) only in workgroups whose
+// nodes, shifted by o, leave that range (a uniform test per offset; a
+// clamped node meets stored zeros).  Rows past n read in-bounds padding.
+template <typename VT, typename AT, int R, bool NT, typename Src>
+__device__ __forceinline__ void b3_dots(const DiaView &T, int64_t pos, int w0, int rb, int n, Src src, AT (&acc)[R])
+{
+    constexpr int RB = DIA_THREADS * R;
+    const VT *__restrict__ val = (const VT *)T.val;
+    const int nn = n / 3;
+    const int f0 = w0 / 3, f1 = ((w0 + RB < n ? w0 + RB : n) - 1) / 3;
+    int node[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int row = rb + k * WAVE;
+        node[k] = (row < n ? row : n - 1) / 3;
+    }
+#pragma unroll 2
+    for (int d = 0; d < T.ndiag; ++d) {
+        const int o = T.off[d];
+        const bool inside = f0 + o >= 0 && f1 + o < nn;
+        int c0[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int c = node[k] + o;
+            c0[k] = 3 * (inside ? c : (c < 0 ? 0 : (c >= nn ? nn - 1 : c)));
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            AT a[R];
+            dia_vals<VT, AT, R, NT>(val + (int64_t)(3 * d + b) * T.stride + pos, a);
+#pragma unroll
+            for (int k = 0; k < R; ++k) acc[k] += a[k] * src(c0[k] + b);
+        }
+    }
+}
+
 // Copy src over [base, base + span) into xs (columns clamped into [0, n));
 // thread 0 also reads the stop flag, so that every wavefront of the workgroup
 // takes the same early exit after the barrier.  Returns the flag.
@@ -475,7 +521,8 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
                                                   const double *__restrict__ sr, const double *__restrict__ fpart,
                                                   int fnb, void *fst)
 {
-    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT;
+    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT, B3 = FL & DIA_FL_B3;
+    static_assert(!(LDS && B3), "3-row block passes are not staged in LDS");
     constexpr int RB = DIA_THREADS * R; // rows per workgroup
     constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
     if constexpr (FIN) {
@@ -506,6 +553,10 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
             if (dia_stage<AT, SPAN>(xs, base, n, sg, stop, &sflag)) return;
             dia_dots<VT, AT, R, true, NT, ND>(T, pos, w0, rb, n, sg, xs, base, acc);
         }
+    } else if constexpr (B3) {
+        if (stop && *stop) return;
+        if (gv) b3_dots<VT, AT, R, NT>(T, pos, w0, rb, n, sv, acc);
+        else b3_dots<VT, AT, R, NT>(T, pos, w0, rb, n, sg, acc);
     } else {
         if (stop && *stop) return;
         if (gv) dia_dots<VT, AT, R, false, NT, ND>(T, pos, w0, rb, n, sv, nullptr, 0, acc);
@@ -575,7 +626,8 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
                                                   AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
                                                   const double *__restrict__ sr)
 {
-    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT;
+    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT, B3 = FL & DIA_FL_B3;
+    static_assert(!(LDS && B3), "3-row block passes are not staged in LDS");
     constexpr int RB = DIA_THREADS * R;
     constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
     const int wg = remap ? (int)xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -597,6 +649,12 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
         if (ND > 0 || two) dia_dots<VT, AT, R, true, NT, ND>(Q, pos, w0, rb, n, sx, xs, base, acc);
 #pragma unroll
         for (int k = 0; k < R; ++k) own[k] = xs[rb + k * WAVE - base];
+    } else if constexpr (B3) {
+        if (stop && *stop) return;
+        b3_dots<VT, AT, R, NT>(P, pos, w0, rb, n, sx, acc);
+        if (two) b3_dots<VT, AT, R, NT>(Q, pos, w0, rb, n, sx, acc);
+#pragma unroll
+        for (int k = 0; k < R; ++k) own[k] = xh[clamp_col(rb + k * WAVE, n)];
     } else {
         if (stop && *stop) return;
         dia_dots<VT, AT, R, false, NT, ND>(P, pos, w0, rb, n, sx, nullptr, 0, acc);
@@ -693,7 +751,7 @@ struct Launch {
         const DiaView dv = dview(T);
         const int n = (int)h.n;
         // three diagonals per triangle (7-point stencils): the loop over them unrolled
-        if (T.ndiag == 3) {
+        if (T.ndiag == 3 && !(FL & DIA_FL_B3)) {
             if (fj.st)
                 k_dia_inner<VT, AT, R, FL, true, 3><<<grid, DIA_THREADS, 0, s>>>(
                     h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
@@ -721,7 +779,9 @@ struct Launch {
         case 0: dia_inner_r<R, 0>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
         case 1: dia_inner_r<R, 1>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
         case 2: dia_inner_r<R, 2>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
-        default: dia_inner_r<R, 3>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 3: dia_inner_r<R, 3>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        case 4: dia_inner_r<R, 4>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
+        default: dia_inner_r<R, 6>(h, T, rh, gin, v, rv, gv, dst, gout, xh, z, s, fj); break;
         }
     }
     static void dia_inner_l(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
@@ -751,7 +811,7 @@ struct Launch {
         // ND = 3 kernels always add both triangles (no branch on `two`, so the
         // loads of all six diagonals are issued together); one triangle (the
         // compact form's residual) takes the general kernel
-        if (P.ndiag == 3 && Q && Q->ndiag == 3)
+        if (P.ndiag == 3 && Q && Q->ndiag == 3 && !(FL & DIA_FL_B3))
             k_dia_resid<VT, AT, R, FL, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
                                                                        Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
                                                                        h.sl, svp, cdiag, w, dst, rh, xout, z, h.sr);
@@ -768,7 +828,9 @@ struct Launch {
         case 0: dia_resid_r<R, 0>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
         case 1: dia_resid_r<R, 1>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
         case 2: dia_resid_r<R, 2>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
-        default: dia_resid_r<R, 3>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
+        case 3: dia_resid_r<R, 3>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
+        case 4: dia_resid_r<R, 4>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
+        default: dia_resid_r<R, 6>(h, P, Q, xh, v, svp, cdiag, w, dst, rh, xout, z, s); break;
         }
     }
     static void dia_resid_l(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,

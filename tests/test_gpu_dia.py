@@ -190,6 +190,76 @@ def test_dia_gmres_iterations(prec, lds, xcd):
     assert abs(info["iterations"] - io["iterations"]) <= 1, (info, io)
 
 
+B3MATS = {"elasticity_12x11x10": lambda: elasticity_q1(12, 11, 10, seed=7),  # 3960 rows, ragged workgroups
+          "elasticity_5x6x7": lambda: elasticity_q1(5, 6, 7, seed=8)}       # 630 rows: one partial workgroup
+
+
+def b3_schedules():
+    for prec, Rs in R_OF.items():
+        for R in Rs:
+            for xcd in (g.XCD_RANGES, g.XCD_DISPATCH_ORDER):
+                yield prec, R, xcd
+
+
+@pytest.mark.parametrize("name", list(B3MATS))
+@pytest.mark.parametrize("prec,R,xcd", list(b3_schedules()))
+def test_block3_apply_every_schedule(name, prec, R, xcd):
+    """The 3-row block layout of the triangles (3-dof elasticity: 81 scalar
+    offsets, too many for the diagonal layout; 14 node offsets per triangle,
+    the diagonal block's strictly lower / upper entries included) at every
+    rows-per-lane and both workgroup walks, against the oracle at the same
+    bars as the diagonal layout."""
+    A = B3MATS[name]()
+    dA = g.DeviceCSR.from_host(A)
+    v = np.random.default_rng(17).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    for variant, sweeps, inner, w in CASES:
+        h = g.gs2_setup(dA, sweeps, inner, w, variant, precision=prec, format=g.FORMAT_BLOCK3, rows_per_lane=R,
+                        xcd_ranges=xcd)
+        sch = g.gs2_handle_schedule(h)
+        assert (sch["format"], sch["rows_per_lane"], sch["lds_staging"], sch["xcd_ranges"]) == \
+            (g.FORMAT_BLOCK3, R, False, xcd == g.XCD_RANGES)
+        assert sch["ndiag_l"] == 14 and sch["ndiag_u"] == 14, sch
+        g.gs2_apply(h, dev(v), z)
+        ref = reference(A, v, prec, variant, sweeps, inner, w)
+        halves = sweeps * (2 if variant == g.SYMMETRIC else 1)
+        tol = TOL[prec] or 1e-12 * halves
+        assert rel_inf(host(z), ref) <= tol, (variant, sweeps, inner, w, rel_inf(host(z), ref))
+
+
+@pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
+def test_block3_damping_compact_and_gmres(prec):
+    """On the block layout: inner damping gamma and the compact form (against
+    the oracle's float64 forms, with the reduced-precision bars of
+    test_dia_reduced_precision_damping_and_compact), and GMRES(30) within
+    one iteration of the oracle's solve in the same form: with SGS2(2,3) at
+    omega 0.4 (the oracle's reduced-precision forms have no inner damping;
+    undamped SGS2 at omega 1 stagnates on elasticity), and in float64 also
+    with the elasticity study's SGS2(1,3), omega 0.7, gamma 0.5."""
+    A = B3MATS["elasticity_12x11x10"]()
+    dA = g.DeviceCSR.from_host(A)
+    v = np.random.default_rng(18).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    bar = {g.FP64: 4e-12, g.FP32: 1e-5, g.FP16_SCALED: 3e-3}[prec]
+    h = g.gs2_setup(dA, 2, 3, 0.9, g.SYMMETRIC, precision=prec, inner_damping=0.6, format=g.FORMAT_BLOCK3)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), oracle.gs2_apply(A, v, g.SYMMETRIC, 2, 3, 0.9, 0.6)) <= bar
+    h = g.gs2_setup(dA, 2, 1, 0.8, g.FORWARD, precision=prec, compact=True, format=g.FORMAT_BLOCK3)
+    g.gs2_apply(h, dev(v), z)
+    assert rel_inf(host(z), oracle.gs2c_sweep(A, v, np.zeros(A.n), g.FORWARD, 2, 1, 0.8)) <= bar
+    b = np.random.default_rng(19).standard_normal(A.n)
+    settings = [(2, 3, 0.4, 1.0)] + ([(1, 3, 0.7, 0.5)] if prec == g.FP64 else [])
+    for sweeps, inner, w, gamma in settings:
+        _, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=sweeps,
+                             inner=inner, omega=w, gamma=gamma, precision=prec)
+        h = g.gs2_setup(dA, sweeps, inner, w, g.SYMMETRIC, precision=prec, inner_damping=gamma,
+                        format=g.FORMAT_BLOCK3)
+        x = torch.zeros(A.n, dtype=torch.float64, device=DEV)
+        info = g.gmres_solve(dA, dev(b), x, 30, 1e-8, 5000, g.PREC_GS2, h)
+        assert io["converged"] and info["converged"], (info, io)
+        assert abs(info["iterations"] - io["iterations"]) <= 1, (sweeps, inner, w, gamma, info, io)
+
+
 def test_dia_eligibility():
     """The diagonal layout is refused where it does not apply: too many
     distinct offsets (3-dof elasticity), hybrid blocks, or a rows-per-lane
@@ -212,6 +282,15 @@ def test_dia_eligibility():
     R = random_sparse(500, seed=3, avg_offdiag=6)
     sch = g.gs2_handle_schedule(g.gs2_setup(g.DeviceCSR.from_host(R), 1, 1, 1.0, g.FORWARD))
     assert sch["format"] == g.FORMAT_SELL
+    # the 3-row block layout: refused for a row count not divisible by 3, for
+    # scattered columns (far more than 32 node offsets), for hybrid blocks
+    for M in (dL, g.DeviceCSR.from_host(random_sparse(600, seed=4, avg_offdiag=6))):
+        with pytest.raises(g.Gs2Error):
+            g.gs2_setup(M, 1, 1, 1.0, g.FORWARD, format=g.FORMAT_BLOCK3)
+    with pytest.raises(g.Gs2Error):
+        g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD, blocks=2, format=g.FORMAT_BLOCK3)
+    sch = g.gs2_handle_schedule(g.gs2_setup(dA, 1, 1, 1.0, g.FORWARD, format=g.FORMAT_BLOCK3))
+    assert sch["format"] == g.FORMAT_BLOCK3 and sch["ndiag_l"] == sch["ndiag_u"] == 14
 
 
 @pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
