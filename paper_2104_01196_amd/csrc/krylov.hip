@@ -13,6 +13,7 @@
 // quantity sums the partials in a fixed order.  No floating-point atomics.
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -62,6 +63,9 @@ struct GmresWork {
     CycleKey key;
     SellA A;         // the solver's copy of the system matrix
     int fmt_req = -1; // the layout request it was built for
+    // Arnoldi steps from which the delayed passes keep fewer loads in flight
+    // (INT_MAX: never), timed once per workspace (tune_basis)
+    int upd_narrow = INT_MAX, dot_narrow = INT_MAX, basis_tuned = 0;
 };
 
 template <typename F>
@@ -762,9 +766,28 @@ __global__ __launch_bounds__(KT) void k_dcgs_update_pairs(int64_t n, double *__r
     if (t == 0) part[blockIdx.x] = s;
 }
 constexpr int UPD_PAIRS = 4; // pairs of rows per thread in k_dcgs_update_pairs (2048-row workgroups)
-// Arnoldi steps from which the basis passes keep fewer loads in flight
-// (the crossovers measured on the 192^3 problem's basis)
+// Arnoldi steps from which the basis passes keep fewer loads in flight when
+// that is faster on the basis at hand (tune_basis; the crossovers measured
+// on the 192^3 problem's basis, where each column is 57 MB: on the 128^3
+// one, 17 MB per column and much of the basis in the last-level cache, the
+// wide groups are faster at every step)
 constexpr int UPD_NARROW_FROM = 12, DOT_NARROW_FROM = 8;
+
+// A state for timing the passes at step j: nothing converged, a = c = 0,
+// unit norms (the reorthogonalisation scalars stay finite).
+__global__ void k_probe_state(GState *__restrict__ st, int j)
+{
+    if (threadIdx.x != 0) return;
+    st->j = j;
+    st->done = 0;
+    for (int k = 0; k < MAXM + 2; ++k) {
+        st->hA[k] = 0.0;
+        st->hB[k] = 0.0;
+        st->zs[k] = 1.0;
+    }
+    st->bb = 1.0;
+    st->dd = 0.0;
+}
 
 __global__ __launch_bounds__(KT) void k_dcgs_finish(const double *__restrict__ part, int nb, GState *__restrict__ st)
 {
@@ -947,6 +970,63 @@ static int precondition(int kind, gs2_handle *P, const double *v, double *z, int
 // rule's lanes per row, unless forced): launch overhead would dominate.
 constexpr int64_t SPMV_TUNE_MIN_ROWS = 65536;
 
+// Loads in flight of the two delayed basis passes (all groups of one width:
+// block_multidot's and k_dcgs_update_pairs' G), decided once per workspace
+// by timing both widths of each pass at step min(m - 1, 24) on the zeroed
+// basis (best of three batches of three launches after a warm-up batch; a
+// narrow variant must win by 3 %).  The narrow width then runs from the
+// crossover step.  Small bases (fewer than BASIS_TUNE_MIN_ROWS rows, or a
+// restart below 16) keep the wide groups.  The probe's writes (two columns,
+// the partial sums, the state) are all set again by the solve.
+constexpr int64_t BASIS_TUNE_MIN_ROWS = 1 << 20;
+static int tune_basis(GmresWork *W, hipStream_t s)
+{
+    if (W->basis_tuned) return GS2_OK;
+    W->upd_narrow = W->dot_narrow = INT_MAX;
+    const int64_t n = W->n;
+    if (n < BASIS_TUNE_MIN_ROWS || W->m < 16 || n % 2) {
+        W->basis_tuned = 1;
+        return GS2_OK;
+    }
+    const int jt = std::min(W->m - 1, 24), nb = W->nb;
+    const unsigned nbu = (unsigned)((n + 2 * UPD_PAIRS * KT - 1) / (2 * UPD_PAIRS * KT));
+    GS2_TRY_HIP(hipMemsetAsync(W->V, 0, sizeof(double) * (size_t)n * (jt + 2), s));
+    GS2_TRY_HIP(hipMemsetAsync(W->w, 0, sizeof(double) * (size_t)n, s));
+    k_probe_state<<<1, 64, 0, s>>>(W->st, jt);
+    GS2_TRY_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    GS2_TRY_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    GS2_TRY_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    int st = GS2_OK;
+    auto timed = [&](auto launch) -> float {
+        float best = 1e30f;
+        for (int rep = 0; rep < 4 && st == GS2_OK; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = GS2_ERR_HIP;
+            for (int b = 0; b < 3; ++b) launch();
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = GS2_ERR_HIP;
+            float t = 0.f;
+            if (st == GS2_OK && hipEventElapsedTime(&t, e0, e1) != hipSuccess) st = GS2_ERR_HIP;
+            if (rep > 0) best = std::min(best, t);
+        }
+        return best;
+    };
+    GState *gs = W->st;
+    const float dw = timed([&] { k_dot2<8><<<(unsigned)nb, KT, 0, s>>>(n, W->w, W->V, n, gs, W->part, nb); });
+    const float dn = timed([&] { k_dot2<2><<<(unsigned)nb, KT, 0, s>>>(n, W->w, W->V, n, gs, W->part, nb); });
+    const float uw = timed([&] {
+        k_dcgs_update_pairs<UPD_PAIRS, UPD_PAIRS><<<nbu, KT, 0, s>>>(n, W->V, n, gs, W->w, W->part);
+    });
+    const float un = timed([&] { k_dcgs_update_pairs<UPD_PAIRS, 1><<<nbu, KT, 0, s>>>(n, W->V, n, gs, W->w, W->part); });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    GS2_TRY(st);
+    GS2_TRY_HIP(hipGetLastError());
+    if (dn < 0.97f * dw) W->dot_narrow = DOT_NARROW_FROM;
+    if (un < 0.97f * uw) W->upd_narrow = UPD_NARROW_FROM;
+    W->basis_tuned = 1;
+    return GS2_OK;
+}
+
 // Time of one product w2 = b - A w in the layout sel (best of three batches
 // of five launches after a warm-up batch; timing-only events).
 static int time_product(GmresWork *W, int sel, hipStream_t s, float *ms)
@@ -1075,6 +1155,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     const unsigned gN = (unsigned)nb;
     const unsigned gE = (unsigned)((n + 255) / 256);
     GS2_TRY(prepare_matrix(W, A, P ? P->h.spmv_fmt : GS2_FORMAT_AUTO, s));
+    GS2_TRY(tune_basis(W, s));
     const SellAView AS = view(W->A);
     const DiaAView AD = dview(W->A);
     const int K = W->A.sel;
@@ -1192,7 +1273,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                             }
                         }
                         Prof pr(cs, PK_SPMV_DOT, vb + 8.0 * n);
-                        if (j < DOT_NARROW_FROM) k_dot2<8><<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
+                        if (j < W->dot_narrow) k_dot2<8><<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
                         else k_dot2<2><<<gN, KT, 0, cs>>>(n, W->w, W->V, n, st, W->part, nb);
                     } else {
                         Prof pr(cs, PK_SPMV_DOT, spmv_b + vb);
@@ -1207,7 +1288,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                         Prof pr(cs, PK_CGS, 8.0 * n * (j + 4));
                         if (!pairs)
                             k_dcgs_update<<<gN, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
-                        else if (j < UPD_NARROW_FROM)
+                        else if (j < W->upd_narrow)
                             k_dcgs_update_pairs<UPD_PAIRS, UPD_PAIRS>
                                 <<<(unsigned)nbu, KT, 0, cs>>>(n, W->V, n, st, W->w, W->part);
                         else
