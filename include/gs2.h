@@ -351,6 +351,17 @@ int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, in
 int gs2_gmres_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *ndiag,
                        int *tuned);
 
+/*
+ * Loads in flight of the delayed reorthogonalisation's two passes over the
+ * Krylov basis with this handle (host outputs, any may be NULL; all 0 before
+ * the handle's first solve): dot_narrow_from / update_narrow_from, the
+ * Arnoldi step from which the first / second pass keeps fewer loads in
+ * flight per wavefront (-1: never, the wide groups throughout); tuned = 1 if
+ * timed on this workspace's basis (bases of 2^20 rows and more, restart >=
+ * 16, an even row count), 0 if defaulted to the wide groups.
+ */
+int gs2_gmres_basis_schedule(const gs2_handle *h, int *dot_narrow_from, int *update_narrow_from, int *tuned);
+
 /* --------------------------------------------------------------- batched
  *
  * Many independent systems of uneven sizes, each with nrhs right-hand sides,

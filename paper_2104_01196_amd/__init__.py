@@ -10,5 +10,5 @@ from .native import (  # noqa: F401
     DeviceCSR, Gs2Error, Handle, BatchHandle,
     gs2_setup, gs2_apply, jr_apply, gs_trisolve_apply, gmres_solve, cg_solve, gs2_destroy, gs2_handle_query,
     gs2_setup_batched, gmres_solve_batched, gs2_destroy_batched, gs2_batched_schedule, status_string, lib,
-    gs2_handle_schedule, gs2_gmres_schedule, gs2_inner_residuals, XCD_AUTO, XCD_DISPATCH_ORDER, XCD_RANGES, gs2_inner_residuals_noalloc, ERR_SCRATCH, STAGNATED, NOT_CONVERGED, FORMAT_AUTO, FORMAT_SELL, FORMAT_DIA, FORMAT_BLOCK3, LDS_AUTO, LDS_OFF, LDS_ON,
+    gs2_handle_schedule, gs2_gmres_schedule, gs2_gmres_basis_schedule, gs2_inner_residuals, XCD_AUTO, XCD_DISPATCH_ORDER, XCD_RANGES, gs2_inner_residuals_noalloc, ERR_SCRATCH, STAGNATED, NOT_CONVERGED, FORMAT_AUTO, FORMAT_SELL, FORMAT_DIA, FORMAT_BLOCK3, LDS_AUTO, LDS_OFF, LDS_ON,
 )

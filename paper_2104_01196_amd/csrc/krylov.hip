@@ -1390,6 +1390,17 @@ extern "C" int gs2_gmres_schedule(const gs2_handle *H, int *format, int *lanes_p
     return GS2_OK;
 }
 
+extern "C" int gs2_gmres_basis_schedule(const gs2_handle *H, int *dot_narrow_from, int *update_narrow_from, int *tuned)
+{
+    if (!H) return GS2_ERR_ARG;
+    const GmresWork *W = H->h.gw;
+    const bool done = W && W->basis_tuned;
+    if (dot_narrow_from) *dot_narrow_from = !done ? 0 : W->dot_narrow == INT_MAX ? -1 : W->dot_narrow;
+    if (update_narrow_from) *update_narrow_from = !done ? 0 : W->upd_narrow == INT_MAX ? -1 : W->upd_narrow;
+    if (tuned) *tuned = !done ? 0 : (W->n >= BASIS_TUNE_MIN_ROWS && W->m >= 16 && W->n % 2 == 0) ? 1 : 0;
+    return GS2_OK;
+}
+
 extern "C" int gmres_solve(const gs2_csr *A, const double *b, double *x, int restart, double rtol, int maxit,
                            int prec_kind, gs2_handle *prec, gs2_solve_info *info, void *stream)
 {

@@ -86,6 +86,7 @@ def lib():
         L.gs2_handle_query.argtypes = [vp, i64p, i64p, i64p, i64p, ip, ip, ip]
         L.gs2_handle_schedule.argtypes = [vp, ip, ip, ip, ip, ip, ip, ip, ip, ip]
         L.gs2_gmres_schedule.argtypes = [vp, ip, ip, ip, ip, ip]
+        L.gs2_gmres_basis_schedule.argtypes = [vp, ip, ip, ip]
         L.gs2_inner_residuals.argtypes = [vp, vp, i, C.POINTER(C.c_double), vp]
         L.gs2_inner_residuals_noalloc.argtypes = [vp, vp, i, vp, vp]
         L.gs2_profile.argtypes = [i]
@@ -296,6 +297,15 @@ def gs2_gmres_schedule(h: Handle) -> dict:
     if st != OK:
         raise Gs2Error(st, "gs2_gmres_schedule")
     return {k: x.value for k, x in zip(["format", "lanes_per_row", "rows_per_lane", "ndiag", "tuned"], v)}
+
+
+def gs2_gmres_basis_schedule(h: Handle) -> dict:
+    """Arnoldi steps from which the basis passes keep fewer loads in flight (-1 never; zeros before the first solve)."""
+    v = [C.c_int() for _ in range(3)]
+    st = lib().gs2_gmres_basis_schedule(h.ptr, *[C.byref(x) for x in v])
+    if st != OK:
+        raise Gs2Error(st, "gs2_gmres_basis_schedule")
+    return {k: x.value for k, x in zip(["dot_narrow_from", "update_narrow_from", "tuned"], v)}
 
 
 def gs2_inner_residuals(h: Handle, r, inner: int, stream=None):

@@ -69,10 +69,14 @@ def test_full_size_gmres_matches_oracle(wname):
                         inner_damping=rec.get("gamma", 1.0))
         x.zero_()
         info = g.gmres_solve(dA, db, x, rec["restart"], rec["rtol"], 20000, g.PREC_GS2, h)
+        bs = g.gs2_gmres_basis_schedule(h)
+        # timed on bases of 2^20 rows and more; the narrow widths start at the fixed crossover steps
+        assert bs["tuned"] == (1 if A.n >= 1 << 20 else 0), bs
+        assert bs["dot_narrow_from"] in (-1, 8) and bs["update_narrow_from"] in (-1, 12), bs
         xs = x.cpu().numpy()
         its_or = rec["solves"][form]["iterations"]
         rel = np.linalg.norm(b - S @ xs) / np.linalg.norm(b)
-        msg = f"{wname} {form}: GPU {info['iterations']} its, oracle {its_or}, relres {rel:.3e}"
+        msg = f"{wname} {form}: GPU {info['iterations']} its, oracle {its_or}, relres {rel:.3e}, basis {bs}"
         print(msg)
         assert info["converged"] and rel <= rec["rtol"], msg
         assert abs(info["iterations"] - its_or) <= 1, msg

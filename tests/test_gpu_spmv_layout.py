@@ -51,6 +51,8 @@ def test_gmres_copy_layout_matches_oracle(name, fmt):
     want_dia = fmt == g.FORMAT_DIA and qualifies
     assert sched["format"] == (g.FORMAT_DIA if want_dia else g.FORMAT_SELL), sched
     assert sched["tuned"] == 0
+    # small bases keep the wide load groups, untimed
+    assert g.gs2_gmres_basis_schedule(h) == {"dot_narrow_from": -1, "update_narrow_from": -1, "tuned": 0}
     if want_dia:
         assert sched["rows_per_lane"] == 2 and sched["ndiag"] == len(np.unique(A.colind - np.repeat(
             np.arange(A.n), np.diff(A.rowptr))))
