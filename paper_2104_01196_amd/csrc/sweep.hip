@@ -751,16 +751,18 @@ struct Launch {
         const DiaView dv = dview(T);
         const int n = (int)h.n;
         // three diagonals per triangle (7-point stencils): the loop over them unrolled
-        if (T.ndiag == 3 && !(FL & DIA_FL_B3)) {
-            if (fj.st)
-                k_dia_inner<VT, AT, R, FL, true, 3><<<grid, DIA_THREADS, 0, s>>>(
-                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
-                    h.sr, fj.part, fj.nb, fj.st);
-            else
-                k_dia_inner<VT, AT, R, FL, false, 3><<<grid, DIA_THREADS, 0, s>>>(
-                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
-                    h.sr, nullptr, 0, nullptr);
-            return;
+        if constexpr (!(FL & DIA_FL_B3)) {
+            if (T.ndiag == 3) {
+                if (fj.st)
+                    k_dia_inner<VT, AT, R, FL, true, 3><<<grid, DIA_THREADS, 0, s>>>(
+                        h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout,
+                        xh, z, h.sr, fj.part, fj.nb, fj.st);
+                else
+                    k_dia_inner<VT, AT, R, FL, false, 3><<<grid, DIA_THREADS, 0, s>>>(
+                        h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout,
+                        xh, z, h.sr, nullptr, 0, nullptr);
+                return;
+            }
         }
         if (fj.st)
             k_dia_inner<VT, AT, R, FL, true, 0><<<grid, DIA_THREADS, 0, s>>>(
@@ -811,14 +813,17 @@ struct Launch {
         // ND = 3 kernels always add both triangles (no branch on `two`, so the
         // loads of all six diagonals are issued together); one triangle (the
         // compact form's residual) takes the general kernel
-        if (P.ndiag == 3 && Q && Q->ndiag == 3 && !(FL & DIA_FL_B3))
-            k_dia_resid<VT, AT, R, FL, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
-                                                                       Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
-                                                                       h.sl, svp, cdiag, w, dst, rh, xout, z, h.sr);
-        else
-            k_dia_resid<VT, AT, R, FL, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
-                                                                       Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
-                                                                       h.sl, svp, cdiag, w, dst, rh, xout, z, h.sr);
+        if constexpr (!(FL & DIA_FL_B3)) {
+            if (P.ndiag == 3 && Q && Q->ndiag == 3) {
+                k_dia_resid<VT, AT, R, FL, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P), dview(*Q), 1,
+                                                                           xh, v, h.sl, svp, cdiag, w, dst, rh, xout,
+                                                                           z, h.sr);
+                return;
+            }
+        }
+        k_dia_resid<VT, AT, R, FL, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
+                                                                   Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v, h.sl,
+                                                                   svp, cdiag, w, dst, rh, xout, z, h.sr);
     }
     template <int R>
     static void dia_resid_f(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,
