@@ -64,40 +64,45 @@ struct DiaOffsA {
     int off[DIA_MAX];
 };
 
-// One thread per row: entry (i, i + off[d]) of the row goes to diagonal d at
-// the row's interleaved position (R rows per lane).  Offsets ascend within a
-// row as they do in off, so the diagonal index walks forward.  Entries of
-// rows past n and absent entries keep the zeros written at allocation.
-__global__ void k_diaA_fill(int64_t n, int R, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                            const double *__restrict__ va, DiaOffsA o, int64_t stride, double *__restrict__ val)
+// Values of the diagonal (B3 = false) or 3-row block (B3 = true) copy, LANES
+// threads per row, each taking every LANES-th entry of the row: entry (i, c)
+// goes to diagonal t (the index of c - i among the offsets), or to plane
+// 3 t + (c mod 3) (t the index of the node offset c/3 - i/3), at row i's
+// position (interleaved by R rows per lane for the diagonal copy; rows
+// contiguous in the block copy).  The offsets are found by binary search in
+// an LDS copy.  Entries of rows past n and absent entries keep the zeros
+// written at allocation.  This runs at every solve (the values may have
+// changed in place): one thread per row walking its entries took 2.3 ms per
+// solve on the 64^3 elasticity matrix.
+template <int LANES, bool B3>
+__global__ __launch_bounds__(256) void k_copy_fill(int64_t n, int R, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                   DiaOffsA o, int64_t stride, double *__restrict__ val)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t blk = (int64_t)WAVE * R;
-    const int64_t pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
-    int t = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int d = (int)((int64_t)ci[k] - i);
-        while (t < o.nd - 1 && o.off[t] < d) ++t;
-        if (o.off[t] == d) val[(int64_t)t * stride + pos] = va[k];
+    __shared__ int soff[DIA_MAX];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < DIA_MAX; ++d) soff[d] = o.off[d];
     }
-}
-
-// 3-row block copy: plane 3 t + (c mod 3) at row r for the entry (r, c) whose
-// node offset c/3 - r/3 is o.off[t] (a row's entries are column-sorted, so
-// its node offsets ascend).
-__global__ void k_b3A_fill(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                           const double *__restrict__ va, DiaOffsA o, int64_t stride, double *__restrict__ val)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __syncthreads();
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = g / LANES;
     if (i >= n) return;
-    const int64_t node = i / 3;
-    int t = 0;
-    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int64_t c = ci[k], cn = c / 3;
-        const int d = (int)(cn - node);
-        while (t < o.nd - 1 && o.off[t] < d) ++t;
-        if (o.off[t] == d) val[(int64_t)(3 * t + (int)(c - 3 * cn)) * stride + i] = va[k];
+    int64_t pos = i;
+    if constexpr (!B3) {
+        const int64_t blk = (int64_t)WAVE * R;
+        pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
+    }
+    for (int32_t k = rp[i] + (int32_t)(g % LANES); k < rp[i + 1]; k += LANES) {
+        const int64_t c = ci[k];
+        const int d = B3 ? (int)(c / 3 - i / 3) : (int)(c - i);
+        int lo = 0, hi = o.nd - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (soff[mid] < d) lo = mid + 1;
+            else hi = mid;
+        }
+        if (soff[lo] == d) val[(int64_t)(B3 ? 3 * lo + (int)(c - 3 * (c / 3)) : lo) * stride + pos] = va[k];
     }
 }
 
@@ -199,16 +204,18 @@ int sella_fill_values(SellA &S, const gs2_csr &A, bool with_col, hipStream_t s)
             DiaOffsA o;
             o.nd = S.ndiag;
             for (int d = 0; d < DIA_MAX; ++d) o.off[d] = S.doff[d];
-            k_b3A_fill<<<(unsigned)((A.n + tb - 1) / tb), tb, 0, s>>>(A.n, A.rowptr, A.colind, A.val, o, S.dstride,
-                                                                     S.dval);
+            constexpr int LN = 32; // 81 entries per row for 27-point 3-dof stencils
+            k_copy_fill<LN, true><<<(unsigned)((A.n * LN + tb - 1) / tb), tb, 0, s>>>(A.n, 1, A.rowptr, A.colind,
+                                                                                      A.val, o, S.dstride, S.dval);
         }
     } else if (S.sel < 0) {
         if (A.n > 0) {
             DiaOffsA o;
             o.nd = S.ndiag;
             for (int d = 0; d < DIA_MAX; ++d) o.off[d] = S.doff[d];
-            k_diaA_fill<<<(unsigned)((A.n + tb - 1) / tb), tb, 0, s>>>(A.n, S.dR, A.rowptr, A.colind, A.val, o,
-                                                                      S.dstride, S.dval);
+            constexpr int LN = 8; // 7-point stencils: one entry per lane
+            k_copy_fill<LN, false><<<(unsigned)((A.n * LN + tb - 1) / tb), tb, 0, s>>>(A.n, S.dR, A.rowptr, A.colind,
+                                                                                       A.val, o, S.dstride, S.dval);
         }
     } else if (S.nslices > 0) {
         const int64_t threads = S.nslices * WAVE;

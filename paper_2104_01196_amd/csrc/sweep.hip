@@ -582,9 +582,10 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
 // same value this pass would form from v and s_l).
 
 // S_l v rounded to the working precision, formed once per apply by the 32-
-// and 16-bit forms on the diagonal layout: the first inner pass then gathers
-// one AT value per neighbour instead of two float64 values (v and s_l), and
-// every residual pass reads 2 or 4 bytes per row instead of 16.  FIN: the
+// and 16-bit forms on the diagonal layout (both work in float32): the first
+// inner pass then gathers one float value per neighbour instead of two
+// float64 values (v and s_l), and every residual pass reads 4 bytes per row
+// instead of 16.  FIN: the
 // first workgroup closes the previous GMRES step instead (as in k_dia_inner).
 // Q: rows per thread, consecutive, for 16-byte loads of v and s_l (Q = 4
 // needs n % 4 == 0 and v, s_l, sv aligned to 16 and 4 sizeof(AT) bytes);
