@@ -77,7 +77,7 @@ def lib():
         L.or_inner_residuals.argtypes = csr + [C.c_int, C.c_double, _f64p, _f64p]
         L.or_round_f16.argtypes = [C.c_double]
         L.or_round_f16.restype = C.c_double
-        L.or_gs2_apply_lp.argtypes = csr + [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _f64p, _f64p]
+        L.or_gs2_apply_lp.argtypes = csr + [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _f64p, _f64p]
         L.or_gmres.argtypes = csr + [_f64p, _f64p, C.c_int, C.c_double, C.c_int, C.POINTER(_Prec), C.c_int,
                                      C.POINTER(_Info), C.c_void_p]
         L.or_pcg.argtypes = csr + [_f64p, _f64p, C.c_double, C.c_int, C.POINTER(_Prec), C.POINTER(_Info)]
@@ -196,10 +196,10 @@ def round_f16(x: float) -> float:
     return lib().or_round_f16(float(x))
 
 
-def gs2_apply_lp(A, v, precision=FP32, variant=FORWARD, sweeps=1, inner=1, omega=1.0):
-    """Reduced-precision (FP32 or FP16-scaled) GS2 apply from zero."""
+def gs2_apply_lp(A, v, precision=FP32, variant=FORWARD, sweeps=1, inner=1, omega=1.0, gamma=1.0):
+    """Reduced-precision (FP32 or FP16-scaled) GS2 apply from zero, inner damping gamma."""
     z = np.empty(A.n)
-    _chk(lib().or_gs2_apply_lp(*_csr(A), precision, variant, sweeps, inner, omega, _vec(v), z))
+    _chk(lib().or_gs2_apply_lp(*_csr(A), precision, variant, sweeps, inner, omega, gamma, _vec(v), z))
     return z
 
 

@@ -341,6 +341,9 @@ int or_inner_residuals(int n, const int32_t *rp, const int32_t *ci, const double
  * round to nearest even).  Then, all in binary32 arithmetic:
  *   rh = round32(v_i * s_l[i]) - xh_i - sum_{j != i} Ah_ij xh_j   (CSR order)
  *   g0 = rh;  g_{j+1} = rh - w * sum_{T} Ah_ij g_j
+ *   (with inner damping gamma != 1, Section 9: g_{j+1} = (1 - gamma) g_j +
+ *    gamma (rh - w * sum_{T} Ah_ij g_j), the float64 form's update in
+ *    scaled variables, where D^{-1} is the identity)
  *   xh = xh + w g
  * and the output is z_i = (double) xh_i * s_r[i] in float64.  The first
  * residual of an apply from zero is round32(v_i s_l[i]) exactly.
@@ -370,7 +373,7 @@ typedef struct {
     int32_t *rp, *ci; /* off-diagonal pattern only */
     float *va;
     double *sl, *sr;
-    float w;
+    float w, gamma;
 } or_scaled;
 
 static void scaled_free(or_scaled *S)
@@ -379,12 +382,13 @@ static void scaled_free(or_scaled *S)
     memset(S, 0, sizeof(*S));
 }
 
-static int scaled_build(const or_csr *A, int precision, double w, or_scaled *S)
+static int scaled_build(const or_csr *A, int precision, double w, double gamma, or_scaled *S)
 {
     const int n = A->n;
     memset(S, 0, sizeof(*S));
     S->n = n;
     S->w = (float)w;
+    S->gamma = (float)gamma;
     int64_t nnz = A->rp[n];
     S->rp = malloc(sizeof(int32_t) * (size_t)(n + 1));
     S->ci = malloc(sizeof(int32_t) * (size_t)(nnz + 1));
@@ -423,7 +427,7 @@ static void scaled_half(const or_scaled *S, int lower, int inner, int from_zero,
                         float *r, float *g, float *gn)
 {
     const int n = S->n;
-    const float w = S->w;
+    const float w = S->w, gamma = S->gamma;
     for (int i = 0; i < n; ++i) {
         float base = (float)(v[i] * S->sl[i]);
         if (from_zero) { r[i] = base; continue; }
@@ -439,7 +443,8 @@ static void scaled_half(const or_scaled *S, int lower, int inner, int from_zero,
                 int c = S->ci[k];
                 if (lower ? (c < i) : (c > i)) s = s + S->va[k] * g[c];
             }
-            gn[i] = r[i] - w * s;
+            const float jac = r[i] - w * s;
+            gn[i] = (gamma == 1.0f) ? jac : (1.0f - gamma) * g[i] + gamma * jac;
         }
         float *t = g; g = gn; gn = t;
     }
@@ -461,14 +466,15 @@ static int scaled_apply(const or_scaled *S, int variant, int sweeps, int inner, 
     return OR_OK;
 }
 
-/* Reduced-precision GS2 apply (FP32 or FP16-scaled form), zero initial guess. */
+/* Reduced-precision GS2 apply (FP32 or FP16-scaled form, inner damping
+ * gamma), zero initial guess. */
 int or_gs2_apply_lp(int n, const int32_t *rp, const int32_t *ci, const double *va, int precision, int variant,
-                    int sweeps, int inner, double w, const double *v, double *z)
+                    int sweeps, int inner, double w, double gamma, const double *v, double *z)
 {
     if (precision != OR_FP32 && precision != OR_FP16S) return OR_ERR_ARG;
     or_csr A = {n, rp, ci, va};
     or_scaled S;
-    int st = scaled_build(&A, precision, w, &S);
+    int st = scaled_build(&A, precision, w, gamma, &S);
     if (st != OR_OK) return st;
     float *work = malloc(sizeof(float) * (size_t)n * 4 + 16);
     if (!work) { scaled_free(&S); return OR_ERR_NOMEM; }
@@ -567,7 +573,9 @@ int or_gmres(int n, const int32_t *rp, const int32_t *ci, const double *va, cons
     C.P = P;
     C.A = &A;
     if ((P->kind == OR_PREC_GS2 || P->kind == OR_PREC_JR) && P->precision != OR_FP64) {
-        int st = scaled_build(&A, P->precision, P->omega, &C.S);
+        /* the reduced-precision forms are defined for the non-compact, single-block sweep only */
+        if (P->compact || P->blocks > 1) return info->status = OR_ERR_ARG;
+        int st = scaled_build(&A, P->precision, P->omega, P->gamma, &C.S);
         if (st != OR_OK) return info->status = st;
         C.have_scaled = 1;
         C.work = malloc(sizeof(float) * (size_t)n * 4 + 16);
@@ -848,7 +856,9 @@ int or_pcg(int n, const int32_t *rp, const int32_t *ci, const double *va, const 
     C.P = P;
     C.A = &A;
     if ((P->kind == OR_PREC_GS2 || P->kind == OR_PREC_JR) && P->precision != OR_FP64) {
-        int st = scaled_build(&A, P->precision, P->omega, &C.S);
+        /* the reduced-precision forms are defined for the non-compact, single-block sweep only */
+        if (P->compact || P->blocks > 1) return info->status = OR_ERR_ARG;
+        int st = scaled_build(&A, P->precision, P->omega, P->gamma, &C.S);
         if (st != OR_OK) return info->status = st;
         C.have_scaled = 1;
         C.work = malloc(sizeof(float) * (size_t)n * 4 + 16);

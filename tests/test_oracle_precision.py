@@ -61,6 +61,32 @@ def test_reduced_forms_exact_on_dyadic_data(prec, variant, sweeps, inner):
     assert np.array_equal(z64, zlp)
 
 
+@pytest.mark.parametrize("prec", [oracle.FP32, oracle.FP16S])
+@pytest.mark.parametrize("variant,sweeps,inner,w,gamma", [(F, 1, 2, 1.0, 0.5), (S, 1, 2, 0.5, 0.5),
+                                                          (F, 2, 2, 0.5, 0.5), (B, 1, 3, 1.0, 0.75),
+                                                          (F, 1, 3, 0.5, 0.25)])
+def test_reduced_forms_inner_damping_exact_on_dyadic_data(prec, variant, sweeps, inner, w, gamma):
+    """Inner damping (Section 9) in the reduced forms: with dyadic damping
+    factors and few enough sweeps every value stays a dyadic rational short
+    enough for binary32, so the reduced form with gamma must equal the
+    float64 textbook form with the same gamma bit for bit; a gamma dropped,
+    applied to the wrong term or to the wrong iterate changes the result."""
+    A, v = dyadic_problem(6)
+    z64 = oracle.gs2_apply(A, v, variant, sweeps, inner, w, gamma)
+    zlp = oracle.gs2_apply_lp(A, v, prec, variant, sweeps, inner, w, gamma)
+    assert np.array_equal(z64, zlp)
+    assert not np.array_equal(z64, oracle.gs2_apply(A, v, variant, sweeps, inner, w, 1.0))
+
+
+def test_reduced_forms_refuse_compact_and_blocks():
+    """The reduced-precision forms are defined for the non-compact sweep over
+    the whole matrix: the oracle's GMRES refuses the others in them."""
+    A, v = dyadic_problem(6)
+    for kw in (dict(compact=True), dict(blocks=2)):
+        _, info = oracle.gmres(A, v, restart=10, rtol=1e-8, prec="gs2", precision=oracle.FP32, **kw)
+        assert info["status"] == -1 and info["iterations"] == 0, (kw, info)  # argument error
+
+
 @pytest.mark.parametrize("mk", [lambda: random_sparse(200, seed=7, avg_offdiag=6, neg_diag_rows=10),
                                 lambda: vardiff3d(6, seed=3), lambda: laplace3d(6)])
 @pytest.mark.parametrize("variant,sweeps,inner", [(F, 2, 1), (S, 1, 2)])
