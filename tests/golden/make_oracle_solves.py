@@ -43,9 +43,8 @@ WORKLOADS = {
     # 128^3 Laplacian, forward GS2(2 sweeps, 1 inner), GMRES(50)
     "laplace3d_128": dict(config=2, size=128, variant=0, sweeps=2, inner=1, restart=50),
     # Q1 elasticity on 64^3 free nodes, SGS2(1 sweep, 3 inner) with damping 0.7 and inner damping 0.5,
-    # GMRES(50); float64 preconditioner only (the reduced-precision forms have no inner damping)
-    "elasticity_64": dict(config=3, size=64, variant=2, sweeps=1, inner=3, omega=0.7, gamma=0.5, restart=50,
-                          precisions=(0,)),
+    # GMRES(50), in the three preconditioner forms
+    "elasticity_64": dict(config=3, size=64, variant=2, sweeps=1, inner=3, omega=0.7, gamma=0.5, restart=50),
 }
 RTOL = 1e-8
 MAXIT = 20000

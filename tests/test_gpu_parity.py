@@ -109,6 +109,12 @@ def test_gs2_inner_damping(name, gamma):
     z = torch.empty(A.n, dtype=torch.float64, device=DEV)
     g.gs2_apply(h, dev(v), z)
     assert rel_inf(host(z), ref) <= 4e-12
+    # the reduced-precision forms with the same damping, against the oracle's (same bars as the undamped forms)
+    for prec, tol in ((g.FP32, 2e-5), (g.FP16_SCALED, 1e-4)):
+        h = g.gs2_setup(dA, 2, 3, 0.9, g.SYMMETRIC, precision=prec, inner_damping=gamma, format=g.FORMAT_SELL)
+        g.gs2_apply(h, dev(v), z)
+        ref = oracle.gs2_apply_lp(A, v, prec, g.SYMMETRIC, 2, 3, 0.9, gamma)
+        assert rel_inf(host(z), ref) <= tol, (prec, rel_inf(host(z), ref))
 
 
 @pytest.mark.parametrize("name", ["rand_negdiag", "poisson2d_64", "elasticity_5"])
