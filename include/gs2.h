@@ -136,6 +136,14 @@ typedef struct gs2_options {
                           /* per lane) or _BLOCK3 (2 rows per lane), each    */
                           /* falling back to sliced ELL if A does not        */
                           /* qualify                                         */
+    int basis_loads;      /* gmres_solve with this handle: loads in flight   */
+                          /* of the delayed passes over the Krylov basis:    */
+                          /* 0 = timed once per workspace (bases of 2^20     */
+                          /* rows and more, else wide), 1 = wide groups at   */
+                          /* every step, 2 = narrow groups from the          */
+                          /* crossover steps (even row counts; wide where    */
+                          /* the row count is odd).  Results are the same    */
+                          /* bit for bit: only the loads' grouping differs.  */
 } gs2_options;
 
 /* gs2_options.format */

@@ -229,6 +229,7 @@ struct Handle {
     int orth = 0;        // GMRES orthogonalisation (0 delayed CGS2, 1 CGS2)
     int stag_cycles = 0; // GMRES stagnation window in restart cycles (0 default, < 0 off)
     int spmv_fmt = 0;    // GMRES: layout request for the solver's copy of A (GS2_FORMAT_*)
+    int basis_req = 0;   // GMRES: basis passes' loads in flight (0 timed, 1 wide, 2 narrow)
     int block_waves = 4; // wavefronts per workgroup in the sweep kernels
     Sell L, U;
     // diagonal-interleaved copies of L and U, used by the GS2 / JR passes

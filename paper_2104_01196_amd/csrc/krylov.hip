@@ -64,7 +64,8 @@ struct GmresWork {
     SellA A;         // the solver's copy of the system matrix
     int fmt_req = -1; // the layout request it was built for
     // Arnoldi steps from which the delayed passes keep fewer loads in flight
-    // (INT_MAX: never), timed once per workspace (tune_basis)
+    // (INT_MAX: never), timed once per workspace (tune_basis); basis_tuned 1
+    // decided there, 2 forced by the handle's request
     int upd_narrow = INT_MAX, dot_narrow = INT_MAX, basis_tuned = 0;
 };
 
@@ -979,13 +980,17 @@ constexpr int64_t SPMV_TUNE_MIN_ROWS = 65536;
 // restart below 16) keep the wide groups.  The probe's writes (two columns,
 // the partial sums, the state) are all set again by the solve.
 constexpr int64_t BASIS_TUNE_MIN_ROWS = 1 << 20;
-static int tune_basis(GmresWork *W, hipStream_t s)
+static int tune_basis(GmresWork *W, int req, hipStream_t s)
 {
     if (W->basis_tuned) return GS2_OK;
     W->upd_narrow = W->dot_narrow = INT_MAX;
     const int64_t n = W->n;
-    if (n < BASIS_TUNE_MIN_ROWS || W->m < 16 || n % 2) {
-        W->basis_tuned = 1;
+    if (req == 2 && n % 2 == 0) { // forced narrow (from the crossover steps)
+        W->upd_narrow = UPD_NARROW_FROM;
+        W->dot_narrow = DOT_NARROW_FROM;
+    }
+    if (req != 0 || n < BASIS_TUNE_MIN_ROWS || W->m < 16 || n % 2) {
+        W->basis_tuned = req != 0 ? 2 : 1;
         return GS2_OK;
     }
     const int jt = std::min(W->m - 1, 24), nb = W->nb;
@@ -1155,7 +1160,7 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
     const unsigned gN = (unsigned)nb;
     const unsigned gE = (unsigned)((n + 255) / 256);
     GS2_TRY(prepare_matrix(W, A, P ? P->h.spmv_fmt : GS2_FORMAT_AUTO, s));
-    GS2_TRY(tune_basis(W, s));
+    GS2_TRY(tune_basis(W, P ? P->h.basis_req : 0, s));
     const SellAView AS = view(W->A);
     const DiaAView AD = dview(W->A);
     const int K = W->A.sel;
@@ -1397,7 +1402,7 @@ extern "C" int gs2_gmres_basis_schedule(const gs2_handle *H, int *dot_narrow_fro
     const bool done = W && W->basis_tuned;
     if (dot_narrow_from) *dot_narrow_from = !done ? 0 : W->dot_narrow == INT_MAX ? -1 : W->dot_narrow;
     if (update_narrow_from) *update_narrow_from = !done ? 0 : W->upd_narrow == INT_MAX ? -1 : W->upd_narrow;
-    if (tuned) *tuned = !done ? 0 : (W->n >= BASIS_TUNE_MIN_ROWS && W->m >= 16 && W->n % 2 == 0) ? 1 : 0;
+    if (tuned) *tuned = !done || W->basis_tuned == 2 ? 0 : (W->n >= BASIS_TUNE_MIN_ROWS && W->m >= 16 && W->n % 2 == 0) ? 1 : 0;
     return GS2_OK;
 }
 

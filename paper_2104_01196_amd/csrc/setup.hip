@@ -1015,6 +1015,7 @@ void gs2_default_options(gs2_options *opt)
     opt->lds_staging = 0;
     opt->stagnation_cycles = 0;
     opt->spmv_format = GS2_FORMAT_AUTO;
+    opt->basis_loads = 0;
     opt->xcd_ranges = 0;
 }
 
@@ -1039,7 +1040,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     if (!(o.inner_damping > 0.0 && o.inner_damping <= 2.0)) return GS2_ERR_ARG;
     if (o.format < GS2_FORMAT_AUTO || o.format > GS2_FORMAT_BLOCK3 || o.rows_per_lane < 0 || o.lds_staging < 0 ||
         o.lds_staging > 2 || o.spmv_format < GS2_FORMAT_AUTO || o.spmv_format > GS2_FORMAT_BLOCK3 || o.xcd_ranges < 0 ||
-        o.xcd_ranges > 2)
+        o.xcd_ranges > 2 || o.basis_loads < 0 || o.basis_loads > 2)
         return GS2_ERR_ARG;
     gs2_handle *H = new (std::nothrow) gs2_handle;
     if (!H) return GS2_ERR_NOMEM;
@@ -1054,6 +1055,7 @@ int gs2_setup(const gs2_csr *A, int sweeps, int inner, double damping, int varia
     h.orth = o.orthogonalization;
     h.stag_cycles = o.stagnation_cycles;
     h.spmv_fmt = o.spmv_format;
+    h.basis_req = o.basis_loads;
     h.blocks = std::max(1, o.blocks);
     h.local_sweeps = std::max(1, o.local_sweeps);
     h.precision = o.precision;

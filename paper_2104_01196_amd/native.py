@@ -46,7 +46,8 @@ class Options(C.Structure):
                 ("rhs_per_item", C.c_int), ("orthogonalization", C.c_int), ("blocks", C.c_int),
                 ("local_sweeps", C.c_int), ("team_rows", C.c_int), ("team_wait_ms", C.c_int),
                 ("format", C.c_int), ("rows_per_lane", C.c_int), ("lds_staging", C.c_int),
-                ("xcd_ranges", C.c_int), ("stagnation_cycles", C.c_int), ("spmv_format", C.c_int)]
+                ("xcd_ranges", C.c_int), ("stagnation_cycles", C.c_int), ("spmv_format", C.c_int),
+                ("basis_loads", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -184,12 +185,12 @@ class Handle:
 def gs2_setup(A: DeviceCSR, sweeps=1, inner=1, damping=1.0, variant=FORWARD, precision=FP64, inner_damping=1.0,
               compact=False, build_levels=False, autotune=True, lanes_per_row=0, orthogonalization=0, blocks=1,
               local_sweeps=1, format=FORMAT_AUTO, rows_per_lane=0, lds_staging=0, stagnation_cycles=0,
-              spmv_format=FORMAT_AUTO, xcd_ranges=0, stream=None) -> Handle:
+              spmv_format=FORMAT_AUTO, xcd_ranges=0, basis_loads=0, stream=None) -> Handle:
     opt = Options(precision=precision, inner_damping=inner_damping, compact=int(compact),
                   build_levels=int(build_levels), autotune=int(autotune), lanes_per_row=lanes_per_row,
                   orthogonalization=orthogonalization, blocks=blocks, local_sweeps=local_sweeps, format=format,
                   rows_per_lane=rows_per_lane, lds_staging=lds_staging, xcd_ranges=xcd_ranges,
-                  stagnation_cycles=stagnation_cycles, spmv_format=spmv_format)
+                  stagnation_cycles=stagnation_cycles, spmv_format=spmv_format, basis_loads=basis_loads)
     out = C.c_void_p()
     d = A.desc()
     st = lib().gs2_setup(C.byref(d), sweeps, inner, damping, variant, C.byref(opt), _stream(stream), C.byref(out))

@@ -24,7 +24,7 @@ def test_status_strings_and_defaults():
     o = native.Options()
     native.lib().gs2_default_options(C.byref(o))
     assert (o.precision, o.inner_damping, o.compact, o.build_levels, o.autotune, o.lanes_per_row,
-            o.rhs_per_item) == (0, 1.0, 0, 0, 1, 0, 0)
+            o.rhs_per_item, o.spmv_format, o.basis_loads) == (0, 1.0, 0, 0, 1, 0, 0, 0, 0)
 
 
 def test_argument_errors_without_device():
@@ -36,6 +36,11 @@ def test_argument_errors_without_device():
         assert L.gs2_setup(C.byref(d), *args, None, None, C.byref(out)) == native.ERR_ARG
     bad = native.Options(7, 1.0, 0, 0, 1, 0)
     assert L.gs2_setup(C.byref(d), 1, 1, 1.0, 0, C.byref(bad), None, C.byref(out)) == native.ERR_ARG
+    for field, val in (("basis_loads", 3), ("spmv_format", 4), ("format", 4)):
+        o = native.Options()
+        L.gs2_default_options(C.byref(o))
+        setattr(o, field, val)
+        assert L.gs2_setup(C.byref(d), 1, 1, 1.0, 0, C.byref(o), None, C.byref(out)) == native.ERR_ARG, field
     info = native.SolveInfo()
     assert L.gmres_solve(C.byref(d), 8, 8, 0, 1e-8, 10, 0, None, C.byref(info), None) == native.ERR_ARG
     assert info.status == native.ERR_ARG

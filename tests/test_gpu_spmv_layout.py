@@ -84,6 +84,40 @@ def test_diagonal_copy_follows_values_changed_in_place():
     assert np.linalg.norm(2.0 * xs - x1) / np.linalg.norm(x1) <= 1e-6
 
 
+@pytest.mark.parametrize("name", ["vardiff3d_23", "laplace3d_20"])
+def test_basis_load_groups_bitwise_equal(name):
+    """The basis passes' narrow and wide load groups (forced through
+    basis_loads) change only how the loads are issued, not the order of any
+    sum: GMRES(40) gives bit-identical iterates and iteration counts, and
+    matches the oracle.  12,167 rows (odd: the paired second pass does not
+    apply, wide throughout) and 8,000 rows (even: narrow from steps 8 and
+    12), both with a partial last workgroup in both passes."""
+    A = MATS[name][0]() if name != "vardiff3d_24" else vardiff3d(24, seed=4)
+    dA = g.DeviceCSR.from_host(A)
+    b = make_rhs(A, "normal", seed=24)[1]
+    xs = []
+    for mode in (1, 2):
+        h = g.gs2_setup(dA, 1, 1, 1.0, g.SYMMETRIC, basis_loads=mode)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        info = g.gmres_solve(dA, torch.as_tensor(b, device="cuda"), x, 40, 1e-8, 5000, g.PREC_GS2, h)
+        bs = g.gs2_gmres_basis_schedule(h)
+        narrow = mode == 2 and A.n % 2 == 0
+        assert bs == {"dot_narrow_from": 8 if narrow else -1, "update_narrow_from": 12 if narrow else -1,
+                      "tuned": 0}, bs
+        xs.append((x.cpu().numpy(), info["iterations"]))
+    assert xs[0][1] == xs[1][1] and np.array_equal(xs[0][0], xs[1][0])
+    xo, io = oracle.gmres(A, b, restart=40, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=1)
+    assert abs(xs[0][1] - io["iterations"]) <= 1
+    assert np.linalg.norm(xs[0][0] - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_basis_load_groups_even_ragged():
+    """The same on an even row count with partial last workgroups (24^3 =
+    13,824 rows: 6.75 workgroups of the second pass, 13.5 of the first),
+    where the narrow groups run from steps 8 and 12."""
+    test_basis_load_groups_bitwise_equal("vardiff3d_24")
+
+
 @pytest.mark.slow
 def test_timed_layout_choice_matches_oracle():
     """Automatic choice on a matrix large enough to be timed: the schedule
