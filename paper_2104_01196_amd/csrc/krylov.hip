@@ -544,10 +544,12 @@ __global__ __launch_bounds__(KT) void k_dia_spmv(DiaAView A, int64_t n, const do
     }
 }
 
-// w = zs[j] (A z) from the 3-row block copy (b3_rows' scheme, written
-// straight from registers): a lane owns NB rows 64 apart.  The copy is
-// padded to whole 1024-row workgroups, so every load is in bounds; rows past
-// n are not written.
+// w = zs[j] (A z) from the 3-row block copy (node-major planes), a lane
+// owning NB nodes 64 apart: per node offset it gathers the neighbour node's
+// three z entries once and loads the nine values of the block (nine
+// coalesced loads), forming its three rows' sums in the order b3_rows uses.
+// The planes are padded to whole 1024-node groups, so every load is in
+// bounds; nodes past n/3 are not written.
 template <int NB>
 __global__ __launch_bounds__(KT) void k_b3_spmv(DiaAView A, int64_t n, const double *__restrict__ z,
                                                 double *__restrict__ w, const GState *__restrict__ st)
@@ -555,35 +557,42 @@ __global__ __launch_bounds__(KT) void k_b3_spmv(DiaAView A, int64_t n, const dou
     if (st && st->done) return;
     const double zsc = st ? st->zs[st->j] : 1.0;
     const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
-    const int64_t w0 = ((int64_t)blockIdx.x * (KT / WAVE) + wv) * (WAVE * NB), nn = n / 3;
-    double acc[NB];
+    const int64_t nn = n / 3, g0 = ((int64_t)blockIdx.x * (KT / WAVE) + wv) * (WAVE * NB);
+    double acc[NB][3];
     int64_t nd[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const int64_t row = w0 + b * WAVE + ln;
-        acc[b] = 0.0;
-        nd[b] = (row < n ? row : n - 1) / 3;
+        const int64_t i = g0 + b * WAVE + ln;
+        acc[b][0] = acc[b][1] = acc[b][2] = 0.0;
+        nd[b] = i < nn ? i : nn - 1;
     }
-    const int64_t f0 = w0 / 3, f1 = ((w0 + WAVE * NB < n ? w0 + WAVE * NB : n) - 1) / 3;
+    const int64_t f1 = (g0 + WAVE * NB < nn ? g0 + WAVE * NB : nn) - 1; // the wavefront's last node
     for (int d = 0; d < A.ndiag; ++d) {
         const int64_t o = A.off[d];
-        const bool inside = f0 + o >= 0 && f1 + o < nn;
-        const double *__restrict__ p0 = A.val + (int64_t)(3 * d) * A.stride;
+        const bool inside = g0 + o >= 0 && f1 + o < nn;
+        const double *__restrict__ p0 = A.val + (int64_t)(9 * d) * A.stride;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int64_t row = w0 + b * WAVE + ln;
+            const int64_t i = g0 + b * WAVE + ln;
             int64_t c = nd[b] + o;
             c = inside ? c : (c < 0 ? 0 : (c >= nn ? nn - 1 : c));
             c *= 3;
-            acc[b] += __builtin_nontemporal_load(p0 + row) * z[c];
-            acc[b] += __builtin_nontemporal_load(p0 + A.stride + row) * z[c + 1];
-            acc[b] += __builtin_nontemporal_load(p0 + 2 * A.stride + row) * z[c + 2];
+            const double z0 = z[c], z1 = z[c + 1], z2 = z[c + 2];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double *__restrict__ pv = p0 + (int64_t)(3 * k) * A.stride + i;
+                acc[b][k] += __builtin_nontemporal_load(pv) * z0;
+                acc[b][k] += __builtin_nontemporal_load(pv + A.stride) * z1;
+                acc[b][k] += __builtin_nontemporal_load(pv + 2 * A.stride) * z2;
+            }
         }
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-        const int64_t row = w0 + b * WAVE + ln;
-        if (row < n) __builtin_nontemporal_store(zsc * acc[b], &w[row]);
+        const int64_t i = g0 + b * WAVE + ln;
+        if (i < nn)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) __builtin_nontemporal_store(zsc * acc[b][k], &w[3 * i + k]);
     }
 }
 
@@ -1032,8 +1041,9 @@ static int tune_basis(GmresWork *W, int req, hipStream_t s)
     return GS2_OK;
 }
 
-// Time of one product w2 = b - A w in the layout sel (best of three batches
-// of five launches after a warm-up batch; timing-only events).
+// Time of one product in the layout sel (best of three batches of five
+// launches after a warm-up batch; timing-only events): w2 = b - A w, or for
+// the block copy the kernel the solver's steps use, w2 = A w.
 static int time_product(GmresWork *W, int sel, hipStream_t s, float *ms)
 {
     const int64_t n = W->n;
@@ -1047,8 +1057,16 @@ static int time_product(GmresWork *W, int sel, hipStream_t s, float *ms)
     float best = 1e30f;
     for (int rep = 0; rep < 4; ++rep) {
         GS2_TRY_HIP(hipEventRecord(e0, s));
-        for (int b = 0; b < 5; ++b)
-            GS2_SPMV_DISPATCH(sel, k_true_resid, (unsigned)nb, AS, AD, n, W->w, W->w, W->w2, W->part, nb);
+        for (int b = 0; b < 5; ++b) {
+            if (sel <= -10) {
+                const int R = -sel - 10;
+                const unsigned gD = (unsigned)((n / 3 + (int64_t)KT * R - 1) / ((int64_t)KT * R));
+                if (R == 2) k_b3_spmv<2><<<gD, KT, 0, s>>>(AD, n, W->w, W->w2, nullptr);
+                else k_b3_spmv<1><<<gD, KT, 0, s>>>(AD, n, W->w, W->w2, nullptr);
+            } else {
+                GS2_SPMV_DISPATCH(sel, k_true_resid, (unsigned)nb, AS, AD, n, W->w, W->w, W->w2, W->part, nb);
+            }
+        }
         GS2_TRY_HIP(hipEventRecord(e1, s));
         GS2_TRY_HIP(hipEventSynchronize(e1));
         float t = 0.f;
@@ -1265,7 +1283,8 @@ static int gmres_impl(const gs2_csr &A, const double *b, double *x, int m, doubl
                         {
                             Prof pr(cs, PK_SPMV, spmv_b);
                             const int R = K <= -10 ? -K - 10 : -K;
-                            const unsigned gD = (unsigned)((n + (int64_t)KT * R - 1) / ((int64_t)KT * R));
+                            const int64_t units = K <= -10 ? n / 3 : n; // nodes or rows
+                            const unsigned gD = (unsigned)((units + (int64_t)KT * R - 1) / ((int64_t)KT * R));
                             if (K <= -10) {
                                 if (K == -12) k_b3_spmv<2><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);
                                 else k_b3_spmv<1><<<gD, KT, 0, cs>>>(AD, n, zj, W->w, st);

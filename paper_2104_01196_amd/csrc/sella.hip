@@ -66,10 +66,10 @@ struct DiaOffsA {
 
 // Values of the diagonal (B3 = false) or 3-row block (B3 = true) copy, LANES
 // threads per row, each taking every LANES-th entry of the row: entry (i, c)
-// goes to diagonal t (the index of c - i among the offsets), or to plane
-// 3 t + (c mod 3) (t the index of the node offset c/3 - i/3), at row i's
-// position (interleaved by R rows per lane for the diagonal copy; rows
-// contiguous in the block copy).  The offsets are found by binary search in
+// goes to diagonal t (the index of c - i among the offsets) at row i's
+// position (interleaved by R rows per lane), or to plane
+// 9 t + 3 (i mod 3) + (c mod 3) (t the index of the node offset c/3 - i/3)
+// at node i/3's position.  The offsets are found by binary search in
 // an LDS copy.  Entries of rows past n and absent entries keep the zeros
 // written at allocation.  This runs at every solve (the values may have
 // changed in place): one thread per row walking its entries took 2.3 ms per
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_copy_fill(int64_t n, int R, const int32
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = g / LANES;
     if (i >= n) return;
-    int64_t pos = i;
+    int64_t pos = i / 3;
     if constexpr (!B3) {
         const int64_t blk = (int64_t)WAVE * R;
         pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
@@ -102,7 +102,8 @@ __global__ __launch_bounds__(256) void k_copy_fill(int64_t n, int R, const int32
             if (soff[mid] < d) lo = mid + 1;
             else hi = mid;
         }
-        if (soff[lo] == d) val[(int64_t)(B3 ? 3 * lo + (int)(c - 3 * (c / 3)) : lo) * stride + pos] = va[k];
+        if (soff[lo] == d)
+            val[(int64_t)(B3 ? 9 * lo + 3 * (int)(i - 3 * (i / 3)) + (int)(c - 3 * (c / 3)) : lo) * stride + pos] = va[k];
     }
 }
 
@@ -186,9 +187,9 @@ int sella_build_b3(SellA &S, const gs2_csr &A, int R, const std::vector<int> &of
     S.nnz = A.nnz;
     S.dR = R;
     S.ndiag = (int)offs.size();
-    S.dstride = std::max<int64_t>(1, (A.n + KRB - 1) / KRB) * KRB;
+    S.dstride = std::max<int64_t>(1, (A.n / 3 + KRB - 1) / KRB) * KRB; // nodes
     for (int d = 0; d < DIA_MAX; ++d) S.doff[d] = d < S.ndiag ? offs[d] : 0;
-    const size_t bytes = sizeof(double) * 3 * (size_t)std::max(S.ndiag, 1) * (size_t)S.dstride;
+    const size_t bytes = sizeof(double) * 9 * (size_t)std::max(S.ndiag, 1) * (size_t)S.dstride;
     GS2_TRY_HIP(hipMalloc(&S.dval, bytes));
     GS2_TRY_HIP(hipMemsetAsync(S.dval, 0, bytes, s));
     S.sel = -10 - R;

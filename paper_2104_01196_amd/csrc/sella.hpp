@@ -46,14 +46,16 @@ struct SellA {
     // Block-diagonal alternative for matrices of 3-row blocks (3 unknowns
     // per grid node, node-major, e.g. elasticity) with at most DIA_MAX
     // distinct node offsets c/3 - r/3: the same arrays (ndiag node offsets
-    // in doff, dval, dstride), where plane 3 d + b holds a_{r, 3(r/3 +
-    // off[d]) + b} for every row r (0 where absent), rows contiguous.  A
-    // row's three values of one block sit in three planes at the same
-    // position, and its x operands are the three consecutive entries of one
-    // node.  No column indices.
+    // in doff, dval, dstride), indexed by node, where plane 9 d + 3 k + b
+    // holds a_{3i + k, 3(i + off[d]) + b} for every node i (0 where absent),
+    // nodes contiguous and padded to whole KRB-node groups (dstride).  The
+    // nine values of one node's block sit in nine planes at the same
+    // position, so a lane that owns a node loads them with nine coalesced
+    // loads and gathers the neighbour node's three x entries once for its
+    // three rows.  No column indices.
     // the product's layout: sel > 0 sliced ELL with K = sel lanes per row,
     // -9 <= sel < 0 the diagonal copy with R = -sel rows per lane, sel <= -10
-    // the 3-row block copy with -sel - 10 rows per lane
+    // the 3-row block copy with -sel - 10 nodes per lane
     int sel = 1;
     int tuned = 0; // 1 if sel was chosen by timing the candidates
 };
@@ -222,10 +224,11 @@ __device__ __forceinline__ void dia_rows(const DiaAView A, int64_t n, int64_t r0
 
 // ybuf[i] = (A z)[r0 + i] from the 3-row block copy (layout in SellA): a
 // lane owns rows 64 apart, and per block it loads its row's three values
-// (three coalesced loads from three planes) and the three z entries of the
-// neighbour node.  Node indices are clamped into [0, n/3) only where the
-// wavefront's nodes shifted by the offset leave it (a clamped node meets
-// stored zeros).  Ends with a barrier.
+// (from the three planes of its row within the node) and the three z
+// entries of the neighbour node, in the order the node-per-lane product
+// uses, so the two give the same sums.  Node indices are clamped into
+// [0, n/3) only where the wavefront's nodes shifted by the offset leave it
+// (a clamped node meets stored zeros).  Ends with a barrier.
 template <int NW>
 __device__ __forceinline__ void b3_rows(const DiaAView A, int64_t n, int64_t r0, const double *__restrict__ z,
                                         double *ybuf)
@@ -235,27 +238,28 @@ __device__ __forceinline__ void b3_rows(const DiaAView A, int64_t n, int64_t r0,
     const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
     const int64_t w0 = r0 + (int64_t)wv * RW, nn = n / 3;
     double acc[NBLK];
-    int64_t nd[NBLK];
+    int64_t nd[NBLK], pk[NBLK];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b) {
-        const int64_t row = w0 + b * WAVE + ln;
+        const int64_t row = w0 + b * WAVE + ln, rc = row < n ? row : n - 1;
         acc[b] = 0.0;
-        nd[b] = (row < n ? row : n - 1) / 3;
+        nd[b] = rc / 3;
+        pk[b] = 3 * (rc - 3 * nd[b]) * A.stride + nd[b]; // row's first plane within a block, at its node
     }
     const int64_t f0 = w0 / 3, f1 = ((w0 + RW < n ? w0 + RW : n) - 1) / 3; // the wavefront's nodes
     for (int d = 0; d < A.ndiag; ++d) {
         const int64_t o = A.off[d];
         const bool inside = f0 + o >= 0 && f1 + o < nn;
-        const double *__restrict__ p0 = A.val + (int64_t)(3 * d) * A.stride;
+        const double *__restrict__ p0 = A.val + (int64_t)(9 * d) * A.stride;
 #pragma unroll
         for (int b = 0; b < NBLK; ++b) {
-            const int64_t row = w0 + b * WAVE + ln;
             int64_t c = nd[b] + o;
             if (!inside) c = c < 0 ? 0 : (c >= nn ? nn - 1 : c);
             c *= 3;
-            acc[b] += __builtin_nontemporal_load(p0 + row) * z[c];
-            acc[b] += __builtin_nontemporal_load(p0 + A.stride + row) * z[c + 1];
-            acc[b] += __builtin_nontemporal_load(p0 + 2 * A.stride + row) * z[c + 2];
+            const double *__restrict__ pv = p0 + pk[b];
+            acc[b] += __builtin_nontemporal_load(pv) * z[c];
+            acc[b] += __builtin_nontemporal_load(pv + A.stride) * z[c + 1];
+            acc[b] += __builtin_nontemporal_load(pv + 2 * A.stride) * z[c + 2];
         }
     }
 #pragma unroll
