@@ -201,18 +201,18 @@ constexpr int DIA_HALO = 64;  // LDS staging covers offsets |off| <= DIA_HALO
 constexpr int DIA_THREADS = 256; // threads per workgroup of the passes on it
 struct Dia {
     int ndiag = 0;
-    int R = 1;          // rows per lane
-    int64_t stride = 0; // entries per diagonal (rows padded to 64 R)
+    int R = 1;          // rows (3-row blocks: nodes) per lane
+    int64_t stride = 0; // entries per diagonal (rows or nodes padded to whole workgroups)
     int64_t nnz = 0;    // real entries
     int off[DIA_MAX] = {};
     void *val = nullptr;
     int val_bytes = 8;
     int nt = 0; // stream the values with the non-temporal policy
     // 3-row blocks (3 unknowns per node, node-major): off[] holds node
-    // offsets c/3 - r/3, and plane 3 d + b (b < 3) holds a_{r, 3(r/3 +
-    // off[d]) + b} at row r's interleaved position
+    // offsets c/3 - r/3, and plane 9 d + 3 j + b (j, b < 3) holds
+    // a_{3i + j, 3(i + off[d]) + b} at node i's interleaved position
     int b3 = 0;
-    double stored_bytes() const { return (double)ndiag * (b3 ? 3.0 : 1.0) * (double)stride * val_bytes; }
+    double stored_bytes() const { return (double)ndiag * (b3 ? 9.0 : 1.0) * (double)stride * val_bytes; }
 };
 
 // The schedule the setup picked for the sweep kernels.

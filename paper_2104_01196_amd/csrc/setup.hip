@@ -387,8 +387,9 @@ __global__ void k_dia_fill(int64_t n, int R, const int32_t *__restrict__ rp, con
 }
 
 // The 3-row block layout: entry (i, c) of the part goes to plane
-// 3 t + (c mod 3), t the index of its node offset c/3 - i/3, at row i's
-// interleaved position; scaled and rounded as in k_dia_fill.
+// 9 t + 3 (i mod 3) + (c mod 3), t the index of its node offset c/3 - i/3,
+// at node i/3's interleaved position (R nodes per lane); scaled and rounded
+// as in k_dia_fill.
 template <typename VT>
 __global__ void k_b3_fill(int64_t n, int R, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                           const double *__restrict__ va, const int32_t *__restrict__ lcnt, int lower, DiaOffs o,
@@ -397,11 +398,10 @@ __global__ void k_b3_fill(int64_t n, int R, const int32_t *__restrict__ rp, cons
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t blk = (int64_t)WAVE * R;
-    const int64_t pos = (i / blk) * blk + (i % WAVE) * R + (i % blk) / WAVE;
+    const int64_t blk = (int64_t)WAVE * R, node = i / 3, j = i - 3 * node;
+    const int64_t pos = (node / blk) * blk + (node % WAVE) * R + (node % blk) / WAVE;
     const int64_t b = lower ? rp[i] : rp[i] + lcnt[i] + 1, e = lower ? rp[i] + lcnt[i] : rp[i + 1];
     const double srow = sl[i];
-    const int64_t node = i / 3;
     int t = 0, ovf = 0;
     for (int64_t k = b; k < e; ++k) {
         const int c = ci[k];
@@ -412,14 +412,15 @@ __global__ void k_b3_fill(int64_t n, int R, const int32_t *__restrict__ rp, cons
             atomicOr(err, ERRF_BAD_CSR); // cannot happen for a pattern the offsets came from
             return;
         }
-        val[(int64_t)(3 * t + (c - 3 * cn)) * stride + pos] = convert_scaled<VT>((srow * va[k]) * sr[c], &ovf);
+        val[(int64_t)(9 * t + 3 * j + (c - 3 * cn)) * stride + pos] = convert_scaled<VT>((srow * va[k]) * sr[c], &ovf);
     }
     if (ovf) atomicOr(err, ERRF_FP16);
 }
 
 // Build one triangle (lower or upper) in the diagonal-interleaved layout
-// with R rows per lane; rows are padded to whole workgroups of the sweep
-// kernels (DIA_THREADS * R rows) so that every launched lane has a slot.
+// with R rows per lane, or in the 3-row block layout with R nodes per lane;
+// rows (nodes) are padded to whole workgroups of the sweep kernels
+// (DIA_THREADS * R of them) so that every launched lane has a slot.
 static int build_dia(Dia &D, int64_t n, int precision, int lower, int R, const std::vector<int> &offs, int64_t nnz,
                      const gs2_csr &A, const int32_t *lcnt, const double *sl, const double *sr, int *err,
                      hipStream_t s, int b3 = 0)
@@ -430,15 +431,15 @@ static int build_dia(Dia &D, int64_t n, int precision, int lower, int R, const s
     D.nnz = nnz;
     D.b3 = b3;
     D.val_bytes = precision == GS2_FP64 ? 8 : precision == GS2_FP32 ? 4 : 2;
-    const int64_t wg = (int64_t)DIA_THREADS * R;
-    D.stride = std::max<int64_t>(1, (n + wg - 1) / wg) * wg;
+    const int64_t wg = (int64_t)DIA_THREADS * R, units = b3 ? n / 3 : n;
+    D.stride = std::max<int64_t>(1, (units + wg - 1) / wg) * wg;
     DiaOffs o;
     o.nd = D.ndiag;
     for (int d = 0; d < DIA_MAX; ++d) {
         D.off[d] = d < D.ndiag ? offs[d] : 0;
         o.off[d] = D.off[d];
     }
-    const size_t bytes = (size_t)std::max(1, D.ndiag) * (b3 ? 3 : 1) * (size_t)D.stride * D.val_bytes;
+    const size_t bytes = (size_t)std::max(1, D.ndiag) * (b3 ? 9 : 1) * (size_t)D.stride * D.val_bytes;
     GS2_TRY_HIP(hipMalloc(&D.val, bytes));
     GS2_TRY_HIP(hipMemsetAsync(D.val, 0, bytes, s));
     if (D.ndiag == 0 || n == 0) return GS2_OK;

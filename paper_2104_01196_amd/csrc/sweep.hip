@@ -456,42 +456,52 @@ __device__ __forceinline__ void dia_dots(const DiaView &T, int64_t pos, int w0, 
     }
 }
 
-// The same sums on a 3-row block triangle: per node offset o, the three
-// planes' values of the lane's R rows (one load each) and the source at the
-// three unknowns 3(node + o) .. 3(node + o) + 2 of the neighbour node, node =
-// row / 3.  Node indices are clamped into [0, n/3) only in workgroups whose
-// nodes, shifted by o, leave that range (a uniform test per offset; a
-// clamped node meets stored zeros).  Rows past n read in-bounds padding.
+// The sums on a 3-row block triangle, one node per lane slot:
+// acc[k][j] += sum over the node offsets o of the block row j of node
+// nb + 64 k against the source at the neighbour node's three unknowns
+// 3(node + o) .. 3(node + o) + 2.  Per offset a lane gathers those three
+// source entries once for its node's three rows and loads the block's nine
+// planes (R consecutive nodes' values per load; pos is the lane's first
+// value of plane 0).  Each row's sum runs over o, then the three columns of
+// the block, in order.  Node indices are clamped into [0, n/3) only in
+// workgroups whose nodes, shifted by o, leave that range (a uniform test per
+// offset; a clamped node meets stored zeros).  Nodes past n/3 read in-bounds
+// padding.
 template <typename VT, typename AT, int R, bool NT, typename Src>
-__device__ __forceinline__ void b3_dots(const DiaView &T, int64_t pos, int w0, int rb, int n, Src src, AT (&acc)[R])
+__device__ __forceinline__ void b3_node_dots(const DiaView &T, int64_t pos, int g0, int nb, int nn, Src src,
+                                             AT (&acc)[R][3])
 {
-    constexpr int RB = DIA_THREADS * R;
+    constexpr int NBW = DIA_THREADS * R; // nodes per workgroup
     const VT *__restrict__ val = (const VT *)T.val;
-    const int nn = n / 3;
-    const int f0 = w0 / 3, f1 = ((w0 + RB < n ? w0 + RB : n) - 1) / 3;
+    const int f1 = (g0 + NBW < nn ? g0 + NBW : nn) - 1;
     int node[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        const int row = rb + k * WAVE;
-        node[k] = (row < n ? row : n - 1) / 3;
-    }
-#pragma unroll 2
+    for (int k = 0; k < R; ++k) node[k] = nb + k * WAVE < nn ? nb + k * WAVE : nn - 1;
+    // one offset per iteration: the nine value loads and three gathers of an
+    // offset already fill the wavefront's loads in flight, and unrolling by
+    // two took the float64 inner pass from 50 to 78 registers at one node per
+    // lane
+#pragma unroll 1
     for (int d = 0; d < T.ndiag; ++d) {
         const int o = T.off[d];
-        const bool inside = f0 + o >= 0 && f1 + o < nn;
-        int c0[R];
+        const bool inside = g0 + o >= 0 && f1 + o < nn;
+        AT zs[R][3];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int c = node[k] + o;
-            c0[k] = 3 * (inside ? c : (c < 0 ? 0 : (c >= nn ? nn - 1 : c)));
+            int c = node[k] + o;
+            c = 3 * (inside ? c : (c < 0 ? 0 : (c >= nn ? nn - 1 : c)));
+#pragma unroll
+            for (int b = 0; b < 3; ++b) zs[k][b] = src(c + b);
         }
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            AT a[R];
-            dia_vals<VT, AT, R, NT>(val + (int64_t)(3 * d + b) * T.stride + pos, a);
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < R; ++k) acc[k] += a[k] * src(c0[k] + b);
-        }
+            for (int b = 0; b < 3; ++b) {
+                AT a[R];
+                dia_vals<VT, AT, R, NT>(val + (int64_t)(9 * d + 3 * j + b) * T.stride + pos, a);
+#pragma unroll
+                for (int k = 0; k < R; ++k) acc[k][j] += a[k] * zs[k][b];
+            }
     }
 }
 
@@ -521,8 +531,8 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
                                                   const double *__restrict__ sr, const double *__restrict__ fpart,
                                                   int fnb, void *fst)
 {
-    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT, B3 = FL & DIA_FL_B3;
-    static_assert(!(LDS && B3), "3-row block passes are not staged in LDS");
+    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT;
+    static_assert(!(FL & DIA_FL_B3), "3-row block triangles take k_b3_inner");
     constexpr int RB = DIA_THREADS * R; // rows per workgroup
     constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
     if constexpr (FIN) {
@@ -553,10 +563,6 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_inner(const int *__restrict
             if (dia_stage<AT, SPAN>(xs, base, n, sg, stop, &sflag)) return;
             dia_dots<VT, AT, R, true, NT, ND>(T, pos, w0, rb, n, sg, xs, base, acc);
         }
-    } else if constexpr (B3) {
-        if (stop && *stop) return;
-        if (gv) b3_dots<VT, AT, R, NT>(T, pos, w0, rb, n, sv, acc);
-        else b3_dots<VT, AT, R, NT>(T, pos, w0, rb, n, sg, acc);
     } else {
         if (stop && *stop) return;
         if (gv) dia_dots<VT, AT, R, false, NT, ND>(T, pos, w0, rb, n, sv, nullptr, 0, acc);
@@ -627,8 +633,8 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
                                                   AT *__restrict__ rh, AT *__restrict__ xout, double *__restrict__ z,
                                                   const double *__restrict__ sr)
 {
-    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT, B3 = FL & DIA_FL_B3;
-    static_assert(!(LDS && B3), "3-row block passes are not staged in LDS");
+    constexpr bool LDS = FL & DIA_FL_LDS, NT = FL & DIA_FL_NT;
+    static_assert(!(FL & DIA_FL_B3), "3-row block triangles take k_b3_resid");
     constexpr int RB = DIA_THREADS * R;
     constexpr int SPAN = LDS ? RB + 2 * DIA_HALO : 1;
     const int wg = remap ? (int)xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -650,12 +656,6 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
         if (ND > 0 || two) dia_dots<VT, AT, R, true, NT, ND>(Q, pos, w0, rb, n, sx, xs, base, acc);
 #pragma unroll
         for (int k = 0; k < R; ++k) own[k] = xs[rb + k * WAVE - base];
-    } else if constexpr (B3) {
-        if (stop && *stop) return;
-        b3_dots<VT, AT, R, NT>(P, pos, w0, rb, n, sx, acc);
-        if (two) b3_dots<VT, AT, R, NT>(Q, pos, w0, rb, n, sx, acc);
-#pragma unroll
-        for (int k = 0; k < R; ++k) own[k] = xh[clamp_col(rb + k * WAVE, n)];
     } else {
         if (stop && *stop) return;
         dia_dots<VT, AT, R, false, NT, ND>(P, pos, w0, rb, n, sx, nullptr, 0, acc);
@@ -670,6 +670,93 @@ __global__ __launch_bounds__(DIA_THREADS) void k_dia_resid(const int *__restrict
         const AT s0 = svp ? svp[row] : (AT)(v[row] * sl[row]);
         const AT r = (s0 - cdiag * own[k]) - acc[k];
         finish<AT>(dst, row, r, w, rh, const_cast<AT *>(xh), xout, z, sr);
+    }
+}
+
+// Inner JR pass on a 3-row block triangle (as k_dia_inner), a lane owning
+// the R nodes nb + 64 k and their three rows each.  FIN as in k_dia_inner.
+template <typename VT, typename AT, int R, bool NT, bool FIN>
+__global__ __launch_bounds__(DIA_THREADS) void k_b3_inner(const int *__restrict__ stop, int remap, int n, DiaView T,
+                                                          const AT *__restrict__ rh, const AT *__restrict__ gin,
+                                                          const double *__restrict__ v, const double *__restrict__ sl,
+                                                          int rv, int gv, int damp, AT w, AT gamma, int dst,
+                                                          AT *__restrict__ gout, AT *__restrict__ xh,
+                                                          double *__restrict__ z, const double *__restrict__ sr,
+                                                          const double *__restrict__ fpart, int fnb, void *fst)
+{
+    constexpr int NBW = DIA_THREADS * R; // nodes per workgroup
+    if constexpr (FIN) {
+        if (blockIdx.x == 0) {
+            dcgs_finish_block(fpart, fnb, static_cast<GState *>(fst));
+            return;
+        }
+    }
+    const int sh = FIN ? 1 : 0;
+    const int wg = remap ? (int)xcd_remap(blockIdx.x - sh, gridDim.x - sh) : (int)(blockIdx.x - sh);
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int nn = n / 3, g0 = wg * NBW;
+    const int nb = g0 + wv * (WAVE * R) + lane;
+    const int64_t pos = (int64_t)g0 + wv * (WAVE * R) + lane * R;
+    if (stop && *stop) return;
+    auto sv = [&](int c) { return (AT)(v[c] * sl[c]); };
+    auto sg = [&](int c) { return gin[c]; };
+    AT acc[R][3];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k][0] = acc[k][1] = acc[k][2] = AT(0);
+    if (gv) b3_node_dots<VT, AT, R, NT>(T, pos, g0, nb, nn, sv, acc);
+    else b3_node_dots<VT, AT, R, NT>(T, pos, g0, nb, nn, sg, acc);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int node = nb + k * WAVE;
+        if (node >= nn) break;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int row = 3 * node + j;
+            const AT r = rv ? (AT)(v[row] * sl[row]) : rh[row];
+            AT g = r - w * acc[k][j];
+            if (damp) {
+                const AT go = gv ? (AT)(v[row] * sl[row]) : gin[row];
+                g = (AT(1) - gamma) * go + gamma * g;
+            }
+            finish<AT>(dst, row, g, w, gout, xh, xh, z, sr);
+        }
+    }
+}
+
+// Outer residual pass on 3-row block triangles (as k_dia_resid), a lane
+// owning the R nodes nb + 64 k and their three rows each.
+template <typename VT, typename AT, int R, bool NT>
+__global__ __launch_bounds__(DIA_THREADS) void k_b3_resid(const int *__restrict__ stop, int remap, int n, DiaView P,
+                                                          DiaView Q, int two, const AT *__restrict__ xh,
+                                                          const double *__restrict__ v, const double *__restrict__ sl,
+                                                          const AT *__restrict__ svp, AT cdiag, AT w, int dst,
+                                                          AT *__restrict__ rh, AT *__restrict__ xout,
+                                                          double *__restrict__ z, const double *__restrict__ sr)
+{
+    constexpr int NBW = DIA_THREADS * R;
+    const int wg = remap ? (int)xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const int nn = n / 3, g0 = wg * NBW;
+    const int nb = g0 + wv * (WAVE * R) + lane;
+    const int64_t pos = (int64_t)g0 + wv * (WAVE * R) + lane * R;
+    if (stop && *stop) return;
+    auto sx = [&](int c) { return xh[c]; };
+    AT acc[R][3];
+#pragma unroll
+    for (int k = 0; k < R; ++k) acc[k][0] = acc[k][1] = acc[k][2] = AT(0);
+    b3_node_dots<VT, AT, R, NT>(P, pos, g0, nb, nn, sx, acc);
+    if (two) b3_node_dots<VT, AT, R, NT>(Q, pos, g0, nb, nn, sx, acc);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int node = nb + k * WAVE;
+        if (node >= nn) break;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int row = 3 * node + j;
+            const AT s0 = svp ? svp[row] : (AT)(v[row] * sl[row]);
+            const AT r = (s0 - cdiag * xh[row]) - acc[k][j];
+            finish<AT>(dst, row, r, w, rh, const_cast<AT *>(xh), xout, z, sr);
+        }
     }
 }
 
@@ -748,11 +835,22 @@ struct Launch {
                             int gv, int dst, AT *gout, AT *xh, double *z, hipStream_t s, const Handle::FinJob &fj)
     {
         const int damp = h.gamma != 1.0;
-        const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R)) + (fj.st ? 1u : 0u);
+        const int64_t units = (FL & DIA_FL_B3) ? h.n / 3 : h.n; // nodes or rows
+        const unsigned grid = (unsigned)((units + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R)) + (fj.st ? 1u : 0u);
         const DiaView dv = dview(T);
         const int n = (int)h.n;
-        // three diagonals per triangle (7-point stencils): the loop over them unrolled
-        if constexpr (!(FL & DIA_FL_B3)) {
+        if constexpr ((FL & DIA_FL_B3) != 0) {
+            constexpr bool NT = FL & DIA_FL_NT;
+            if (fj.st)
+                k_b3_inner<VT, AT, R, NT, true><<<grid, DIA_THREADS, 0, s>>>(
+                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
+                    z, h.sr, fj.part, fj.nb, fj.st);
+            else
+                k_b3_inner<VT, AT, R, NT, false><<<grid, DIA_THREADS, 0, s>>>(
+                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
+                    z, h.sr, nullptr, 0, nullptr);
+        } else {
+            // three diagonals per triangle (7-point stencils): the loop over them unrolled
             if (T.ndiag == 3) {
                 if (fj.st)
                     k_dia_inner<VT, AT, R, FL, true, 3><<<grid, DIA_THREADS, 0, s>>>(
@@ -764,15 +862,15 @@ struct Launch {
                         xh, z, h.sr, nullptr, 0, nullptr);
                 return;
             }
+            if (fj.st)
+                k_dia_inner<VT, AT, R, FL, true, 0><<<grid, DIA_THREADS, 0, s>>>(
+                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
+                    z, h.sr, fj.part, fj.nb, fj.st);
+            else
+                k_dia_inner<VT, AT, R, FL, false, 0><<<grid, DIA_THREADS, 0, s>>>(
+                    h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh,
+                    z, h.sr, nullptr, 0, nullptr);
         }
-        if (fj.st)
-            k_dia_inner<VT, AT, R, FL, true, 0><<<grid, DIA_THREADS, 0, s>>>(
-                h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
-                h.sr, fj.part, fj.nb, fj.st);
-        else
-            k_dia_inner<VT, AT, R, FL, false, 0><<<grid, DIA_THREADS, 0, s>>>(
-                h.stop, h.remap, n, dv, rh, gin, v, h.sl, rv, gv, damp, (AT)h.omega, (AT)h.gamma, dst, gout, xh, z,
-                h.sr, nullptr, 0, nullptr);
     }
     template <int R>
     static void dia_inner_f(const Handle &h, const Dia &T, const AT *rh, const AT *gin, const double *v, int rv,
@@ -809,22 +907,27 @@ struct Launch {
     static void dia_resid_r(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,
                             AT w, int dst, AT *rh, AT *xout, double *z, hipStream_t s)
     {
-        const unsigned grid = (unsigned)((h.n + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R));
+        const int64_t units = (FL & DIA_FL_B3) ? h.n / 3 : h.n; // nodes or rows
+        const unsigned grid = (unsigned)((units + (int64_t)DIA_THREADS * R - 1) / ((int64_t)DIA_THREADS * R));
         const int n = (int)h.n;
-        // ND = 3 kernels always add both triangles (no branch on `two`, so the
-        // loads of all six diagonals are issued together); one triangle (the
-        // compact form's residual) takes the general kernel
-        if constexpr (!(FL & DIA_FL_B3)) {
+        if constexpr ((FL & DIA_FL_B3) != 0) {
+            k_b3_resid<VT, AT, R, (FL & DIA_FL_NT) != 0><<<grid, DIA_THREADS, 0, s>>>(
+                h.stop, h.remap, n, dview(P), Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v, h.sl, svp, cdiag, w, dst, rh,
+                xout, z, h.sr);
+        } else {
+            // ND = 3 kernels always add both triangles (no branch on `two`, so the
+            // loads of all six diagonals are issued together); one triangle (the
+            // compact form's residual) takes the general kernel
             if (P.ndiag == 3 && Q && Q->ndiag == 3) {
                 k_dia_resid<VT, AT, R, FL, 3><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P), dview(*Q), 1,
                                                                            xh, v, h.sl, svp, cdiag, w, dst, rh, xout,
                                                                            z, h.sr);
                 return;
             }
+            k_dia_resid<VT, AT, R, FL, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
+                                                                       Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v,
+                                                                       h.sl, svp, cdiag, w, dst, rh, xout, z, h.sr);
         }
-        k_dia_resid<VT, AT, R, FL, 0><<<grid, DIA_THREADS, 0, s>>>(h.stop, h.remap, n, dview(P),
-                                                                   Q ? dview(*Q) : dview(P), Q ? 1 : 0, xh, v, h.sl,
-                                                                   svp, cdiag, w, dst, rh, xout, z, h.sr);
     }
     template <int R>
     static void dia_resid_f(const Handle &h, const Dia &P, const Dia *Q, const AT *xh, const double *v, const AT *svp, AT cdiag,
