@@ -222,50 +222,42 @@ __device__ __forceinline__ void dia_rows(const DiaAView A, int64_t n, int64_t r0
     __syncthreads();
 }
 
-// ybuf[i] = (A z)[r0 + i] from the 3-row block copy (layout in SellA): a
-// lane owns rows 64 apart, and per block it loads its row's three values
-// (from the three planes of its row within the node) and the three z
-// entries of the neighbour node, in the order the node-per-lane product
-// uses, so the two give the same sums.  Node indices are clamped into
-// [0, n/3) only where the wavefront's nodes shifted by the offset leave it
-// (a clamped node meets stored zeros).  Ends with a barrier.
+// ybuf[i] = (A z)[r0 + i] from the 3-row block copy (layout in SellA): the
+// workgroup's threads take the nodes whose rows meet [r0, r0 + KRB), one
+// node each in turn (the boundary nodes shared with the neighbouring
+// workgroups are formed by both), and per node offset gather the neighbour
+// node's three z entries once and load the block's nine values, in the
+// order k_b3_spmv uses, so the two give the same sums.  Neighbour nodes are
+// clamped into [0, n/3) (a clamped node meets stored zeros).  Rows past n
+// get 0.  Ends with a barrier.
 template <int NW>
 __device__ __forceinline__ void b3_rows(const DiaAView A, int64_t n, int64_t r0, const double *__restrict__ z,
                                         double *ybuf)
 {
-    constexpr int RW = KRB / NW;   // rows per wavefront
-    constexpr int NBLK = RW / WAVE; // rows per lane
-    const int wv = threadIdx.x / WAVE, ln = threadIdx.x & (WAVE - 1);
-    const int64_t w0 = r0 + (int64_t)wv * RW, nn = n / 3;
-    double acc[NBLK];
-    int64_t nd[NBLK], pk[NBLK];
+    constexpr int NT = NW * WAVE; // threads of the workgroup
+    const int64_t nn = n / 3, a0 = r0 / 3, a1 = (r0 + KRB - 1) / 3 < nn ? (r0 + KRB - 1) / 3 : nn - 1;
+    for (int i = threadIdx.x; i < KRB; i += NT)
+        if (r0 + i >= n) ybuf[i] = 0.0;
+    for (int64_t i = a0 + threadIdx.x; i <= a1; i += NT) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int d = 0; d < A.ndiag; ++d) {
+            int64_t c = i + A.off[d];
+            c = 3 * (c < 0 ? 0 : (c >= nn ? nn - 1 : c));
+            const double z0 = z[c], z1 = z[c + 1], z2 = z[c + 2];
+            const double *__restrict__ p0 = A.val + (int64_t)(9 * d) * A.stride + i;
 #pragma unroll
-    for (int b = 0; b < NBLK; ++b) {
-        const int64_t row = w0 + b * WAVE + ln, rc = row < n ? row : n - 1;
-        acc[b] = 0.0;
-        nd[b] = rc / 3;
-        pk[b] = 3 * (rc - 3 * nd[b]) * A.stride + nd[b]; // row's first plane within a block, at its node
-    }
-    const int64_t f0 = w0 / 3, f1 = ((w0 + RW < n ? w0 + RW : n) - 1) / 3; // the wavefront's nodes
-    for (int d = 0; d < A.ndiag; ++d) {
-        const int64_t o = A.off[d];
-        const bool inside = f0 + o >= 0 && f1 + o < nn;
-        const double *__restrict__ p0 = A.val + (int64_t)(9 * d) * A.stride;
-#pragma unroll
-        for (int b = 0; b < NBLK; ++b) {
-            int64_t c = nd[b] + o;
-            if (!inside) c = c < 0 ? 0 : (c >= nn ? nn - 1 : c);
-            c *= 3;
-            const double *__restrict__ pv = p0 + pk[b];
-            acc[b] += __builtin_nontemporal_load(pv) * z[c];
-            acc[b] += __builtin_nontemporal_load(pv + A.stride) * z[c + 1];
-            acc[b] += __builtin_nontemporal_load(pv + 2 * A.stride) * z[c + 2];
+            for (int k = 0; k < 3; ++k) {
+                const double *__restrict__ pv = p0 + (int64_t)(3 * k) * A.stride;
+                acc[k] += __builtin_nontemporal_load(pv) * z0;
+                acc[k] += __builtin_nontemporal_load(pv + A.stride) * z1;
+                acc[k] += __builtin_nontemporal_load(pv + 2 * A.stride) * z2;
+            }
         }
-    }
 #pragma unroll
-    for (int b = 0; b < NBLK; ++b) {
-        const int64_t row = w0 + b * WAVE + ln;
-        ybuf[row - r0] = row < n ? acc[b] : 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const int64_t row = 3 * i + k;
+            if (row >= r0 && row < r0 + KRB) ybuf[row - r0] = acc[k];
+        }
     }
     __syncthreads();
 }

@@ -705,6 +705,11 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
     for (int R = 1; R <= 8; R *= 2)
         if (R * vb >= 2 && R * vb <= 16 && (o.rows_per_lane == 0 || o.rows_per_lane == R)) Rs.push_back(R);
     if (Rs.empty()) return GS2_ERR_ARG; // a forced rows-per-lane whose load is not 2..16 bytes
+    // the block passes try the widest load first: a narrower one must then win
+    // by the margin below (the float64 elasticity passes at two nodes per lane
+    // ran 10 % faster in the solve than at one, while the timed pair of passes
+    // often put the two within the margin)
+    if (b3) std::reverse(Rs.begin(), Rs.end());
     if (b3) ldss = {0}; // block passes read their source directly
     else if (o.lds_staging == 0) ldss = {0, 1};
     else ldss = {o.lds_staging == 2 ? 1 : 0};
