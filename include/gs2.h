@@ -112,8 +112,9 @@ typedef struct gs2_options {
                           /* GS2_FORMAT_AUTO (0, timed at setup), _SELL (1), */
                           /* _DIA (2) or _BLOCK3 (3; these two GS2_ERR_ARG   */
                           /* if the matrix does not qualify, see gs2_setup)  */
-    int rows_per_lane;    /* diagonal layout: rows per lane R (vector width  */
-                          /* R x value bytes, 2..16): 0 = timed, else forced */
+    int rows_per_lane;    /* diagonal layout: rows per lane R (block layout: */
+                          /* nodes of 3 rows per lane; vector width R x      */
+                          /* value bytes, 2..16): 0 = timed, else forced     */
     int lds_staging;      /* diagonal layout: stage the source vector in LDS */
                           /* for offsets |col - row| <= 64: 0 = timed,       */
                           /* 1 = off, 2 = on                                 */
@@ -131,9 +132,10 @@ typedef struct gs2_options {
                           /* sliced ELL at two lane counts, diagonal copy at */
                           /* 1 and 2 rows per lane when A qualifies --, else */
                           /* or, for n = 3 x nodes with <= 32 node offsets  */
-                          /* c/3 - r/3, the 3-row block copy at 1 and 2 rows */
-                          /* per lane; else sliced ELL), _SELL, _DIA (2 rows */
-                          /* per lane) or _BLOCK3 (2 rows per lane), each    */
+                          /* c/3 - r/3, the 3-row block copy at 1 and 2      */
+                          /* nodes per lane; else sliced ELL), _SELL, _DIA   */
+                          /* (2 rows per lane) or _BLOCK3 (2 nodes per       */
+                          /* lane), each                                     */
                           /* falling back to sliced ELL if A does not        */
                           /* qualify                                         */
     int basis_loads;      /* gmres_solve with this handle: loads in flight   */
@@ -330,8 +332,8 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * The schedule the setup chose for the GS2 / JR passes (host outputs, any
  * may be NULL): format GS2_FORMAT_SELL, GS2_FORMAT_DIA or
  * GS2_FORMAT_BLOCK3; lanes_per_row of the sliced-ELL layout; rows_per_lane
- * and vector_bytes (rows_per_lane x value bytes, the width of one value
- * load), lds_staging (0/1) and xcd_ranges (1 if each XCD walks its own range
+ * (block layout: nodes of 3 rows per lane) and vector_bytes (rows_per_lane
+ * x value bytes, the width of one value load), lds_staging (0/1) and xcd_ranges (1 if each XCD walks its own range
  * of rows, 0 for dispatch order) of the diagonal or block layout (0 when it
  * is not used); ndiag_l / ndiag_u, the diagonals (block layout: node
  * offsets) of L and U (0 if the matrix qualifies for neither);
@@ -343,7 +345,9 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * staging) at every rows_per_lane whose load is 2 to 16 bytes, with and
  * without LDS staging, with and without per-XCD ranges; each is timed on
  * one inner pass over L plus one residual pass over L and U (Section 4
- * passes), the fastest kept.
+ * passes), and a later candidate must be 3 % faster to replace an earlier
+ * one (the block layout's widest load is timed first, the diagonal
+ * layout's narrowest).
  */
 int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,
                         int *lds_staging, int *xcd_ranges, int *ndiag_l, int *ndiag_u, int *tuned);
@@ -352,7 +356,8 @@ int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, in
  * The layout gmres_solve used for its copy of A with this handle (host
  * outputs, any may be NULL; all 0 before the handle's first solve): format
  * GS2_FORMAT_SELL, GS2_FORMAT_DIA or GS2_FORMAT_BLOCK3, lanes_per_row
- * (sliced ELL) or rows_per_lane (diagonal or block copy), ndiag (diagonals,
+ * (sliced ELL) or rows_per_lane (diagonal copy; nodes of 3 rows per lane
+ * for the block copy), ndiag (diagonals,
  * or node offsets of the block copy; 0 for sliced ELL), tuned = 1 if chosen
  * by timing the candidates.
  */
