@@ -168,6 +168,34 @@ def test_block3_copy_matches_oracle(name, fmt):
     assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-6
 
 
+@pytest.mark.parametrize("name", list(ELA))
+def test_block3_copy_without_delay_matches_oracle(name):
+    """The block copy inside the fused product-and-dots kernels (the
+    orthogonalisation without delayed reorthogonalisation forms w = A z one
+    1024-row workgroup at a time, one node per thread over the nodes that
+    meet its rows, the boundary nodes formed by both neighbours): iterations
+    within one of the oracle's GMRES(30), solution within 1e-6, and the same
+    iterations as the sliced-ELL copy on the same path."""
+    A = ELA[name]()
+    dA = g.DeviceCSR.from_host(A)
+    b = make_rhs(A, "normal", seed=23)[1]
+    its = {}
+    for fmt in (g.FORMAT_SELL, g.FORMAT_BLOCK3):
+        h = g.gs2_setup(dA, 1, 3, 0.7, g.SYMMETRIC, inner_damping=0.5, spmv_format=fmt, orthogonalization=1)
+        x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        info = g.gmres_solve(dA, torch.as_tensor(b, device="cuda"), x, 30, 1e-8, 5000, g.PREC_GS2, h)
+        assert g.gs2_gmres_schedule(h)["format"] == fmt
+        its[fmt] = info["iterations"]
+        xs = x.cpu().numpy()
+        rel = np.linalg.norm(b - A.to_scipy() @ xs) / np.linalg.norm(b)
+        assert info["converged"] and rel <= 1e-8
+    xo, io = oracle.gmres(A, b, restart=30, rtol=1e-8, prec="gs2", variant=oracle.SYMMETRIC, sweeps=1, inner=3,
+                          omega=0.7, gamma=0.5)
+    print(f"{name} without delay: GPU {its}, oracle {io['iterations']}")
+    assert abs(its[g.FORMAT_BLOCK3] - io["iterations"]) <= 1 and abs(its[g.FORMAT_SELL] - its[g.FORMAT_BLOCK3]) <= 1
+    assert np.linalg.norm(xs - xo) / np.linalg.norm(xo) <= 1e-6
+
+
 def test_block3_refused_where_it_does_not_apply():
     """Forced block copy on matrices that do not qualify falls back to sliced
     ELL: a row count not divisible by 3, and scattered columns with far more
