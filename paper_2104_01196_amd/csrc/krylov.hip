@@ -943,8 +943,9 @@ __global__ void k_copy_stop(int64_t n, const double *__restrict__ a, double *__r
 
 // ------------------------------------------------------------- host side
 
-// SEL > 0: sliced ELL with SEL lanes per row; SEL < 0: the diagonal copy
-// with -SEL rows per lane
+// SEL > 0: sliced ELL with SEL lanes per row; -9 <= SEL < 0: the diagonal
+// copy with -SEL rows per lane; SEL <= -10: the 3-row block copy (the fused
+// kernels form its rows one node per thread whatever -SEL - 10 says)
 #define GS2_SPMV_DISPATCH(K, kern, grid, ...)                                \
     do {                                                                     \
         switch (K) {                                                         \
@@ -1093,11 +1094,12 @@ static int build_layout(SellA &S, const gs2_csr &A, int sel, const std::vector<i
 // in place between solves are honoured.  Candidates: sliced ELL at the
 // lanes per row the mean row length suggests and at twice that, and, when
 // A qualifies, the diagonal copy at one and two rows per lane (8- and
-// 16-byte value loads).  fmt GS2_FORMAT_AUTO times them (one product each;
+// 16-byte value loads) or, failing that, the 3-row block copy at one and
+// two nodes per lane.  fmt GS2_FORMAT_AUTO times them (one product each;
 // a later candidate must win by 3 %) on matrices of at least
-// SPMV_TUNE_MIN_ROWS rows; GS2_FORMAT_SELL / _DIA force a layout (the
-// diagonal one at two rows per lane, falling back to sliced ELL when A does
-// not qualify).
+// SPMV_TUNE_MIN_ROWS rows; GS2_FORMAT_SELL / _DIA / _BLOCK3 force a layout
+// (the diagonal one at two rows per lane, the block one at two nodes per
+// lane, falling back to sliced ELL when A does not qualify).
 static int prepare_matrix(GmresWork *W, const gs2_csr &A, int fmt, hipStream_t s)
 {
     SellA &S = W->A;

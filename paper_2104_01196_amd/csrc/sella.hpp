@@ -110,7 +110,7 @@ int sella_build_dia(SellA &S, const gs2_csr &A, int R, const std::vector<int> &o
 // block copy (n divisible by 3, <= DIA_MAX offsets, the blocks storing <=
 // 1.5x the entries); *st reports HIP failures
 bool sella_b3_offsets(const gs2_csr &A, std::vector<int> &offs, hipStream_t s, int *st);
-// 3-row block copy for the product kernel with R rows per lane (zeroed;
+// 3-row block copy for the product kernel with R nodes per lane (zeroed;
 // fill with sella_fill_values)
 int sella_build_b3(SellA &S, const gs2_csr &A, int R, const std::vector<int> &offs, hipStream_t s);
 // copy A's values (and columns, for a new sliced-ELL structure) into S
