@@ -726,7 +726,7 @@ static int choose_format(Handle &h, const gs2_csr &A, const gs2_options &o, Setu
                        (o.format == GS2_FORMAT_AUTO || Rs.size() > 1 || ldss.size() > 1 || rms.size() > 1);
     if (!timed) {
         if (o.format == GS2_FORMAT_AUTO) return GS2_OK; // untimed automatic choice: sliced ELL
-        GS2_TRY(build(Rs.back()));                       // forced: the widest load allowed
+        GS2_TRY(build(*std::max_element(Rs.begin(), Rs.end()))); // forced: the widest load allowed
         h.fmt = FMT_DIA;
         h.lds = ldss.back();
         h.remap = rms.front();

@@ -229,6 +229,29 @@ def test_block3_apply_every_schedule(name, prec, R, xcd):
 
 
 @pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
+@pytest.mark.parametrize("fmt,name", [(g.FORMAT_BLOCK3, "elasticity_12x11x10"), (g.FORMAT_DIA, "vardiff3d_23")])
+def test_forced_layout_untimed_takes_widest_load(prec, fmt, name):
+    """A forced layout without timing (autotune off, rows per lane free)
+    takes the widest value load the precision allows (16 bytes: 2 float64,
+    4 float32 or 8 float16 values per lane), in either layout, and applies
+    as the oracle does at the layouts' usual bars."""
+    if fmt == g.FORMAT_BLOCK3:
+        A = B3MATS[name]()
+        dA = g.DeviceCSR.from_host(A)
+    else:
+        A, dA = mat(name)
+    v = np.random.default_rng(19).standard_normal(A.n)
+    z = torch.empty(A.n, dtype=torch.float64, device=DEV)
+    h = g.gs2_setup(dA, 1, 2, 0.9, g.SYMMETRIC, precision=prec, format=fmt, autotune=False)
+    sch = g.gs2_handle_schedule(h)
+    assert (sch["format"], sch["rows_per_lane"], sch["vector_bytes"], sch["tuned"]) == \
+        (fmt, max(R_OF[prec]), 16, 0), sch
+    g.gs2_apply(h, dev(v), z)
+    ref = reference(A, v, prec, g.SYMMETRIC, 1, 2, 0.9)
+    assert rel_inf(host(z), ref) <= (TOL[prec] or 2e-12)
+
+
+@pytest.mark.parametrize("prec", [g.FP64, g.FP32, g.FP16_SCALED])
 def test_block3_damping_compact_and_gmres(prec):
     """On the block layout: inner damping gamma (against the oracle's apply in
     the same form) and the compact form (against the oracle's float64
