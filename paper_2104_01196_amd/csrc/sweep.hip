@@ -461,12 +461,12 @@ __device__ __forceinline__ void dia_dots(const DiaView &T, int64_t pos, int w0, 
 // nb + 64 k against the source at the neighbour node's three unknowns
 // 3(node + o) .. 3(node + o) + 2.  Per offset a lane gathers those three
 // source entries once for its node's three rows and loads the block's nine
-// planes (R consecutive nodes' values per load; pos is the lane's first
-// value of plane 0).  Each row's sum runs over o, then the three columns of
-// the block, in order.  Node indices are clamped into [0, n/3) only in
-// workgroups whose nodes, shifted by o, leave that range (a uniform test per
-// offset; a clamped node meets stored zeros).  Nodes past n/3 read in-bounds
-// padding.
+// planes (the lane's R nodes' values of one plane sit side by side: one
+// R-value load per plane; pos is the lane's first value in a plane).  Each
+// row's sum runs over o, then the three columns of the block, in order.
+// Node indices are clamped into [0, n/3) only in workgroups whose nodes,
+// shifted by o, leave that range (a uniform test per offset; a clamped node
+// meets stored zeros).  Nodes past n/3 read in-bounds padding.
 template <typename VT, typename AT, int R, bool NT, typename Src>
 __device__ __forceinline__ void b3_node_dots(const DiaView &T, int64_t pos, int g0, int nb, int nn, Src src,
                                              AT (&acc)[R][3])
