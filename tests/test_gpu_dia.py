@@ -207,9 +207,10 @@ def b3_schedules():
 def test_block3_apply_every_schedule(name, prec, R, xcd):
     """The 3-row block layout of the triangles (3-dof elasticity: 81 scalar
     offsets, too many for the diagonal layout; 14 node offsets per triangle,
-    the diagonal block's strictly lower / upper entries included) at every
-    rows-per-lane and both workgroup walks, against the oracle at the same
-    bars as the diagonal layout."""
+    the diagonal block's strictly lower / upper entries included; nine
+    node-major planes per offset, a lane owning R nodes and their three rows)
+    at every nodes-per-lane R and both workgroup walks, against the oracle at
+    the same bars as the diagonal layout."""
     A = B3MATS[name]()
     dA = g.DeviceCSR.from_host(A)
     v = np.random.default_rng(17).standard_normal(A.n)

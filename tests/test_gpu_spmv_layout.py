@@ -1,7 +1,8 @@
 """GPU parity of the layouts of the GMRES solver's copy of A (the product
 w = A z of every Arnoldi step and the true residual): sliced ELL, the
 diagonal-interleaved copy (no column indices, two rows per lane) and the
-3-row block copy (3 unknowns per node, blocks along node offsets), forced
+3-row block copy (3 unknowns per node, blocks along node offsets, one or
+two nodes per lane), forced
 through the handle's spmv_format, and the timed automatic choice.  Each
 GS2-preconditioned GMRES solve is compared with the CPU oracle's solve of
 the same system: iteration count within one step (the two orthogonalise in
@@ -215,7 +216,7 @@ def test_block3_refused_where_it_does_not_apply():
 def test_block3_timed_choice_on_elasticity():
     """Automatic choice on an elasticity matrix large enough to be timed
     (98,304 rows): every candidate (sliced ELL at two lane counts, the block
-    copy at one and two rows per lane) builds and runs; the solve matches the
+    copy at one and two nodes per lane) builds and runs; the solve matches the
     oracle."""
     A = elasticity_q1(32, 32, 32, seed=5)
     dA = g.DeviceCSR.from_host(A)
