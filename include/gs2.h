@@ -345,8 +345,10 @@ int gs2_handle_query(const gs2_handle *h, int64_t *n, int64_t *nnz_l, int64_t *n
  * staging) at every rows_per_lane whose load is 2 to 16 bytes, with and
  * without LDS staging, with and without per-XCD ranges; each is timed on
  * one inner pass over L plus one residual pass over L and U (Section 4
- * passes), and a later candidate must be 3 % faster to replace an earlier
- * one (the block layout's widest load is timed first, the diagonal
+ * passes), each timing after a read of a 512 MB buffer (twice the
+ * last-level cache; the setup holds it while it times, and times back to
+ * back if it cannot allocate it), and a later candidate must be 3 % faster
+ * to replace an earlier one (the block layout's widest load is timed first, the diagonal
  * layout's narrowest).
  */
 int gs2_handle_schedule(const gs2_handle *h, int *format, int *lanes_per_row, int *rows_per_lane, int *vector_bytes,

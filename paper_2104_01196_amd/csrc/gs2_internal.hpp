@@ -179,6 +179,15 @@ struct Sell {
 // 238.8 ms normal, 252.1 / 239.1 / 236.4 ms non-temporal).
 constexpr double NT_TRIANGLES_BYTES = 150e6;
 
+// Bytes read before each timed pass of the setup's schedule timing: twice
+// the last-level cache (256 MB), so that every candidate is timed with the
+// triangles out of the caches, as a Krylov solve finds them (its basis
+// passes between two applies evict them).  Timed back to back instead, the
+// 192^3 problem's float32 triangles (170 MB) stayed in that cache and one
+// row per lane timed within the 3 % margin of two, while in the solve it
+// ran 17 % slower per inner pass (42.0 against 35.8 us).
+constexpr size_t FLUSH_BYTES = size_t(512) << 20;
+
 // Build the 16-bit column offsets of a sliced-ELL array (K lanes per row,
 // slice pointers sp, padded entries, columns col; lane l of slice s holds row
 // s * 64/K + l/K): *off = col - row - *off_min.  *off is left null when the
@@ -230,6 +239,7 @@ struct Handle {
     int stag_cycles = 0; // GMRES stagnation window in restart cycles (0 default, < 0 off)
     int spmv_fmt = 0;    // GMRES: layout request for the solver's copy of A (GS2_FORMAT_*)
     int basis_req = 0;   // GMRES: basis passes' loads in flight (0 timed, 1 wide, 2 narrow)
+    double *flush = nullptr; // setup only: FLUSH_BYTES read before each timed pass (null: none)
     int block_waves = 4; // wavefronts per workgroup in the sweep kernels
     Sell L, U;
     // diagonal-interleaved copies of L and U, used by the GS2 / JR passes

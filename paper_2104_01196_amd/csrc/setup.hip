@@ -650,6 +650,33 @@ static int64_t count_total(const int32_t *tot, int64_t n, hipStream_t s, int *st
     return c;
 }
 
+// The setup's flush buffer (FLUSH_BYTES of zeros, read before each timed
+// pass), held for the timing and released when the setup returns.  Without
+// memory for it the passes are timed back to back.
+struct FlushBuffer {
+    Handle &h;
+    FlushBuffer(Handle &hh, bool on, hipStream_t s) : h(hh)
+    {
+        h.flush = nullptr;
+        if (!on) return;
+        if (hipMalloc(&h.flush, FLUSH_BYTES) != hipSuccess) {
+            h.flush = nullptr;
+            (void)hipGetLastError();
+            return;
+        }
+        if (hipMemsetAsync(h.flush, 0, FLUSH_BYTES, s) != hipSuccess) {
+            (void)hipFree(h.flush);
+            h.flush = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    ~FlushBuffer()
+    {
+        if (h.flush) (void)hipFree(h.flush);
+        h.flush = nullptr;
+    }
+};
+
 // Schedules of the diagonal layout chosen by timing, per (size bucket, mean
 // row length, longest-row bucket, precision, diagonal counts).
 struct DiaChoice {
@@ -927,6 +954,8 @@ int setup_handle(Handle &h, const gs2_csr &A, const gs2_options &o, hipStream_t 
 
     int K = o.lanes_per_row;
     if (K != 0 && (K < 1 || K > 64 || (K & (K - 1)))) return GS2_ERR_ARG;
+    // the schedule timing below reads the flush buffer before each timed pass
+    FlushBuffer flush(h, o.autotune && alloc_vecs && n >= 4096, s);
     if (K == 0) {
         K = choose_lanes(avg, maxlen);
         if (o.autotune && alloc_vecs && n >= 4096) {

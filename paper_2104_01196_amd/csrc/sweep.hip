@@ -808,6 +808,16 @@ __global__ void k_ratios(const double *__restrict__ sums, int nq, double *__rest
     if (j < nq - 1) out[j] = sqrt(sums[j]) / sqrt(sums[nq - 1]);
 }
 
+// Reads p[0 .. m) (zeros) so that the caches hold none of the data a timed
+// pass is about to read; the sum is stored only if nonzero, which keeps the
+// loads.
+__global__ __launch_bounds__(KT) void k_flush(double *__restrict__ p, int64_t m)
+{
+    double t = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < m; i += (int64_t)gridDim.x * KT) t += p[i];
+    if (t != 0.0) p[0] = t;
+}
+
 // ------------------------------------------------------------ host drivers
 
 constexpr int TB = KT; // 4 wavefronts per workgroup, one or two slices each
@@ -1301,15 +1311,18 @@ struct Launch {
     // after a warm-up batch.
     static int time_inner(Handle &h, hipStream_t s, float *ms, bool with_resid)
     {
-        constexpr int BATCH = 5;
+        // with the flush buffer: one pair of passes per timing, each after a
+        // read of the buffer; without it, batches of five back to back
+        const int batch = h.flush ? 1 : 5, reps = h.flush ? 6 : 4;
         hipEvent_t e0, e1;
         GS2_TRY_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
         GS2_TRY_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
         k_fill_zero<AT><<<grid_rows(h.n), TB, 0, s>>>(h.stop, h.n, (AT *)h.ga);
         float best = 1e30f;
-        for (int rep = 0; rep < 4; ++rep) {
+        for (int rep = 0; rep < reps; ++rep) {
+            if (h.flush) k_flush<<<2048, TB, 0, s>>>(h.flush, (int64_t)(FLUSH_BYTES / sizeof(double)));
             GS2_TRY_HIP(hipEventRecord(e0, s));
-            for (int b = 0; b < BATCH; ++b) {
+            for (int b = 0; b < batch; ++b) {
                 inner(h, h.L, (const AT *)h.ga, (const AT *)h.ga, nullptr, 0, 0, DST_G, (AT *)h.gb, nullptr, nullptr,
                       s);
                 if (with_resid)
@@ -1320,7 +1333,7 @@ struct Launch {
             GS2_TRY_HIP(hipEventSynchronize(e1));
             float t = 0.f;
             GS2_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
-            if (rep > 0) best = std::min(best, t / BATCH);
+            if (rep > 0) best = std::min(best, t / batch);
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
