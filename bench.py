@@ -65,7 +65,8 @@ def parse():
                     help="force the sweep kernels' schedule per form instead of timing it at setup, e.g. "
                          "'fp64=1/0/0,fp32=4/0/0,fp16_scaled=8/0/1' (diagonal layout, rows per lane / LDS staging "
                          "0 or 1 / per-XCD row ranges 0 or 1; the solver's copy of A then uses the diagonal layout "
-                         "too): for counter runs, whose "
+                         "too; a 'b3:' prefix, e.g. 'fp64=b3:2/0/1', names the 3-row block layout, nodes per lane "
+                         "instead of rows): for counter runs, whose "
                          "serialised launches would time the candidates differently")
     ap.add_argument("--profile", choices=["on", "off"], default="on",
                     help="per-kernel HIP-event timing of the float64 solves (a second pass of the same solves)")
@@ -143,10 +144,13 @@ def forced_schedule(args, form, g):
     for item in args.schedule.split(","):
         name, val = item.split("=")
         if name == form:
+            fmt = g.FORMAT_DIA
+            if val.startswith("b3:"):  # the 3-row block layout (rows per lane then counts nodes)
+                fmt, val = g.FORMAT_BLOCK3, val[3:]
             rows, lds, *xcd = val.split("/")
-            return {"format": g.FORMAT_DIA, "rows_per_lane": int(rows), "lds_staging": g.LDS_ON if int(lds) else g.LDS_OFF,
+            return {"format": fmt, "rows_per_lane": int(rows), "lds_staging": g.LDS_ON if int(lds) else g.LDS_OFF,
                     "xcd_ranges": (g.XCD_RANGES if int(xcd[0]) else g.XCD_DISPATCH_ORDER) if xcd else g.XCD_AUTO,
-                    "spmv_format": g.FORMAT_DIA}
+                    "spmv_format": fmt}
     return {}
 
 
