@@ -295,6 +295,7 @@ def main():
                          "max_s": max(each), "iterations": info["iterations"], "restarts": info["restarts"],
                          "converged": info["converged"], "relres_true": rel, "setup_s": setup_s, "lanes_per_row": lanes,
                          "schedule": sched, "gmres_schedule": g.gs2_gmres_schedule(h),
+                         "basis_schedule": g.gs2_gmres_basis_schedule(h),
                          "rel_err_vs_oracle_fp64": (float(np.linalg.norm(xs - x_or) / np.linalg.norm(x_or))
                                                     if x_or is not None else None),
                          "rel_err_vs_oracle_fp64_sampled": oracle_sampled_error(orec, xs, np),
